@@ -1,0 +1,98 @@
+"""Exact matrix signs used to pin the oracle (test infrastructure only).
+
+* Symmetric tridiagonal Toeplitz matrices tridiag(c, d, c) are diagonalised by
+  the sine basis v_j(i) = sqrt(2/(n+1)) sin(i j theta), theta = pi/(n+1), with
+  eigenvalues d + 2c cos(j theta).  Any function f of such a matrix is
+      f(T)_ik = F(i-k) - F(i+k),   F(m) = 1/(n+1) sum_j f(lambda_j) cos(m j theta)
+  (1-based i, k), which is evaluated here with exact argument reduction of
+  m*j modulo 2(n+1) and compensated summation.
+* The Section 4.2 matrix A = [[0, B], [I, 0]] has sign(A) = [[0, B^(1/2)],
+  [B^(-1/2), 0]] (eq. 1.26); B = tridiag(1/16, 7/8, 1/16) is of the above kind.
+* Dense definitions (Section 1): sign(A) = V sign(Lambda) V^T for symmetric A,
+  and the Schur form sign(A) = Q sign(T) Q^* for general A, with the Schur
+  form ordered so that the left-half-plane eigenvalues come first; then
+  sign(T) = [[-I, Y], [0, I]] with T11 Y - Y T22 = -2 T12.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.linalg as sla
+
+
+def _toeplitz_function_table(n: int, lam: np.ndarray, f) -> np.ndarray:
+    """F(m) for m = 0 .. 2n+1, F(m) = 1/(n+1) sum_j f(lam_j) cos(pi m j/(n+1))."""
+    j = np.arange(1, n + 1, dtype=np.int64)
+    fv = np.asarray(f(lam), dtype=np.float64)
+    period = 2 * (n + 1)
+    F = np.empty(2 * n + 2)
+    for m in range(2 * n + 2):
+        r = (m * j) % period                         # exact argument reduction
+        terms = fv * np.cos(np.pi * r.astype(np.float64) / (n + 1))
+        F[m] = math.fsum(terms) / (n + 1)
+    return F
+
+
+def tridiag_toeplitz_function(n: int, d: float, c: float, f) -> np.ndarray:
+    """Dense f(T) for T = tridiag(c, d, c) of order n (symmetric)."""
+    theta = np.pi / (n + 1)
+    lam = d + 2.0 * c * np.cos(np.arange(1, n + 1) * theta)
+    F = _toeplitz_function_table(n, lam, f)
+    i = np.arange(1, n + 1)
+    diff = np.abs(i[:, None] - i[None, :])
+    summ = i[:, None] + i[None, :]
+    return F[diff] - F[summ]
+
+
+def sign_tridiag_c1(n: int) -> np.ndarray:
+    """sign(tridiag(-1, 0, -1)), the first benchmark matrix, in closed form."""
+    return tridiag_toeplitz_function(n, 0.0, -1.0, np.sign)
+
+
+def ode_sqrt_blocks(nB: int, lam: float = 1.0 / 16.0):
+    """(B^(1/2), B^(-1/2)) for B = tridiag(lam, 1-2lam, lam)."""
+    half = tridiag_toeplitz_function(nB, 1.0 - 2.0 * lam, lam, np.sqrt)
+    mhalf = tridiag_toeplitz_function(nB, 1.0 - 2.0 * lam, lam, lambda x: 1.0 / np.sqrt(x))
+    return half, mhalf
+
+
+def sign_ode_block(nB: int, lam: float = 1.0 / 16.0) -> np.ndarray:
+    """sign([[0, B], [I, 0]]) = [[0, B^(1/2)], [B^(-1/2), 0]] (eq. 1.26)."""
+    half, mhalf = ode_sqrt_blocks(nB, lam)
+    S = np.zeros((2 * nB, 2 * nB))
+    S[:nB, nB:] = half
+    S[nB:, :nB] = mhalf
+    return S
+
+
+def dense_sign_sym(M: np.ndarray) -> np.ndarray:
+    w, V = np.linalg.eigh(M)
+    if np.any(w == 0.0):
+        raise ValueError("zero eigenvalue: sign undefined")
+    return (V * np.sign(w)) @ V.T
+
+
+def dense_sign_schur(M: np.ndarray) -> np.ndarray:
+    """Schur method of Section 1 for a real or complex square matrix."""
+    T, Q, k = sla.schur(M.astype(np.complex128), output="complex", sort="lhp")
+    n = M.shape[0]
+    ev = np.diag(T)
+    if np.any(ev.real == 0.0):
+        raise ValueError("eigenvalue on the imaginary axis: sign undefined")
+    T11, T12, T22 = T[:k, :k], T[:k, k:], T[k:, k:]
+    sT = np.zeros((n, n), dtype=np.complex128)
+    sT[:k, :k] = -np.eye(k)
+    sT[k:, k:] = np.eye(n - k)
+    if 0 < k < n:
+        sT[:k, k:] = sla.solve_sylvester(T11, -T22, -2.0 * T12)
+    S = Q @ sT @ Q.conj().T
+    if np.isrealobj(M):
+        return S.real
+    return S
+
+
+def dense_sign(M: np.ndarray) -> np.ndarray:
+    if np.allclose(M, M.T, rtol=0, atol=0):
+        return dense_sign_sym(M)
+    return dense_sign_schur(M)

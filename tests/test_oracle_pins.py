@@ -1,0 +1,372 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each check ties a part of the oracle to a closed form, a library routine
+applied to the plain definition, an exact identity of the paper, or brute
+force, so that a plausible slip in the oracle (a dropped term, a sign, an
+index, a transposed operand, an off-by-one bucket) fails at least one test.
+"""
+import math
+import struct
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as W
+from oracle import closed_forms as cf
+
+
+def _rel(X, S):
+    return np.linalg.norm(X - S) / np.linalg.norm(S)
+
+
+def _dense(r):
+    return r.to_scipy().toarray()
+
+
+# ---------------------------------------------------------------------------
+# closed forms themselves, against library eigen/Schur routines
+# ---------------------------------------------------------------------------
+def test_sine_closed_form_matches_eigh():
+    n = 256
+    A = W.tridiag_c1(n).to_dense()
+    S = cf.sign_tridiag_c1(n)
+    assert _rel(S, cf.dense_sign_sym(A)) < 1e-13
+    # Frobenius norm of an orthogonal involution of order n is sqrt(n)
+    assert abs(np.linalg.norm(S) - math.sqrt(n)) < 1e-12
+
+
+def test_ode_closed_form_matches_schur():
+    nB = 48
+    A = W.ode_block_matrix(nB).to_dense()
+    S = cf.sign_ode_block(nB)
+    assert _rel(S, cf.dense_sign_schur(A)) < 1e-12
+    half, mhalf = cf.ode_sqrt_blocks(nB)
+    B = A[:nB, nB:]
+    assert np.abs(half @ half - B).max() < 1e-14
+    assert np.abs(half @ mhalf - np.eye(nB)).max() < 1e-14
+
+
+def test_schur_sign_matches_eigh_on_symmetric():
+    A = W.laplacian_2d(6, jitter=0.05, seed=3, m=8.0).to_dense()
+    assert _rel(cf.dense_sign_schur(A), cf.dense_sign_sym(A)) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# end-to-end NSF against exact signs
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [64, 1024])
+def test_nsf_c1_matches_sine_closed_form(oracle_lib, n):
+    A = W.tridiag_c1(n)
+    r = oracle_lib.nsf(A, tol=1e-12, stop_rule=1)
+    assert r.status == "OK"
+    X = _dense(r)
+    S = cf.sign_tridiag_c1(n)
+    assert np.linalg.norm(X - S) / math.sqrt(n) < 1e-12
+    # chiral structure: sign(tridiag(-1,0,-1)) has no entry with i+k even,
+    # and the iteration never creates one
+    rows = np.repeat(np.arange(n), np.diff(r.indptr))
+    assert np.all((rows + r.indices) % 2 == 1)
+    if n == 1024:
+        assert r.nnz == n * n // 2
+
+
+def test_nsf_ode_matrix_matches_eq_1_26(oracle_lib):
+    nB = 500
+    A = W.ode_block_matrix(nB)
+    r = oracle_lib.nsf(A, tol=1e-12)
+    assert r.status == "OK"
+    # ||A||_inf = 1 here, so the scaled start is the paper's X_1 = A
+    assert r.scale == 1.0
+    S = cf.sign_ode_block(nB)
+    assert _rel(_dense(r), S) < 1e-12
+
+
+def test_nsf_vs_ns_difference_matches_table_4_2_1(oracle_lib):
+    """AE = ||X_NS - X_NSF|| stays at the order the paper prints (Table 4.2.1)."""
+    rows = [l.split() for l in open(__file__.replace("test_oracle_pins.py",
+                                                     "golden/table_4_2_1.txt"))
+            if l.strip() and not l.startswith("#")]
+    paper = {int(r[0]): float(r[2]) for r in rows}
+    nB = 500
+    A = W.ode_block_matrix(nB)
+    f = oracle_lib.nsf(A, tol=1e-12)
+    u = oracle_lib.nsf(A, tol=1e-12, c_fixed=0.0, switch_res=0.0)   # tau = 0: plain NS
+    assert u.trace["ffro"][: u.iters].max() == 0.0
+    ae = np.linalg.norm(_dense(f) - _dense(u))
+    assert ae <= 10 * paper[nB], (ae, paper[nB])
+
+
+@pytest.mark.parametrize("make", [
+    lambda: W.laplacian_1d(160, sigma=2.0, jitter=0.05, seed=1, m=4.0),
+    lambda: W.laplacian_2d(12, jitter=0.05, seed=2, m=8.0),
+    lambda: W.convdiff_2d(12, beta=0.5, sigma=4.0, m=8.0),
+    lambda: W.convdiff_2d(10, beta=0.5, sigma=4.0, m=8.0, scale_by_h=False),
+    lambda: W.laplacian_3d(5, perturb=0.5, seed=4, m=12.0),
+], ids=["lap1d", "lap2d", "convdiff", "convdiff_unscaled_beta", "lap3d"])
+def test_nsf_matches_dense_definition(oracle_lib, make):
+    A = make()
+    r = oracle_lib.nsf(A, tol=1e-12)
+    assert r.status == "OK"
+    S = cf.dense_sign(A.to_dense())
+    assert _rel(_dense(r), S) < 1e-11
+    # trace(S) = n+ - n- equals the staggering sum for the gapped families
+    assert round(np.trace(S)) == A.meta["inertia"]
+    assert abs(_dense(r).trace() - A.meta["inertia"]) < 1e-9
+
+
+def test_nsf_invariants_at_moderate_size(oracle_lib):
+    A = W.laplacian_2d(40, jitter=0.05, seed=2, m=8.0)
+    r = oracle_lib.nsf(A, tol=1e-12)
+    assert r.status == "OK"
+    S = r.to_scipy()
+    As = A.to_scipy()
+    n = A.n
+    I = sp.identity(n, format="csr")
+    assert sp.linalg.norm(S @ S - I) < 1e-10
+    comm = sp.linalg.norm(S @ As - As @ S) / (sp.linalg.norm(S) * sp.linalg.norm(As))
+    assert comm < 1e-13
+    assert sp.linalg.norm(S - S.T) < 1e-12
+    assert abs(S.diagonal().sum() - A.meta["inertia"]) < 1e-8
+    assert abs(sp.linalg.norm(S) - math.sqrt(n)) < 1e-8
+
+
+# ---------------------------------------------------------------------------
+# Lemma 2.1.1 (eq. 1.3): one unfiltered NS step maps R to 3/4 R^2 + 1/4 R^3
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("sym", [True, False])
+def test_ns_step_residual_recurrence(oracle_lib, sym):
+    if sym:
+        A = W.laplacian_2d(9, jitter=0.05, seed=7, m=8.0)
+    else:
+        A = W.convdiff_2d(9, beta=0.5, sigma=4.0, m=8.0, scale_by_h=False)
+    X0 = A.to_scipy() / oracle_lib.norm_inf(A)
+    X0 = sp.csr_matrix(X0)
+    Xc = W.Csr(n=A.n, indptr=X0.indptr.astype(np.int64), indices=X0.indices.astype(np.int32),
+               data=X0.data)
+    rp, ci, v = oracle_lib.ns_step(Xc)
+    X1 = sp.csr_matrix((v, ci, rp), shape=(A.n, A.n)).toarray()
+    D0 = X0.toarray()
+    I = np.eye(A.n)
+    R0 = I - D0 @ D0
+    R1 = I - X1 @ X1
+    pred = 0.75 * R0 @ R0 + 0.25 * R0 @ R0 @ R0
+    assert np.linalg.norm(R1 - pred) <= 1e-14 * max(1.0, np.linalg.norm(R0))
+    # the step itself against the dense formula 1/2 X (3I - X^2)
+    assert np.abs(X1 - 0.5 * D0 @ (3 * I - D0 @ D0)).max() < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# products
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", [0, 1])
+def test_spgemm_matches_dense_product(oracle_lib, seed):
+    A = W.random_sparse(300, mean_row=6, seed=seed)
+    B = W.random_sparse(300, mean_row=9, seed=seed + 10)
+    rp, ci, v = oracle_lib.spgemm(A, B)
+    C = sp.csr_matrix((v, ci, rp), shape=(300, 300))
+    ref = A.to_dense() @ B.to_dense()
+    assert np.abs(C.toarray() - ref).max() <= 1e-14 * max(1.0, np.abs(ref).max())
+    # sorted, unique columns; no stored zeros
+    for i in range(300):
+        row = ci[rp[i]:rp[i + 1]]
+        assert np.all(np.diff(row) > 0)
+    assert np.all(v != 0.0)
+    # pattern = nonzeros of the exact product (values are random, no cancellation)
+    assert C.nnz == np.count_nonzero(ref)
+
+
+def test_spgemm_non_commuting_operands(oracle_lib):
+    """A*B and B*A differ for these operands; catches a swapped operand order."""
+    A = W.convdiff_2d(6, beta=0.5, sigma=4.0, m=1.0, scale_by_h=False)
+    B = W.random_sparse(36, mean_row=5, seed=3)
+    rp, ci, v = oracle_lib.spgemm(A, B)
+    C = sp.csr_matrix((v, ci, rp), shape=(36, 36)).toarray()
+    assert np.abs(C - A.to_dense() @ B.to_dense()).max() < 1e-14
+    assert np.abs(C - B.to_dense() @ A.to_dense()).max() > 1e-3
+
+
+# ---------------------------------------------------------------------------
+# element threshold from a norm budget
+# ---------------------------------------------------------------------------
+def _bucket_bits(x: float) -> int:
+    """Bucket from the IEEE-754 bit pattern (independent of frexp)."""
+    bits = struct.unpack("<Q", struct.pack("<d", abs(x)))[0]
+    if abs(x) >= 1.0:
+        return 2033
+    ebits = (bits >> 52) & 0x7FF
+    E = ebits - 1023
+    if x == 0.0 or ebits == 0 or E < -127:
+        return 0
+    j = (bits >> 48) & 0xF
+    return 1 + 16 * (E + 127) + j
+
+
+def test_bucket_matches_bit_pattern(oracle_lib):
+    rng = np.random.default_rng(0)
+    xs = np.concatenate([
+        rng.uniform(-1, 1, 2000),
+        np.exp(rng.uniform(-300, 0, 4000)) * rng.choice([-1, 1], 4000),
+        [0.0, 1.0, -1.0, 2.0, 0.5, 2.0 ** -127, 2.0 ** -128, 2.0 ** -127 * 1.99, 1 - 2 ** -53,
+         5e-324, 1e-310],
+    ])
+    for x in xs:
+        assert oracle_lib.bucket(float(x)) == _bucket_bits(float(x)), x
+
+
+def test_bucket_edges(oracle_lib):
+    for b in range(1, 2033):
+        lo, hi = oracle_lib.bucket_lo(b), oracle_lib.bucket_hi(b)
+        assert lo < hi
+        assert oracle_lib.bucket(lo) == b
+        assert oracle_lib.bucket(np.nextafter(hi, 0)) == b
+        assert oracle_lib.bucket(hi) == b + 1 if b + 1 < 2033 else True
+        assert hi / lo <= 17.0 / 16.0 + 1e-15
+    assert oracle_lib.bucket(2.0 ** -127) == 1
+    assert oracle_lib.bucket(np.nextafter(2.0 ** -127, 0)) == 0
+    # scaling by 2 moves a value by exactly 16 buckets
+    for x in [3e-5, 0.3, 1.7e-20]:
+        assert oracle_lib.bucket(2 * x) == oracle_lib.bucket(x) + 16
+
+
+def _brute_cut(vals, tau):
+    counts = np.zeros(2048, np.int64)
+    for x in vals:
+        counts[_bucket_bits(x)] += 1
+    hi = [2.0 ** -127] + [(1 + ((b - 1) % 16 + 1) / 16) * 2.0 ** ((b - 1) // 16 - 127)
+                          for b in range(1, 2033)]
+    best = 0
+    for c in range(0, 2034):
+        bound = sum(counts[b] * hi[b] ** 2 for b in range(c) if counts[b])
+        if bound <= tau * tau:
+            best = c
+    return best
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_select_matches_brute_force(oracle_lib, seed):
+    rng = np.random.default_rng(seed)
+    m = int(rng.integers(1, 60))
+    vals = np.exp(rng.uniform(-60, 1, m)) * rng.choice([-1, 1], m)
+    vals[vals > 1] = 0.9
+    tau = float(np.exp(rng.uniform(-60, 0)))
+    b, keep, dsq = oracle_lib.filter_values(vals, tau)
+    assert b == _brute_cut(vals, tau)
+    # rigorous budget: the dropped entries have Frobenius norm <= tau
+    assert math.sqrt(dsq) <= tau
+    assert dsq == pytest.approx(float(np.sum(vals[~keep] ** 2)), rel=1e-15, abs=0)
+    # ties go to keep: an entry exactly at the lower edge of the cut bucket stays
+    if 0 < b < 2033:
+        lo = oracle_lib.bucket_lo(b)
+        b2, keep2, _ = oracle_lib.filter_values(np.append(vals, lo), tau)
+        if b2 == b:
+            assert keep2[-1]
+
+
+def test_select_zero_budget_drops_nothing(oracle_lib):
+    vals = np.array([1e-300, 1e-30, 0.5, 2.0 ** -130])
+    b, keep, dsq = oracle_lib.filter_values(vals, 0.0)
+    assert keep.all() and dsq == 0.0
+
+
+def test_select_never_drops_entries_at_or_above_one(oracle_lib):
+    vals = np.array([1.0, 3.0, 1e-3])
+    b, keep, _ = oracle_lib.filter_values(vals, 1e6)
+    assert b == 2033
+    assert keep.tolist() == [True, True, False]
+
+
+# ---------------------------------------------------------------------------
+# filtering theory: Theorem 3.2.1 and the budget bookkeeping
+# ---------------------------------------------------------------------------
+def test_filter_budget_respected_every_step(oracle_lib):
+    A = W.laplacian_2d(30, jitter=0.05, seed=2, m=8.0)
+    r = oracle_lib.nsf(A, tol=1e-12)
+    k = r.iters
+    assert np.all(r.trace["ffro"][:k] <= r.trace["tau"][:k])
+    # before the switch the budget is the fixed c4*tol, after it eq. 1.18
+    e = r.trace["e"][:k]
+    assert np.all(r.trace["tau"][:k][e >= 1e-6] == 1e-4 * 1e-12)
+    after = e < 1e-6
+    assert np.any(after)
+    assert np.all(r.trace["tau"][:k][after] < 1e-16)
+
+
+def test_theorem_3_2_1_nsf_vs_ns(oracle_lib):
+    """Once the residual is small, ||R^_k - R_k|| <= 3 ||R_k|| (eq. 1.18 budget)."""
+    A = W.laplacian_2d(20, jitter=0.05, seed=2, m=8.0)
+    f = oracle_lib.nsf(A, tol=1e-12)
+    u = oracle_lib.nsf(A, tol=1e-12, c_fixed=0.0, switch_res=0.0)
+    k = min(f.iters, u.iters)
+    # residual norms of both runs agree to within the filter budget scale
+    for i in range(k + 1):
+        dR = abs(f.trace["e"][i] - u.trace["e"][i])
+        if u.trace["e"][i] < 1e-2:
+            assert dR <= 3 * u.trace["e"][i] + 1e-13
+    Xf, Xu = _dense(f), _dense(u)
+    assert np.linalg.norm(Xf - Xu) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# status handling
+# ---------------------------------------------------------------------------
+def test_guard_max_iter_returns_last_iterate(oracle_lib):
+    A = W.laplacian_2d(8, jitter=0.05, seed=2, m=8.0)
+    r = oracle_lib.nsf(A, tol=1e-12, max_iter=1)
+    assert r.status == "ENOCONV"
+    assert r.iters == 1 and r.nnz > 0
+
+
+def test_guard_divergence(oracle_lib):
+    A = W.laplacian_2d(8, jitter=0.05, seed=2, m=8.0)
+    r = oracle_lib.nsf(A, tol=1e-12, scale=1.0)     # unscaled: ||I - A^2|| >> 1
+    assert r.status == "EDIVERGED"
+
+
+def test_invalid_input(oracle_lib):
+    A = W.tridiag_c1(8)
+    bad = W.Csr(n=8, indptr=A.indptr.copy(), indices=A.indices.copy(), data=A.data.copy())
+    bad.indices[0], bad.indices[1] = bad.indices[1], bad.indices[0]
+    bad.indices[2] = bad.indices[3]
+    assert oracle_lib.nsf(bad).status == "EINVAL"
+    assert oracle_lib.nsf(A, tol=0.0).status == "EINVAL"
+
+
+# ---------------------------------------------------------------------------
+# filtered Newton (Algorithm 3.1.1)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("make,exact", [
+    (lambda: W.laplacian_2d(10, jitter=0.05, seed=2, m=8.0), None),
+    (lambda: W.convdiff_2d(10, beta=0.5, sigma=4.0, m=8.0), None),
+    (lambda: W.ode_block_matrix(100), lambda: cf.sign_ode_block(100)),
+], ids=["lap2d", "convdiff", "ode"])
+def test_nmf_matches_exact_sign(oracle_lib, make, exact):
+    A = make()
+    r = oracle_lib.nmf(A, tol=1e-12)
+    assert r.status == "OK"
+    S = exact() if exact else cf.dense_sign(A.to_dense())
+    assert _rel(_dense(r), S) < 1e-11
+    assert r.trace["inner_total"] > 0
+
+
+def test_nmf_agrees_with_nsf(oracle_lib):
+    A = W.laplacian_2d(24, jitter=0.05, seed=2, m=8.0)
+    a = oracle_lib.nsf(A, tol=1e-12)
+    b = oracle_lib.nmf(A, tol=1e-12)
+    assert _rel(_dense(b), _dense(a)) < 1e-11
+
+
+@pytest.mark.parametrize("make", [
+    lambda: W.tridiag_c1(128),
+    lambda: W.convdiff_2d(9, beta=0.5, sigma=4.0, m=8.0, scale_by_h=False),
+], ids=["c1", "convdiff"])
+def test_nsf_loop_obeys_eq_1_8(oracle_lib, make):
+    """Unfiltered steps of the NSF loop obey ||R_{k+1}|| <= 3/4||R_k||^2 + 1/4||R_k||^3
+    (eq. 1.8; the Frobenius norm is submultiplicative), which pins the update
+    coefficients of the loop itself (a wrong 1/2 still converges, but linearly)."""
+    A = make()
+    r = oracle_lib.nsf(A, tol=1e-13, c_fixed=0.0, switch_res=0.0)
+    e = r.trace["e"][: r.iters + 1]
+    n = A.n
+    for k in range(len(e) - 1):
+        assert e[k + 1] <= 0.75 * e[k] ** 2 + 0.25 * e[k] ** 3 + 1e-14 * math.sqrt(n) * 10, (k, e)
