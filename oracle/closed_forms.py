@@ -96,3 +96,35 @@ def dense_sign(M: np.ndarray) -> np.ndarray:
     if np.allclose(M, M.T, rtol=0, atol=0):
         return dense_sign_sym(M)
     return dense_sign_schur(M)
+
+
+def ball(A, i: int, radius: int) -> np.ndarray:
+    """Sorted indices within graph distance `radius` of i in the pattern of A (CSR)."""
+    seen = {i}
+    frontier = [i]
+    for _ in range(radius):
+        nxt = []
+        for r in frontier:
+            for c in A.indices[A.indptr[r]:A.indptr[r + 1]]:
+                c = int(c)
+                if c not in seen:
+                    seen.add(c)
+                    nxt.append(c)
+        frontier = nxt
+    return np.array(sorted(seen), dtype=np.int64)
+
+
+def local_sign_row(A, i: int, radius: int):
+    """Row i of sign(A_B), A_B the principal submatrix of A on the ball B of
+    the given radius around i (dense definition on the patch).
+
+    For a matrix whose sign is exponentially localised (a spectral gap), the
+    entries of this row differ from those of sign(A) by a quantity that decays
+    like q^radius, q < 1 the decay rate of sign(A); it is how single rows of a
+    sign too large for a dense method are checked.  Returns (columns, values).
+    """
+    idx = ball(A, i, radius)
+    sub = A.to_scipy()[idx][:, idx].toarray()
+    S = dense_sign(sub)
+    loc = int(np.searchsorted(idx, i))
+    return idx, S[loc]

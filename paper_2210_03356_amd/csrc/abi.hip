@@ -1,0 +1,342 @@
+// C ABI of libsignfn (declared in include/signfn.h).
+#include <cmath>
+#include <cstring>
+
+#include "driver.hpp"
+
+using namespace sfn;
+
+namespace {
+
+thread_local std::string t_err;
+
+template <typename F>
+int guarded(F &&f) {
+    try {
+        t_err.clear();
+        return f();
+    } catch (const Error &e) {
+        t_err = e.what();
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        t_err = "host allocation failed";
+        return SIGN_ENOMEM;
+    } catch (const std::exception &e) {
+        t_err = e.what();
+        return SIGN_EDEVICE;
+    }
+}
+
+void check_opts(const sign_opts *o) {
+    if (!o) throw Error(SIGN_EINVAL, "options are NULL");
+    if (!(o->tol > 0.0) || !std::isfinite(o->tol)) throw Error(SIGN_EINVAL, "tol must be > 0");
+    if (o->stop_rule != 0 && o->stop_rule != 1) throw Error(SIGN_EINVAL, "stop_rule must be 0 or 1");
+    if (!(o->c_fixed >= 0.0) || !(o->switch_res >= 0.0))
+        throw Error(SIGN_EINVAL, "c_fixed and switch_res must be >= 0");
+    if (o->max_iter < 0) throw Error(SIGN_EINVAL, "max_iter must be >= 0");
+    if (o->precision != 0 && o->precision != 1) throw Error(SIGN_EINVAL, "precision must be 0 or 1");
+    if (o->polish_steps < 0 || o->refine_steps < 0)
+        throw Error(SIGN_EINVAL, "polish_steps and refine_steps must be >= 0");
+    if (!(o->scale >= 0.0) || !std::isfinite(o->scale)) throw Error(SIGN_EINVAL, "scale must be >= 0");
+    if ((o->alloc == nullptr) != (o->free == nullptr))
+        throw Error(SIGN_EINVAL, "alloc and free hooks must be set together");
+}
+
+void check_csr_header(const sign_csr *A) {
+    if (!A) throw Error(SIGN_EINVAL, "matrix is NULL");
+    if (A->n <= 0) throw Error(SIGN_EINVAL, "n must be > 0");
+    if (A->n >= (int64_t)INT32_MAX) throw Error(SIGN_EINVAL, "n must be < 2^31");
+    if (A->nnz < 0) throw Error(SIGN_EINVAL, "nnz must be >= 0");
+    if (!A->row_ptr || (A->nnz > 0 && (!A->col || !A->val)))
+        throw Error(SIGN_EINVAL, "NULL array in matrix");
+    if (A->val_f32 != 0 && A->val_f32 != 1) throw Error(SIGN_EINVAL, "val_f32 must be 0 or 1");
+}
+
+// Validate a device CSR (row pointers, column range/order, finite values).
+void validate(Workspace &w, const sign_csr *A) {
+    check_csr_header(A);
+    w.flag.ensure(sizeof(int));
+    SFN_HIP(hipMemsetAsync(w.flag.get(), 0, sizeof(int), w.s));
+    launch_validate(A->row_ptr, A->col, A->val, A->val_f32, A->n, A->nnz, w.flag.as<int>(), w.s);
+    const int f = read_scalar(w.flag.as<int>(), w.s);
+    if (f) {
+        std::string m = "malformed CSR:";
+        if (f & 1) m += " row_ptr";
+        if (f & 2) m += " column out of range";
+        if (f & 4) m += " columns not strictly ascending";
+        if (f & 8) m += " non-finite value";
+        throw Error(SIGN_EINVAL, m);
+    }
+}
+
+// ||A||_inf in FP64 (row sums of |a_ij|, then a max).
+double norm_inf(Workspace &w, const sign_csr *A) {
+    w.rs1.ensure(sizeof(double) * A->n);
+    launch_row_abs_sum(A->row_ptr, A->val, A->val_f32, A->n, w.rs1.as<double>(), w.s);
+    return w.max_rows(w.rs1, A->n);
+}
+
+// X = A * scale as a device matrix of value type V.
+template <typename V>
+void load_scaled(Workspace &w, const sign_csr *A, double scale, DMat<V> &X) {
+    X.ensure_rows(A->n);
+    X.ensure_entries(A->nnz);
+    SFN_HIP(hipMemcpyAsync(X.beg.get(), A->row_ptr, sizeof(int64_t) * (A->n + 1),
+                           hipMemcpyDeviceToDevice, w.s));
+    launch_row_len(A->row_ptr, A->n, X.lenp(), w.s);
+    if (A->nnz > 0) {
+        SFN_HIP(hipMemcpyAsync(X.col.get(), A->col, sizeof(int32_t) * A->nnz,
+                               hipMemcpyDeviceToDevice, w.s));
+        if (A->val_f32)
+            launch_scale_copy<float, V>((const float *)A->val, X.valp(), A->nnz, scale, w.s);
+        else
+            launch_scale_copy<double, V>((const double *)A->val, X.valp(), A->nnz, scale,
+                                         w.s);
+    }
+    X.nnz = A->nnz;
+}
+
+template <typename Vi, typename Vo>
+void convert(Workspace &w, const DMat<Vi> &In, DMat<Vo> &Out) {
+    Out.ensure_rows(In.n);
+    Out.ensure_entries(In.nnz);
+    SFN_HIP(hipMemcpyAsync(Out.beg.get(), In.beg.get(), sizeof(int64_t) * (In.n + 1),
+                           hipMemcpyDeviceToDevice, w.s));
+    SFN_HIP(hipMemcpyAsync(Out.len.get(), In.len.get(), sizeof(int32_t) * In.n,
+                           hipMemcpyDeviceToDevice, w.s));
+    if (In.nnz > 0) {
+        SFN_HIP(hipMemcpyAsync(Out.col.get(), In.col.get(), sizeof(int32_t) * In.nnz,
+                               hipMemcpyDeviceToDevice, w.s));
+        launch_scale_copy<Vi, Vo>(In.valp(), Out.valp(), In.nnz, 1.0,
+                                  w.s);
+    }
+    Out.nnz = In.nnz;
+}
+
+Allocator make_alloc(const sign_opts *o, hipStream_t s) {
+    Allocator a;
+    if (o && o->alloc) {
+        a.alloc = o->alloc;
+        a.release = o->free;
+        a.ctx = o->alloc_ctx;
+    }
+    a.stream = s;
+    return a;
+}
+
+// Hand a compact device matrix to a new result object.
+template <typename V>
+sign_result *make_result(const Allocator &al, DMat<V> &X) {
+    auto *r = new sign_result();
+    r->al = al;
+    r->n = X.n;
+    r->nnz = X.nnz;
+    r->val_f32 = sizeof(V) == 4;
+    r->rp = std::move(X.beg);
+    r->col = std::move(X.col);
+    r->val = std::move(X.val);
+    r->rp.bind(&r->al);
+    r->col.bind(&r->al);
+    r->val.bind(&r->al);
+    return r;
+}
+
+int finish(sign_result *r, sign_result **out, int status) {
+    *out = r;
+    return status;
+}
+
+}  // namespace
+
+extern "C" {
+
+void sign_opts_default(sign_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->tol = 1e-12;
+    o->stop_rule = 0;
+    o->c_fixed = 1e-4;
+    o->switch_res = 1e-6;
+    o->max_iter = 100;
+    o->precision = 0;
+    o->polish_steps = 2;
+    o->refine_steps = 6;
+    o->filter_y = 0;
+    o->scale = 0.0;
+    o->staging_bytes = 0;
+}
+
+const char *sign_last_error(void) { return t_err.c_str(); }
+
+int sign_ns(const sign_csr *A, const sign_opts *o, void *hip_stream, sign_result **out) {
+    if (out) *out = nullptr;
+    return guarded([&]() -> int {
+        if (!out) throw Error(SIGN_EINVAL, "out is NULL");
+        check_opts(o);
+        const double t_start = now_s();
+        hipStream_t s = (hipStream_t)hip_stream;
+        Allocator al = make_alloc(o, s);
+        Workspace w(&al, o->staging_bytes);
+        validate(w, A);
+        const int64_t n = A->n;
+        const double c = o->scale > 0.0 ? o->scale : norm_inf(w, A);
+        if (!(c > 0.0) || !std::isfinite(c)) throw Error(SIGN_EINVAL, "scale is zero (A = 0?)");
+        std::vector<sign_iter_stats> trace;
+        LoopParams p{o->tol, o->c_fixed, o->switch_res, o->stop_rule, o->max_iter, o->filter_y, 0};
+        LoopOut lo;
+        DMat<double> X;
+        X.bind(&al);
+        if (o->precision == 0) {
+            load_scaled<double>(w, A, 1.0 / c, X);
+            lo = nsf_loop<double>(w, X, p, trace);
+        } else {
+            // FP32 phase to its rounding floor, then FP64 polishing steps
+            DMat<float> X32;
+            X32.bind(&al);
+            load_scaled<float>(w, A, 1.0 / c, X32);
+            LoopParams p32 = p;
+            p32.fp32 = 1;
+            p32.tol = std::max(o->tol, 32.0 * 5.960464477539063e-08 * std::sqrt((double)n));
+            p32.stop_rule = 0;
+            const LoopOut l32 = nsf_loop<float>(w, X32, p32, trace);
+            convert<float, double>(w, X32, X);
+            X32 = DMat<float>();
+            LoopParams p64 = p;
+            p64.max_iter = o->polish_steps;
+            lo = nsf_loop<double>(w, X, p64, trace);
+            lo.iters += l32.iters;
+            if (l32.status == SIGN_EDIVERGED) lo.status = SIGN_EDIVERGED;
+        }
+        SFN_HIP(hipStreamSynchronize(s));
+        sign_result *r = make_result<double>(al, X);
+        r->trace = std::move(trace);
+        sign_stats &st = r->stats;
+        st.status = lo.status;
+        st.iters = lo.iters;
+        st.stagnated = lo.stagnated;
+        st.scale = c;
+        st.res_fro = lo.e;
+        st.step_fro = lo.d;
+        st.nnz = r->nnz;
+        st.products = w.products;
+        st.spgemm_ms = w.spgemm_ms;
+        st.spgemm_bytes = w.spgemm_bytes;
+        st.seconds = now_s() - t_start;
+        return finish(r, out, lo.status);
+    });
+}
+
+int sign_newton(const sign_csr *A, const sign_opts *o, void *hip_stream, sign_result **out) {
+    if (out) *out = nullptr;
+    return guarded([&]() -> int {
+        (void)A; (void)o; (void)hip_stream;
+        throw Error(SIGN_EINVAL, "sign_newton: not available in this build");
+        return SIGN_EINVAL;
+    });
+}
+
+int sign_spgemm(const sign_csr *A, const sign_csr *B, void *hip_stream, sign_result **out) {
+    if (out) *out = nullptr;
+    return guarded([&]() -> int {
+        if (!out) throw Error(SIGN_EINVAL, "out is NULL");
+        hipStream_t s = (hipStream_t)hip_stream;
+        Allocator al = make_alloc(nullptr, s);
+        Workspace w(&al, 0);
+        validate(w, A);
+        validate(w, B);
+        if (A->n != B->n) throw Error(SIGN_EINVAL, "A and B differ in order");
+        if (A->val_f32 != B->val_f32) throw Error(SIGN_EINVAL, "A and B differ in value type");
+        const double t0 = now_s();
+        sign_result *r;
+        if (A->val_f32) {
+            DMat<float> a, b, c;
+            a.bind(&al); b.bind(&al); c.bind(&al);
+            load_scaled<float>(w, A, 1.0, a);
+            load_scaled<float>(w, B, 1.0, b);
+            product<float>(w, a, b, nullptr, 1.0, 0.0, 0.0, c, nullptr, nullptr);
+            SFN_HIP(hipStreamSynchronize(s));
+            r = make_result<float>(al, c);
+        } else {
+            DMat<double> a, b, c;
+            a.bind(&al); b.bind(&al); c.bind(&al);
+            load_scaled<double>(w, A, 1.0, a);
+            load_scaled<double>(w, B, 1.0, b);
+            product<double>(w, a, b, nullptr, 1.0, 0.0, 0.0, c, nullptr, nullptr);
+            SFN_HIP(hipStreamSynchronize(s));
+            r = make_result<double>(al, c);
+        }
+        r->stats.nnz = r->nnz;
+        r->stats.products = w.products;
+        r->stats.spgemm_ms = w.spgemm_ms;
+        r->stats.spgemm_bytes = w.spgemm_bytes;
+        r->stats.seconds = now_s() - t0;
+        return finish(r, out, SIGN_OK);
+    });
+}
+
+int sign_filter(const sign_csr *A, double tau, void *hip_stream, sign_result **out, int *bstar) {
+    if (out) *out = nullptr;
+    return guarded([&]() -> int {
+        if (!out) throw Error(SIGN_EINVAL, "out is NULL");
+        if (!(tau >= 0.0) || !std::isfinite(tau)) throw Error(SIGN_EINVAL, "tau must be >= 0");
+        hipStream_t s = (hipStream_t)hip_stream;
+        Allocator al = make_alloc(nullptr, s);
+        Workspace w(&al, 0);
+        validate(w, A);
+        DMat<double> o;
+        o.bind(&al);
+        int b;
+        if (A->val_f32) {
+            DMat<float> a;
+            a.bind(&al);
+            load_scaled<float>(w, A, 1.0, a);
+            b = filter<float, double>(w, a, tau, o, nullptr, &w.rs4);
+        } else {
+            DMat<double> a;
+            a.bind(&al);
+            load_scaled<double>(w, A, 1.0, a);
+            b = filter<double, double>(w, a, tau, o, nullptr, &w.rs4);
+        }
+        const double dropped = std::sqrt(w.sum_rows(w.rs4, A->n));
+        SFN_HIP(hipStreamSynchronize(s));
+        if (bstar) *bstar = b;
+        sign_result *r = make_result<double>(al, o);
+        r->stats.nnz = r->nnz;
+        r->stats.step_fro = dropped;  // ||F||_F of the dropped part
+        return finish(r, out, SIGN_OK);
+    });
+}
+
+int sign_result_csr(const sign_result *r, sign_csr *view) {
+    return guarded([&]() -> int {
+        if (!r || !view) throw Error(SIGN_EINVAL, "NULL argument");
+        view->n = r->n;
+        view->nnz = r->nnz;
+        view->row_ptr = r->rp.as<int64_t>();
+        view->col = r->col.as<int32_t>();
+        view->val = r->val.get();
+        view->val_f32 = r->val_f32;
+        return SIGN_OK;
+    });
+}
+
+int sign_result_stats(const sign_result *r, sign_stats *s) {
+    return guarded([&]() -> int {
+        if (!r || !s) throw Error(SIGN_EINVAL, "NULL argument");
+        *s = r->stats;
+        return SIGN_OK;
+    });
+}
+
+int sign_result_trace(const sign_result *r, int k, sign_iter_stats *it) {
+    return guarded([&]() -> int {
+        if (!r || !it) throw Error(SIGN_EINVAL, "NULL argument");
+        if (k < 0 || k >= (int)r->trace.size()) throw Error(SIGN_EINVAL, "trace index out of range");
+        *it = r->trace[k];
+        return SIGN_OK;
+    });
+}
+
+void sign_result_free(sign_result *r) { delete r; }
+
+}  // extern "C"

@@ -1,0 +1,307 @@
+// Host drivers: sparse product with batching, filtering, Algorithm 3.2.1 loop.
+#include "driver.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <limits>
+
+namespace sfn {
+
+// Row classes of the numeric product (kernel tiles in kernels.hip).
+constexpr int kSmallTile = 512;
+constexpr int kMidTile = 4096;
+
+Workspace::Workspace(Allocator *a, size_t staging_bytes) : al(a), s(a->stream) {
+    for (DevBuf *b : {&lo, &span, &cap, &work, &capoff, &workoff, &tmp, &bins, &counts, &cursor,
+                      &stage_col, &stage_val, &rs1, &rs2, &rs3, &rs4, &icnt, &hist, &tau,
+                      &bstar, &seg, &red, &flag, &zero_b})
+        b->bind(a);
+    if (staging_bytes == 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+            (void)hipGetLastError();
+            fr = size_t(8) << 30;
+        }
+        staging_bytes = std::max<size_t>(size_t(256) << 20, fr / 4);
+    }
+    staging_limit = staging_bytes;
+    SFN_HIP(hipEventCreate(&ev0));
+    SFN_HIP(hipEventCreate(&ev1));
+}
+
+Workspace::~Workspace() {
+    (void)hipStreamSynchronize(s);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+}
+
+double Workspace::sum_rows(const DevBuf &rows, int64_t n) {
+    seg.ensure(2 * sizeof(int64_t));
+    red.ensure(sizeof(double));
+    const int64_t h[2] = {0, n};
+    SFN_HIP(hipMemcpyAsync(seg.get(), h, sizeof(h), hipMemcpyHostToDevice, s));
+    launch_seg_sum(rows.as<double>(), seg.as<int64_t>(), 1, red.as<double>(), s);
+    return read_scalar(red.as<double>(), s);
+}
+
+double Workspace::max_rows(const DevBuf &rows, int64_t n) {
+    seg.ensure(2 * sizeof(int64_t));
+    red.ensure(sizeof(double));
+    const int64_t h[2] = {0, n};
+    SFN_HIP(hipMemcpyAsync(seg.get(), h, sizeof(h), hipMemcpyHostToDevice, s));
+    launch_seg_max(rows.as<double>(), seg.as<int64_t>(), 1, red.as<double>(), s);
+    return read_scalar(red.as<double>(), s);
+}
+
+template <typename V>
+void product(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D, double coef,
+             double dcoef, double diag, DMat<V> &C, DevBuf *sq_prod, DevBuf *sq_out) {
+    const int64_t n = A.n;
+    hipStream_t s = w.s;
+    if (B.n != n || (D && D->n != n)) throw Error(SIGN_EINVAL, "product: shape mismatch");
+    w.lo.ensure(sizeof(int32_t) * n);
+    w.span.ensure(sizeof(int32_t) * n);
+    w.cap.ensure(sizeof(int64_t) * n);
+    w.work.ensure(sizeof(int64_t) * n);
+    w.capoff.ensure(sizeof(int64_t) * (n + 1));
+    w.workoff.ensure(sizeof(int64_t) * (n + 1));
+    w.tmp.ensure(sizeof(int64_t) * scan_tmp_elems(n));
+    if (sq_prod) sq_prod->ensure(sizeof(double) * n);
+    if (sq_out) sq_out->ensure(sizeof(double) * n);
+    C.ensure_rows(n);
+
+    MatView<V> Dv;
+    if (D) Dv = D->view();
+    launch_plan<V>(A.view(), B.view(), Dv, diag != 0.0, 0, n, w.lo.as<int32_t>(),
+                   w.span.as<int32_t>(), w.cap.as<int64_t>(), w.work.as<int64_t>(), s);
+    launch_exclusive_scan_i64(w.cap.as<int64_t>(), n, w.capoff.as<int64_t>(), w.tmp.as<int64_t>(),
+                              0, s);
+    launch_exclusive_scan_i64(w.work.as<int64_t>(), n, w.workoff.as<int64_t>(),
+                              w.tmp.as<int64_t>(), 0, s);
+    int64_t tot[2];
+    SFN_HIP(hipMemcpyAsync(&tot[0], w.capoff.as<int64_t>() + n, sizeof(int64_t),
+                           hipMemcpyDeviceToHost, s));
+    SFN_HIP(hipMemcpyAsync(&tot[1], w.workoff.as<int64_t>() + n, sizeof(int64_t),
+                           hipMemcpyDeviceToHost, s));
+    SFN_HIP(hipStreamSynchronize(s));
+    const int64_t total_cap = tot[0];
+    w.products += tot[1];
+
+    // batches of rows whose reserved output fits the staging budget
+    const size_t entry = sizeof(int32_t) + sizeof(V);
+    const int64_t budget = std::max<int64_t>((int64_t)(w.staging_limit / entry), n);
+    std::vector<int64_t> cuts{0};
+    std::vector<int64_t> capoff_h;
+    if (total_cap <= budget) {
+        cuts.push_back(n);
+    } else {
+        capoff_h.resize(n + 1);
+        SFN_HIP(hipMemcpyAsync(capoff_h.data(), w.capoff.get(), sizeof(int64_t) * (n + 1),
+                               hipMemcpyDeviceToHost, s));
+        SFN_HIP(hipStreamSynchronize(s));
+        int64_t r0 = 0;
+        while (r0 < n) {
+            // largest r1 with capoff[r1] - capoff[r0] <= budget (at least one row)
+            auto it = std::upper_bound(capoff_h.begin() + r0 + 1, capoff_h.end(),
+                                       capoff_h[r0] + budget);
+            int64_t r1 = (int64_t)(it - capoff_h.begin()) - 1;
+            if (r1 <= r0) r1 = r0 + 1;
+            cuts.push_back(r1);
+            r0 = r1;
+        }
+    }
+    const int64_t a_extent = A.capacity();
+    w.cursor.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(a_extent, 1));
+    w.bins.ensure(sizeof(int32_t) * 4 * (size_t)std::max<int64_t>(n, 1));
+    w.counts.ensure(sizeof(int32_t) * 4);
+
+    int64_t running = 0;
+    for (size_t b = 0; b + 1 < cuts.size(); ++b) {
+        const int64_t r0 = cuts[b], r1 = cuts[b + 1];
+        const int64_t base = capoff_h.empty() ? 0 : capoff_h[r0];
+        const int64_t bcap = capoff_h.empty() ? total_cap : capoff_h[r1] - base;
+        w.stage_col.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(bcap, 1));
+        w.stage_val.ensure(sizeof(V) * (size_t)std::max<int64_t>(bcap, 1));
+        SFN_HIP(hipMemsetAsync(w.counts.get(), 0, sizeof(int32_t) * 4, s));
+        launch_bin_rows(w.span.as<int32_t>(), w.work.as<int64_t>(), r0, r1, kSmallTile, kMidTile,
+                        w.bins.as<int32_t>(), n, w.counts.as<int32_t>(), C.lenp(),
+                        sq_prod ? sq_prod->as<double>() : nullptr,
+                        sq_out ? sq_out->as<double>() : nullptr, s);
+        int32_t cnt[4];
+        SFN_HIP(hipMemcpyAsync(cnt, w.counts.get(), sizeof(cnt), hipMemcpyDeviceToHost, s));
+        SFN_HIP(hipStreamSynchronize(s));
+        SFN_HIP(hipEventRecord(w.ev0, s));
+        for (int cls = 3; cls >= 1; --cls)
+            launch_spgemm<V>(cls, w.bins.as<int32_t>() + (int64_t)cls * n, cnt[cls], A.view(),
+                             B.view(), Dv, coef, dcoef, diag, w.lo.as<int32_t>(),
+                             w.span.as<int32_t>(), base, w.capoff.as<int64_t>(),
+                             w.stage_col.as<int32_t>(), w.stage_val.as<V>(), C.lenp(),
+                             w.cursor.as<int32_t>(), sq_prod ? sq_prod->as<double>() : nullptr,
+                             sq_out ? sq_out->as<double>() : nullptr, s);
+        SFN_HIP(hipEventRecord(w.ev1, s));
+        // compact row starts of this batch, continuing from the previous batches
+        launch_exclusive_scan_i32(C.lenp() + r0, r1 - r0, C.begp() + r0,
+                                  w.tmp.as<int64_t>(), running, s);
+        const int64_t end = read_scalar(C.begp() + r1, s);
+        float ms = 0.f;
+        SFN_HIP(hipEventElapsedTime(&ms, w.ev0, w.ev1));
+        w.spgemm_ms += ms;
+        C.ensure_entries(end, running);
+        launch_copy_rows<V>(w.capoff.as<int64_t>(), base, C.lenp(),
+                            w.stage_col.as<int32_t>(), w.stage_val.as<V>(), r0, r1,
+                            C.begp(), C.colp(), C.valp(), s);
+        running = end;
+    }
+    C.nnz = running;
+    // algorithmic bytes of the numeric kernels: one B entry per product, the
+    // A and D rows with their B-row descriptors, the stored output, row data
+    const double eb = (double)entry;
+    const double a_nnz = (double)A.nnz, d_nnz = D ? (double)D->nnz : 0.0;
+    w.spgemm_bytes += eb * (double)tot[1] + (eb + 12.0) * a_nnz + eb * d_nnz +
+                      eb * (double)running + 40.0 * (double)n;
+}
+
+template <typename V, typename Vo>
+int filter(Workspace &w, const DMat<V> &In, double tau, DMat<Vo> &Out, DevBuf *sq_keep,
+           DevBuf *sq_drop) {
+    const int64_t n = In.n;
+    hipStream_t s = w.s;
+    Out.ensure_rows(n);
+    w.hist.ensure(sizeof(uint64_t) * kBuckets);
+    w.seg.ensure(2 * sizeof(int64_t));
+    w.tau.ensure(sizeof(double));
+    w.bstar.ensure(sizeof(int));
+    w.tmp.ensure(sizeof(int64_t) * scan_tmp_elems(n));
+    if (sq_keep) sq_keep->ensure(sizeof(double) * n);
+    if (sq_drop) sq_drop->ensure(sizeof(double) * n);
+    const int64_t h[2] = {0, n};
+    SFN_HIP(hipMemcpyAsync(w.seg.get(), h, sizeof(h), hipMemcpyHostToDevice, s));
+    SFN_HIP(hipMemcpyAsync(w.tau.get(), &tau, sizeof(double), hipMemcpyHostToDevice, s));
+    SFN_HIP(hipMemsetAsync(w.hist.get(), 0, sizeof(uint64_t) * kBuckets, s));
+    launch_histogram<V>(In.view(), w.seg.as<int64_t>(), 1, n, w.hist.as<uint64_t>(), s);
+    launch_select(w.hist.as<uint64_t>(), w.tau.as<double>(), 1, w.bstar.as<int>(), s);
+    launch_count_keep<V>(In.view(), nullptr, w.bstar.as<int>(), Out.lenp(),
+                         sq_keep ? sq_keep->as<double>() : nullptr,
+                         sq_drop ? sq_drop->as<double>() : nullptr, s);
+    launch_exclusive_scan_i32(Out.lenp(), n, Out.begp(),
+                              w.tmp.as<int64_t>(), 0, s);
+    int64_t total;
+    int bstar;
+    SFN_HIP(hipMemcpyAsync(&total, Out.begp() + n, sizeof(int64_t),
+                           hipMemcpyDeviceToHost, s));
+    SFN_HIP(hipMemcpyAsync(&bstar, w.bstar.get(), sizeof(int), hipMemcpyDeviceToHost, s));
+    SFN_HIP(hipStreamSynchronize(s));
+    Out.ensure_entries(total);
+    launch_scatter_keep<V, Vo>(In.view(), nullptr, w.bstar.as<int>(), Out.begp(),
+                               Out.colp(), Out.valp(), s);
+    Out.nnz = total;
+    return bstar;
+}
+
+template <typename V>
+void row_sumsq(Workspace &w, const DMat<V> &X, DevBuf &rows) {
+    const int64_t n = X.n;
+    rows.ensure(sizeof(double) * n);
+    w.icnt.ensure(sizeof(int32_t) * std::max<int64_t>(n, 1));
+    w.zero_b.ensure(sizeof(int));
+    SFN_HIP(hipMemsetAsync(w.zero_b.get(), 0, sizeof(int), w.s));
+    launch_count_keep<V>(X.view(), nullptr, w.zero_b.as<int>(), w.icnt.as<int32_t>(),
+                         rows.as<double>(), nullptr, w.s);
+}
+
+double nsf_budget(double e, double xfro, double tol, double c_fixed, double switch_res) {
+    if (e >= switch_res) return c_fixed * tol;
+    return 0.75 * e * e / (3.0 * xfro + xfro * xfro * xfro);
+}
+
+double nmf_budget(double e, double xfro, double zfro, double tol, double c_fixed,
+                  double switch_res) {
+    if (e >= switch_res) return c_fixed * tol;
+    return e * e / (xfro + zfro);
+}
+
+template <typename V>
+LoopOut nsf_loop(Workspace &w, DMat<V> &X, const LoopParams &p,
+                 std::vector<sign_iter_stats> &trace) {
+    const int64_t n = X.n;
+    DMat<V> R, Xb, Xn;
+    R.bind(w.al); Xb.bind(w.al); Xn.bind(w.al);
+    LoopOut out;
+    row_sumsq(w, X, w.rs3);
+    double xf = std::sqrt(w.sum_rows(w.rs3, n));
+    double d_prev = std::numeric_limits<double>::infinity();
+    int n_up = 0, n_flat = 0;
+    std::vector<double> es;
+    for (int k = 1;; ++k) {
+        const double t0 = now_s();
+        // residual of the current iterate: R^_k = I - X^_k^2
+        product<V>(w, X, X, nullptr, -1.0, 0.0, 1.0, R, nullptr, &w.rs1);
+        const double e = std::sqrt(w.sum_rows(w.rs1, n));
+        es.push_back(e);
+        sign_iter_stats it{};
+        it.e = e; it.xfro = xf; it.nnz_x = X.nnz; it.nnz_r = R.nnz; it.fp32 = p.fp32;
+        out.iters = k - 1; out.e = e; out.xfro = xf;
+        const bool conv = (p.stop_rule == 1) ? (d_prev < p.tol) : (e <= p.tol);
+        bool stop = conv;
+        if (conv) out.status = SIGN_OK;
+        if (!stop) {
+            if (!std::isfinite(e)) { out.status = SIGN_EDIVERGED; stop = true; }
+            else if (k >= 2) {
+                const double ep = es[k - 2];
+                n_up = (e > ep && e > 1.0) ? n_up + 1 : 0;
+                n_flat = (e < 1e-8 && e > 0.5 * ep) ? n_flat + 1 : 0;
+                if (n_up >= 3) { out.status = SIGN_EDIVERGED; stop = true; }
+                else if (n_flat >= 2) { out.status = SIGN_OK; out.stagnated = 1; stop = true; }
+            }
+            if (!stop && k - 1 >= p.max_iter) { out.status = SIGN_ENOCONV; stop = true; }
+        }
+        if (stop) {
+            it.ms = 1e3 * (now_s() - t0);
+            trace.push_back(it);
+            break;
+        }
+        const double tau = nsf_budget(e, xf, p.tol, p.c_fixed, p.switch_res);
+        if (p.filter_y) {
+            filter<V, V>(w, R, tau, Xn, nullptr, nullptr);
+            std::swap(R, Xn);
+        }
+        // Xbar_{k+1} = X^_k + 1/2 X^_k R^_k  (= 1/2 X^_k (3I - X^_k^2))
+        product<V>(w, X, R, &X, 0.5, 1.0, 0.0, Xb, &w.rs2, nullptr);
+        const double d = std::sqrt(w.sum_rows(w.rs2, n));
+        // X^_{k+1} = Xbar_{k+1} - F_{k+1}
+        const int bstar = filter<V, V>(w, Xb, tau, Xn, &w.rs3, &w.rs4);
+        const double xf_new = std::sqrt(w.sum_rows(w.rs3, n));
+        const double ff = std::sqrt(w.sum_rows(w.rs4, n));
+        it.d = d; it.tau = tau; it.ffro = ff; it.nnz_bar = Xb.nnz; it.bstar = bstar;
+        it.ms = 1e3 * (now_s() - t0);
+        trace.push_back(it);
+        std::swap(X, Xn);
+        xf = xf_new;
+        d_prev = d;
+        out.d = d;
+    }
+    return out;
+}
+
+template void product<double>(Workspace &, const DMat<double> &, const DMat<double> &,
+                              const DMat<double> *, double, double, double, DMat<double> &,
+                              DevBuf *, DevBuf *);
+template void product<float>(Workspace &, const DMat<float> &, const DMat<float> &,
+                             const DMat<float> *, double, double, double, DMat<float> &, DevBuf *,
+                             DevBuf *);
+template int filter<double, double>(Workspace &, const DMat<double> &, double, DMat<double> &,
+                                    DevBuf *, DevBuf *);
+template int filter<float, float>(Workspace &, const DMat<float> &, double, DMat<float> &,
+                                  DevBuf *, DevBuf *);
+template int filter<float, double>(Workspace &, const DMat<float> &, double, DMat<double> &,
+                                   DevBuf *, DevBuf *);
+template int filter<double, float>(Workspace &, const DMat<double> &, double, DMat<float> &,
+                                   DevBuf *, DevBuf *);
+template void row_sumsq<double>(Workspace &, const DMat<double> &, DevBuf &);
+template void row_sumsq<float>(Workspace &, const DMat<float> &, DevBuf &);
+template LoopOut nsf_loop<double>(Workspace &, DMat<double> &, const LoopParams &,
+                                  std::vector<sign_iter_stats> &);
+template LoopOut nsf_loop<float>(Workspace &, DMat<float> &, const LoopParams &,
+                                 std::vector<sign_iter_stats> &);
+
+}  // namespace sfn

@@ -1,0 +1,77 @@
+// Host drivers of libsignfn: one sparse product, one filtering step, and the
+// filtered Newton-Schulz / filtered Newton loops built from them.
+#pragma once
+
+#include <chrono>
+#include <vector>
+
+#include "runtime.hpp"
+
+namespace sfn {
+
+// Per-call scratch shared by every product and filter of one solve.
+struct Workspace {
+    Allocator *al;
+    hipStream_t s;
+    size_t staging_limit;  // bytes of gapped product output per batch
+    DevBuf lo, span, cap, work, capoff, workoff, tmp, bins, counts, cursor, stage_col, stage_val;
+    DevBuf rs1, rs2, rs3, rs4, icnt, hist, tau, bstar, seg, red, flag, zero_b;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // accumulated product statistics
+    int64_t products = 0;
+    double spgemm_ms = 0.0;
+    double spgemm_bytes = 0.0;
+    explicit Workspace(Allocator *a, size_t staging_bytes);
+    ~Workspace();
+    // ||rows||: deterministic sum of a per-row double array over [0, n)
+    double sum_rows(const DevBuf &rows, int64_t n);
+    double max_rows(const DevBuf &rows, int64_t n);
+};
+
+// C = diag*I + coef*A*B + dcoef*D (D may be null); C becomes compact CSR.
+// sq_prod[i] receives the sum of squares of row i of coef*A*B and sq_out[i]
+// that of the stored row of C (either may be null).
+template <typename V>
+void product(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D, double coef,
+             double dcoef, double diag, DMat<V> &C, DevBuf *sq_prod, DevBuf *sq_out);
+
+// Out = In without its largest low-magnitude part of Frobenius norm <= tau.
+// Returns the cut bucket; sq_keep/sq_drop (optional) receive per-row sums of
+// squares of kept / dropped entries.
+template <typename V, typename Vo>
+int filter(Workspace &w, const DMat<V> &In, double tau, DMat<Vo> &Out, DevBuf *sq_keep,
+           DevBuf *sq_drop);
+
+// ||X||_F^2 per row into rows (via the survivor pass with an all-keeping cut).
+template <typename V>
+void row_sumsq(Workspace &w, const DMat<V> &X, DevBuf &rows);
+
+// Budget of the filter: c_fixed*tol before the switch, eq. 1.18 / eq. 1.13 after.
+double nsf_budget(double e, double xfro, double tol, double c_fixed, double switch_res);
+double nmf_budget(double e, double xfro, double zfro, double tol, double c_fixed,
+                  double switch_res);
+
+struct LoopParams {
+    double tol, c_fixed, switch_res;
+    int stop_rule, max_iter, filter_y;
+    int fp32;  // recorded in the trace
+};
+
+struct LoopOut {
+    int status = SIGN_OK;
+    int iters = 0;
+    int stagnated = 0;
+    double e = 0.0, d = 0.0, xfro = 0.0;
+};
+
+// Algorithm 3.2.1 on X (compact, modified in place to the final iterate).
+template <typename V>
+LoopOut nsf_loop(Workspace &w, DMat<V> &X, const LoopParams &p,
+                 std::vector<sign_iter_stats> &trace);
+
+inline double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+}  // namespace sfn

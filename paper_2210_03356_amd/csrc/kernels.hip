@@ -1,0 +1,822 @@
+// Device kernels of libsignfn for gfx950 (CDNA4, wave64).
+//
+// The numeric product is row-wise Gustavson: row i of C = diag*I + coef*A*B + D
+// is accumulated in an LDS-resident dense window of `tile` consecutive columns
+// with native LDS float atomics (ds_add_f64 / ds_add_f32).  Rows whose column
+// range exceeds the tile are swept in several windows; B's rows are sorted,
+// so each (row of A entry, window) pair resumes from a per-entry cursor and
+// every B entry is read once per output row.  The finished window is scanned
+// in column order and its nonzeros written out, so results come out sorted
+// and without stored zeros.  The path is gather- and bandwidth-bound (no
+// dense contraction), so MFMA is not used.
+#include "kernels.hpp"
+
+#include <climits>
+#include <cmath>
+#include <type_traits>
+
+namespace sfn {
+
+namespace {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+__device__ __forceinline__ int wave_id() { return threadIdx.x / kWave; }
+
+__device__ __forceinline__ int rl_i32(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ int64_t rl_i64(int64_t v, int l) {
+    const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffff), l);
+    const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ double rl_val(double v, int l) {
+    return __longlong_as_double(rl_i64(__double_as_longlong(v), l));
+}
+__device__ __forceinline__ float rl_val(float v, int l) {
+    return __int_as_float(rl_i32(__float_as_int(v), l));
+}
+
+// number of set bits of m in lanes below the calling lane
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ int wave_min(int v) {
+    for (int o = kWave / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+    for (int o = kWave / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+// inclusive scan across the wave
+__device__ __forceinline__ int64_t wave_incl_scan(int64_t v) {
+    const int lane = lane_id();
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int64_t t = __shfl_up(v, o);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Bucket of |x| from the IEEE-754 binary64 pattern: 0 below 2^-127, kBucketTop
+// at or above 1, else 1 + 16*(E+127) + (top four fraction bits).
+__device__ __forceinline__ int bucket_of(double x) {
+    const uint64_t b = (uint64_t)__double_as_longlong(x) & 0x7fffffffffffffffull;
+    if (b >= 0x3ff0000000000000ull) return kBucketTop;
+    const int E = (int)(b >> 52) - 1023;
+    if (E < -127) return 0;
+    return 1 + 16 * (E + 127) + (int)((b >> 48) & 15u);
+}
+
+template <typename T>
+__device__ __forceinline__ double as_f64(T v) { return (double)v; }
+
+// ---------------------------------------------------------------------------
+// validation and setup
+// ---------------------------------------------------------------------------
+__global__ void k_validate(const int64_t *rp, const int32_t *ci, const void *val, int f32,
+                           int64_t n, int64_t nnz, int *flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0 && (rp[0] != 0 || rp[n] != nnz)) atomicOr(flag, 1);
+    if (i >= n) return;
+    const int64_t b = rp[i], e = rp[i + 1];
+    if (b < 0 || e < b || e > nnz) { atomicOr(flag, 1); return; }
+    int f = 0;
+    int prev = -1;
+    for (int64_t p = b; p < e; ++p) {
+        const int c = ci[p];
+        if (c < 0 || c >= n) f |= 2;
+        if (c <= prev) f |= 4;
+        prev = c;
+        const double v = f32 ? (double)((const float *)val)[p] : ((const double *)val)[p];
+        if (!isfinite(v)) f |= 8;
+    }
+    if (f) atomicOr(flag, f);
+}
+
+__global__ void k_row_abs_sum(const int64_t *rp, const void *val, int f32, int64_t n,
+                              double *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int64_t p = rp[i]; p < rp[i + 1]; ++p)
+        s += fabs(f32 ? (double)((const float *)val)[p] : ((const double *)val)[p]);
+    out[i] = s;
+}
+
+__global__ void k_row_len(const int64_t *rp, int64_t n, int32_t *len) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) len[i] = (int32_t)(rp[i + 1] - rp[i]);
+}
+
+template <typename Vi, typename Vo>
+__global__ void k_scale_copy(const Vi *src, Vo *dst, int64_t n, double scale) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (Vo)((double)src[i] * scale);
+}
+
+// ---------------------------------------------------------------------------
+// deterministic segmented reductions: one workgroup per segment, each thread
+// sums a fixed strided subset, then a fixed tree
+// ---------------------------------------------------------------------------
+constexpr int kRedThreads = 1024;
+
+template <bool kMax>
+__global__ __launch_bounds__(kRedThreads) void k_seg_reduce(const double *x, const int64_t *seg,
+                                                            double *out) {
+    __shared__ double sh[kRedThreads];
+    const int s = blockIdx.x;
+    const int64_t lo = seg[s], hi = seg[s + 1];
+    double acc = 0.0;
+    for (int64_t r = lo + threadIdx.x; r < hi; r += kRedThreads)
+        acc = kMax ? fmax(acc, x[r]) : acc + x[r];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            sh[threadIdx.x] = kMax ? fmax(sh[threadIdx.x], sh[threadIdx.x + w])
+                                   : sh[threadIdx.x] + sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[s] = sh[0];
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan (three passes, fixed partition)
+// ---------------------------------------------------------------------------
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanChunk = kScanThreads * kScanItems;
+
+template <typename T>
+__device__ int64_t block_excl_scan(int64_t v, int64_t *sh_w, int64_t *total) {
+    const int lane = lane_id(), w = wave_id();
+    const int64_t inc = wave_incl_scan(v);
+    if (lane == kWave - 1) sh_w[w] = inc;
+    __syncthreads();
+    int64_t before = 0, tot = 0;
+    for (int q = 0; q < kScanThreads / kWave; ++q) {
+        if (q < w) before += sh_w[q];
+        tot += sh_w[q];
+    }
+    __syncthreads();
+    *total = tot;
+    return before + inc - v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void k_scan_partial(const T *in, int64_t n,
+                                                               int64_t *part) {
+    __shared__ int64_t shw[kScanThreads / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+    int64_t s = 0;
+    for (int q = 0; q < kScanItems; ++q) {
+        const int64_t i = base + (int64_t)q * kScanThreads + threadIdx.x;
+        if (i < n) s += (int64_t)in[i];
+    }
+    int64_t tot;
+    block_excl_scan<T>(s, shw, &tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// single workgroup: exclusive scan of the block totals in place
+__global__ __launch_bounds__(kScanThreads) void k_scan_top(int64_t *part, int64_t nb) {
+    __shared__ int64_t shw[kScanThreads / kWave];
+    int64_t carry = 0;
+    for (int64_t base = 0; base < nb; base += kScanThreads) {
+        const int64_t i = base + threadIdx.x;
+        const int64_t v = i < nb ? part[i] : 0;
+        int64_t tot;
+        const int64_t ex = block_excl_scan<int64_t>(v, shw, &tot);
+        if (i < nb) part[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) part[nb] = carry;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void k_scan_final(const T *in, int64_t n,
+                                                             const int64_t *part, int64_t nb,
+                                                             int64_t init, int64_t *out) {
+    __shared__ int64_t shw[kScanThreads / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+    // thread-contiguous items for the in-thread serial scan
+    int64_t vals[kScanItems];
+    int64_t s = 0;
+    for (int q = 0; q < kScanItems; ++q) {
+        const int64_t i = base + (int64_t)threadIdx.x * kScanItems + q;
+        vals[q] = i < n ? (int64_t)in[i] : 0;
+        s += vals[q];
+    }
+    int64_t tot;
+    int64_t run = init + part[blockIdx.x] + block_excl_scan<T>(s, shw, &tot);
+    for (int q = 0; q < kScanItems; ++q) {
+        const int64_t i = base + (int64_t)threadIdx.x * kScanItems + q;
+        if (i < n) out[i] = run;
+        run += vals[q];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = init + part[nb];
+}
+
+// ---------------------------------------------------------------------------
+// product planning and row classes
+// ---------------------------------------------------------------------------
+template <typename V>
+__global__ void k_plan(MatView<V> A, MatView<V> B, MatView<V> D, int diag, int64_t r0,
+                       int64_t r1, int32_t *lo, int32_t *span, int64_t *cap, int64_t *work) {
+    const int64_t i = r0 + (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
+    if (i >= r1) return;  // uniform per wave
+    const int lane = lane_id();
+    const int64_t ab = A.beg[i];
+    const int al = A.len[i];
+    int64_t u = 0;
+    int mn = INT_MAX, mx = -1;
+    for (int t = lane; t < al; t += kWave) {
+        const int k = A.col[ab + t];
+        const int bl = B.len[k];
+        if (bl > 0) {
+            const int64_t bb = B.beg[k];
+            u += bl;
+            mn = min(mn, B.col[bb]);
+            mx = max(mx, B.col[bb + bl - 1]);
+        }
+    }
+    u = wave_sum(u);
+    mn = wave_min(mn);
+    mx = wave_max(mx);
+    if (lane == 0) {
+        int64_t extra = 0;
+        if (D.len) {
+            const int dl = D.len[i];
+            if (dl > 0) {
+                const int64_t db = D.beg[i];
+                mn = min(mn, D.col[db]);
+                mx = max(mx, D.col[db + dl - 1]);
+                extra += dl;
+            }
+        }
+        if (diag) {
+            mn = min(mn, (int)i);
+            mx = max(mx, (int)i);
+            extra += 1;
+        }
+        if (mx < 0) {
+            lo[i] = 0; span[i] = 0; cap[i] = 0; work[i] = 0;
+        } else {
+            const int sp = mx - mn + 1;
+            lo[i] = mn;
+            span[i] = sp;
+            cap[i] = min((int64_t)sp, u + extra);
+            work[i] = u;
+        }
+    }
+}
+
+constexpr int kBinThreads = 256;
+
+__global__ __launch_bounds__(kBinThreads) void k_bin_rows(
+    const int32_t *span, const int64_t *work, int64_t r0, int64_t r1, int small_tile,
+    int mid_tile, int32_t *bins, int64_t bin_stride, int32_t *counts, int32_t *out_len,
+    double *sq_prod, double *sq_out) {
+    __shared__ int wc[kBinThreads / kWave][4];
+    __shared__ int base[4];
+    const int64_t i = r0 + (int64_t)blockIdx.x * kBinThreads + threadIdx.x;
+    int cls = -1;
+    if (i < r1) {
+        const int sp = span[i];
+        if (sp == 0) {
+            cls = 0;
+            out_len[i] = 0;
+            if (sq_prod) sq_prod[i] = 0.0;
+            if (sq_out) sq_out[i] = 0.0;
+        } else if (sp <= small_tile && work[i] <= (int64_t)8 * small_tile) {
+            cls = 1;
+        } else if (sp <= mid_tile) {
+            cls = 2;
+        } else {
+            cls = 3;
+        }
+    }
+    const int lane = lane_id(), w = wave_id();
+    int rank = 0;
+    for (int c = 1; c < 4; ++c) {
+        const uint64_t m = __ballot(cls == c);
+        if (cls == c) rank = lanes_below(m);
+        if (lane == 0) wc[w][c] = __popcll(m);
+    }
+    __syncthreads();
+    if (threadIdx.x < 4 && threadIdx.x > 0) {
+        int t = 0;
+        for (int q = 0; q < kBinThreads / kWave; ++q) t += wc[q][threadIdx.x];
+        base[threadIdx.x] = t ? atomicAdd(&counts[threadIdx.x], t) : 0;
+    }
+    __syncthreads();
+    if (cls >= 1) {
+        int off = base[cls] + rank;
+        for (int q = 0; q < w; ++q) off += wc[q][cls];
+        bins[(int64_t)cls * bin_stride + off] = (int32_t)i;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// numeric product
+// ---------------------------------------------------------------------------
+template <typename V, int T, int NT>
+__global__ __launch_bounds__(NT) void k_spgemm(
+    const int32_t *__restrict__ rows, MatView<V> A, MatView<V> B, MatView<V> D, V coef,
+    V dcoef, V diag, const int32_t *__restrict__ row_lo, const int32_t *__restrict__ row_span,
+    const int64_t *__restrict__ off, int64_t base, int32_t *__restrict__ out_col,
+    V *__restrict__ out_val, int32_t *__restrict__ out_len, int32_t *__restrict__ cursor,
+    double *__restrict__ sq_prod, double *__restrict__ sq_out) {
+    constexpr int NW = NT / kWave;
+    constexpr int REG = T / NW;  // LDS slots owned by each wave in the epilogue
+    static_assert(T % (NW * kWave) == 0, "tile must split evenly over the waves");
+    __shared__ V acc[T];
+    __shared__ int wcnt[NW];
+    __shared__ double wsum[2][NW];
+
+    const int lane = lane_id(), wave = wave_id();
+    const int i = rows[blockIdx.x];
+    const int lo = row_lo[i], span = row_span[i];
+    const int64_t abeg = A.beg[i];
+    const int alen = A.len[i];
+    const int64_t obase = off[i] - base;
+    const bool multi = span > T;
+    const bool has_d = D.len != nullptr;
+    const int dlen = has_d ? D.len[i] : 0;
+    const int64_t dbeg = has_d ? D.beg[i] : 0;
+
+    int written = 0;
+    double sqp = 0.0, sqo = 0.0;
+    for (int wlo = lo; wlo < lo + span; wlo += T) {
+        const int nsl = min(T, lo + span - wlo);
+        const int whi = wlo + nsl;
+        const bool first = (wlo == lo);
+        for (int s = threadIdx.x; s < nsl; s += NT) acc[s] = V(0);
+        __syncthreads();
+
+        // products: each wave takes 64 entries of row i of A at a time; lane q
+        // holds entry q's B-row descriptor, broadcast through readlane
+        for (int t0 = wave * kWave; t0 < alen; t0 += NW * kWave) {
+            const int t = t0 + lane;
+            int bl = 0, cur = 0;
+            int64_t bb = 0;
+            V a = V(0);
+            if (t < alen) {
+                const int64_t pa = abeg + t;
+                const int k = A.col[pa];
+                a = coef * A.val[pa];
+                bb = B.beg[k];
+                bl = B.len[k];
+                if (!first) cur = cursor[pa];
+            }
+            const int cnt = min(kWave, alen - t0);
+            for (int q = 0; q < cnt; ++q) {
+                const int blq = rl_i32(bl, q);
+                int p = rl_i32(cur, q);
+                if (p < blq) {
+                    const int64_t bbq = rl_i64(bb, q);
+                    const V aq = rl_val(a, q);
+                    while (true) {
+                        const int pos = p + lane;
+                        int c = INT_MAX;
+                        V bv = V(0);
+                        if (pos < blq) {
+                            c = B.col[bbq + pos];
+                            bv = B.val[bbq + pos];
+                        }
+                        const bool in = c < whi;
+                        if (in) atomicAdd(&acc[c - wlo], aq * bv);
+                        const int np = __popcll(__ballot(in));
+                        p += np;
+                        if (np < kWave) break;
+                    }
+                }
+                if (multi && lane == q) cur = p;
+            }
+            if (multi && t < alen) cursor[abeg + t] = cur;
+        }
+        __syncthreads();
+
+        if (sq_prod) {
+            for (int s = threadIdx.x; s < nsl; s += NT) {
+                const double v = as_f64(acc[s]);
+                sqp += v * v;
+            }
+            __syncthreads();
+        }
+        if (has_d) {
+            for (int q = threadIdx.x; q < dlen; q += NT) {
+                const int c = D.col[dbeg + q];
+                if (c >= wlo && c < whi) acc[c - wlo] += dcoef * D.val[dbeg + q];
+            }
+            __syncthreads();
+        }
+        if (diag != V(0) && threadIdx.x == 0 && i >= wlo && i < whi) acc[i - wlo] += diag;
+        __syncthreads();
+
+        // write the window's nonzeros in column order
+        const int rbeg = wave * REG;
+        int cw = 0;
+        for (int s0 = rbeg; s0 < rbeg + REG && s0 < nsl; s0 += kWave) {
+            const int s = s0 + lane;
+            const V v = s < nsl ? acc[s] : V(0);
+            cw += __popcll(__ballot(v != V(0)));
+        }
+        if (lane == 0) wcnt[wave] = cw;
+        __syncthreads();
+        int o = written, tot = 0;
+        for (int w = 0; w < NW; ++w) {
+            const int c = wcnt[w];
+            if (w < wave) o += c;
+            tot += c;
+        }
+        for (int s0 = rbeg; s0 < rbeg + REG && s0 < nsl; s0 += kWave) {
+            const int s = s0 + lane;
+            const V v = s < nsl ? acc[s] : V(0);
+            const bool nz = v != V(0);
+            const uint64_t m = __ballot(nz);
+            if (nz) {
+                const int64_t pos = obase + o + lanes_below(m);
+                out_col[pos] = wlo + s;
+                out_val[pos] = v;
+                sqo += as_f64(v) * as_f64(v);
+            }
+            o += __popcll(m);
+        }
+        written += tot;
+        __syncthreads();
+    }
+    // row totals
+    sqp = wave_sum(sqp);
+    sqo = wave_sum(sqo);
+    if (lane == 0) { wsum[0][wave] = sqp; wsum[1][wave] = sqo; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int w = 0; w < NW; ++w) { a += wsum[0][w]; b += wsum[1][w]; }
+        out_len[i] = written;
+        if (sq_prod) sq_prod[i] = a;
+        if (sq_out) sq_out[i] = b;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// gapped -> compact copy (one wave per row)
+// ---------------------------------------------------------------------------
+template <typename V>
+__global__ void k_copy_rows(const int64_t *src_off, int64_t src_base, const int32_t *len,
+                            const int32_t *scol, const V *sval, int64_t r0, int64_t r1,
+                            const int64_t *dst_ptr, int32_t *dcol, V *dval) {
+    const int64_t i = r0 + (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
+    if (i >= r1) return;
+    const int l = len[i];
+    const int64_t s = src_off[i] - src_base, d = dst_ptr[i];
+    for (int p = lane_id(); p < l; p += kWave) {
+        dcol[d + p] = scol[s + p];
+        dval[d + p] = sval[s + p];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// filtering: histogram, selection, survivor count, scatter
+// ---------------------------------------------------------------------------
+constexpr int kHistThreads = 512;
+constexpr int kHistRowsPerBlock = 128;
+
+template <typename V>
+__global__ __launch_bounds__(kHistThreads) void k_histogram(MatView<V> X, const int64_t *seg_rows,
+                                                            uint64_t *hist) {
+    __shared__ uint32_t h[kBuckets];
+    const int s = blockIdx.y;
+    const int64_t rlo = seg_rows[s], rhi = seg_rows[s + 1];
+    const int64_t first = rlo + (int64_t)blockIdx.x * kHistRowsPerBlock;
+    if (first >= rhi) return;  // whole block
+    for (int b = threadIdx.x; b < kBuckets; b += kHistThreads) h[b] = 0;
+    __syncthreads();
+    const int64_t last = min(first + kHistRowsPerBlock, rhi);
+    for (int64_t r = first + wave_id(); r < last; r += kHistThreads / kWave) {
+        const int64_t b0 = X.beg[r];
+        const int l = X.len[r];
+        for (int p = lane_id(); p < l; p += kWave)
+            atomicAdd(&h[bucket_of(as_f64(X.val[b0 + p]))], 1u);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < kBuckets; b += kHistThreads)
+        if (h[b]) atomicAdd((unsigned long long *)&hist[(int64_t)s * kBuckets + b],
+                            (unsigned long long)h[b]);
+}
+
+__device__ double bucket_hi(int b) {
+    if (b <= 0) return ldexp(1.0, -127);
+    const int E = (b - 1) / 16 - 127;
+    const int j = (b - 1) % 16;
+    return ldexp(1.0 + (double)(j + 1) / 16.0, E);
+}
+
+__global__ void k_select(const uint64_t *hist, const double *tau, int nseg, int *bstar) {
+#pragma clang fp contract(off)
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nseg) return;
+    const uint64_t *c = hist + (int64_t)s * kBuckets;
+    const double t2 = tau[s] * tau[s];
+    double acc = 0.0;
+    int b = 0;
+    while (b < kBucketTop) {
+        const double h = bucket_hi(b);
+        const double hh = h * h;
+        const double add = (double)c[b] * hh;
+        if (acc + add > t2) break;
+        acc = acc + add;
+        ++b;
+    }
+    bstar[s] = b;
+}
+
+template <typename V>
+__global__ void k_count_keep(MatView<V> X, const int32_t *row_seg, const int *bstar,
+                             int32_t *cnt, double *sq_keep, double *sq_drop) {
+    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
+    if (i >= X.n) return;
+    const int b = bstar[row_seg ? row_seg[i] : 0];
+    const int64_t b0 = X.beg[i];
+    const int l = X.len[i];
+    int k = 0;
+    double sk = 0.0, sd = 0.0;
+    for (int p = lane_id(); p < l; p += kWave) {
+        const double v = as_f64(X.val[b0 + p]);
+        if (v != 0.0 && bucket_of(v) >= b) { ++k; sk += v * v; }
+        else sd += v * v;
+    }
+    k = wave_sum(k);
+    sk = wave_sum(sk);
+    sd = wave_sum(sd);
+    if (lane_id() == 0) {
+        cnt[i] = k;
+        if (sq_keep) sq_keep[i] = sk;
+        if (sq_drop) sq_drop[i] = sd;
+    }
+}
+
+template <typename V, typename Vo>
+__global__ void k_scatter_keep(MatView<V> X, const int32_t *row_seg, const int *bstar,
+                               const int64_t *dst_ptr, int32_t *dcol, Vo *dval) {
+    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
+    if (i >= X.n) return;
+    const int b = bstar[row_seg ? row_seg[i] : 0];
+    const int64_t b0 = X.beg[i];
+    const int l = X.len[i];
+    int64_t o = dst_ptr[i];
+    for (int p0 = 0; p0 < l; p0 += kWave) {
+        const int p = p0 + lane_id();
+        double v = 0.0;
+        int c = 0;
+        if (p < l) { v = as_f64(X.val[b0 + p]); c = X.col[b0 + p]; }
+        const bool keep = p < l && v != 0.0 && bucket_of(v) >= b;
+        const uint64_t m = __ballot(keep);
+        if (keep) {
+            const int64_t w = o + lanes_below(m);
+            dcol[w] = c;
+            dval[w] = (Vo)v;
+        }
+        o += __popcll(m);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// misc
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_fill(T *p, int64_t n, T v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_row_segments(const int64_t *seg_rows, int32_t *row_seg) {
+    const int s = blockIdx.y;
+    const int64_t r = seg_rows[s] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < seg_rows[s + 1]) row_seg[r] = s;
+}
+
+__global__ void k_shift_cols(const int64_t *rp, const int32_t *row_seg, const int32_t *delta,
+                             int64_t n, int32_t *col) {
+    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
+    if (i >= n) return;
+    const int d = delta[row_seg[i]];
+    for (int64_t p = rp[i] + lane_id(); p < rp[i + 1]; p += kWave) col[p] += d;
+}
+
+inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+// ===========================================================================
+// launchers
+// ===========================================================================
+void launch_validate(const int64_t *rp, const int32_t *ci, const void *val, int f32, int64_t n,
+                     int64_t nnz, int *flag, hipStream_t s) {
+    k_validate<<<blocks_for(n, 256), 256, 0, s>>>(rp, ci, val, f32, n, nnz, flag);
+}
+
+void launch_row_abs_sum(const int64_t *rp, const void *val, int f32, int64_t n, double *out,
+                        hipStream_t s) {
+    k_row_abs_sum<<<blocks_for(n, 256), 256, 0, s>>>(rp, val, f32, n, out);
+}
+
+void launch_row_len(const int64_t *rp, int64_t n, int32_t *len, hipStream_t s) {
+    k_row_len<<<blocks_for(n, 256), 256, 0, s>>>(rp, n, len);
+}
+
+template <typename Vi, typename Vo>
+void launch_scale_copy(const Vi *src, Vo *dst, int64_t n, double scale, hipStream_t s) {
+    if (n <= 0) return;
+    k_scale_copy<Vi, Vo><<<blocks_for(n, 256), 256, 0, s>>>(src, dst, n, scale);
+}
+template void launch_scale_copy<double, double>(const double *, double *, int64_t, double, hipStream_t);
+template void launch_scale_copy<double, float>(const double *, float *, int64_t, double, hipStream_t);
+template void launch_scale_copy<float, double>(const float *, double *, int64_t, double, hipStream_t);
+template void launch_scale_copy<float, float>(const float *, float *, int64_t, double, hipStream_t);
+
+void launch_seg_sum(const double *x, const int64_t *seg, int nseg, double *out, hipStream_t s) {
+    if (nseg > 0) k_seg_reduce<false><<<nseg, kRedThreads, 0, s>>>(x, seg, out);
+}
+void launch_seg_max(const double *x, const int64_t *seg, int nseg, double *out, hipStream_t s) {
+    if (nseg > 0) k_seg_reduce<true><<<nseg, kRedThreads, 0, s>>>(x, seg, out);
+}
+
+int64_t scan_tmp_elems(int64_t n) { return (n + kScanChunk - 1) / kScanChunk + 2; }
+
+template <typename T>
+static void scan_impl(const T *in, int64_t n, int64_t *out, int64_t *tmp, int64_t init,
+                      hipStream_t s) {
+    const int64_t nb = (n + kScanChunk - 1) / kScanChunk;
+    if (nb == 0) {
+        k_fill<int64_t><<<1, 1, 0, s>>>(out, 1, init);
+        return;
+    }
+    k_scan_partial<T><<<(unsigned)nb, kScanThreads, 0, s>>>(in, n, tmp);
+    k_scan_top<<<1, kScanThreads, 0, s>>>(tmp, nb);
+    k_scan_final<T><<<(unsigned)nb, kScanThreads, 0, s>>>(in, n, tmp, nb, init, out);
+}
+void launch_exclusive_scan_i64(const int64_t *in, int64_t n, int64_t *out, int64_t *tmp,
+                               int64_t init, hipStream_t s) {
+    scan_impl<int64_t>(in, n, out, tmp, init, s);
+}
+void launch_exclusive_scan_i32(const int32_t *in, int64_t n, int64_t *out, int64_t *tmp,
+                               int64_t init, hipStream_t s) {
+    scan_impl<int32_t>(in, n, out, tmp, init, s);
+}
+
+template <typename V>
+void launch_plan(MatView<V> A, MatView<V> B, MatView<V> D, int diag, int64_t r0, int64_t r1,
+                 int32_t *lo, int32_t *span, int64_t *cap, int64_t *work, hipStream_t s) {
+    if (r1 <= r0) return;
+    k_plan<V><<<blocks_for(r1 - r0, 4), 256, 0, s>>>(A, B, D, diag, r0, r1, lo, span, cap, work);
+}
+template void launch_plan<double>(MatView<double>, MatView<double>, MatView<double>, int, int64_t,
+                                  int64_t, int32_t *, int32_t *, int64_t *, int64_t *, hipStream_t);
+template void launch_plan<float>(MatView<float>, MatView<float>, MatView<float>, int, int64_t,
+                                 int64_t, int32_t *, int32_t *, int64_t *, int64_t *, hipStream_t);
+
+void launch_bin_rows(const int32_t *span, const int64_t *work, int64_t r0, int64_t r1,
+                     int small_tile, int mid_tile, int32_t *bins, int64_t bin_stride,
+                     int32_t *counts, int32_t *out_len, double *sq_prod, double *sq_out,
+                     hipStream_t s) {
+    if (r1 <= r0) return;
+    k_bin_rows<<<blocks_for(r1 - r0, kBinThreads), kBinThreads, 0, s>>>(
+        span, work, r0, r1, small_tile, mid_tile, bins, bin_stride, counts, out_len, sq_prod,
+        sq_out);
+}
+
+BinCfg bin_config(int cls, int value_bytes) {
+    switch (cls) {
+        case 1: return {512, 64};
+        case 2: return {4096, 256};
+        default: return {value_bytes == 8 ? 8192 : 16384, 512};
+    }
+}
+
+template <typename V>
+void launch_spgemm(int cls, const int32_t *rows, int nrows, MatView<V> A, MatView<V> B,
+                   MatView<V> D, double coef, double dcoef, double diag, const int32_t *lo,
+                   const int32_t *span, int64_t base, const int64_t *off, int32_t *out_col,
+                   V *out_val, int32_t *out_len, int32_t *cursor, double *sq_prod,
+                   double *sq_out, hipStream_t s) {
+    if (nrows <= 0) return;
+    const V c = (V)coef, d = (V)diag, dc = (V)dcoef;
+    switch (cls) {
+        case 1:
+            k_spgemm<V, 512, 64><<<nrows, 64, 0, s>>>(rows, A, B, D, c, dc, d, lo, span, off, base,
+                                                      out_col, out_val, out_len, cursor, sq_prod,
+                                                      sq_out);
+            break;
+        case 2:
+            k_spgemm<V, 4096, 256><<<nrows, 256, 0, s>>>(rows, A, B, D, c, dc, d, lo, span, off, base,
+                                                         out_col, out_val, out_len, cursor,
+                                                         sq_prod, sq_out);
+            break;
+        default:
+            k_spgemm<V, (sizeof(V) == 8 ? 8192 : 16384), 512><<<nrows, 512, 0, s>>>(
+                rows, A, B, D, c, dc, d, lo, span, off, base, out_col, out_val, out_len, cursor,
+                sq_prod, sq_out);
+            break;
+    }
+}
+template void launch_spgemm<double>(int, const int32_t *, int, MatView<double>, MatView<double>,
+                                    MatView<double>, double, double, double, const int32_t *,
+                                    const int32_t *, int64_t, const int64_t *, int32_t *, double *,
+                                    int32_t *, int32_t *, double *, double *, hipStream_t);
+template void launch_spgemm<float>(int, const int32_t *, int, MatView<float>, MatView<float>,
+                                   MatView<float>, double, double, double, const int32_t *,
+                                   const int32_t *, int64_t, const int64_t *, int32_t *, float *,
+                                   int32_t *, int32_t *, double *, double *, hipStream_t);
+
+template <typename V>
+void launch_copy_rows(const int64_t *src_off, int64_t src_base, const int32_t *len,
+                      const int32_t *scol, const V *sval, int64_t r0, int64_t r1,
+                      const int64_t *dst_ptr, int32_t *dcol, V *dval, hipStream_t s) {
+    if (r1 <= r0) return;
+    k_copy_rows<V><<<blocks_for(r1 - r0, 4), 256, 0, s>>>(src_off, src_base, len, scol, sval, r0,
+                                                         r1, dst_ptr, dcol, dval);
+}
+template void launch_copy_rows<double>(const int64_t *, int64_t, const int32_t *, const int32_t *,
+                                       const double *, int64_t, int64_t, const int64_t *,
+                                       int32_t *, double *, hipStream_t);
+template void launch_copy_rows<float>(const int64_t *, int64_t, const int32_t *, const int32_t *,
+                                      const float *, int64_t, int64_t, const int64_t *, int32_t *,
+                                      float *, hipStream_t);
+
+template <typename V>
+void launch_histogram(MatView<V> X, const int64_t *seg_rows, int nseg, int64_t max_seg_rows,
+                      uint64_t *hist, hipStream_t s) {
+    if (nseg <= 0 || max_seg_rows <= 0) return;
+    dim3 grid(blocks_for(max_seg_rows, kHistRowsPerBlock), nseg);
+    k_histogram<V><<<grid, kHistThreads, 0, s>>>(X, seg_rows, hist);
+}
+template void launch_histogram<double>(MatView<double>, const int64_t *, int, int64_t, uint64_t *,
+                                       hipStream_t);
+template void launch_histogram<float>(MatView<float>, const int64_t *, int, int64_t, uint64_t *,
+                                      hipStream_t);
+
+void launch_select(const uint64_t *hist, const double *tau, int nseg, int *bstar, hipStream_t s) {
+    if (nseg > 0) k_select<<<blocks_for(nseg, 64), 64, 0, s>>>(hist, tau, nseg, bstar);
+}
+
+template <typename V>
+void launch_count_keep(MatView<V> X, const int32_t *row_seg, const int *bstar, int32_t *cnt,
+                       double *sq_keep, double *sq_drop, hipStream_t s) {
+    if (X.n <= 0) return;
+    k_count_keep<V><<<blocks_for(X.n, 4), 256, 0, s>>>(X, row_seg, bstar, cnt, sq_keep, sq_drop);
+}
+template void launch_count_keep<double>(MatView<double>, const int32_t *, const int *, int32_t *,
+                                        double *, double *, hipStream_t);
+template void launch_count_keep<float>(MatView<float>, const int32_t *, const int *, int32_t *,
+                                       double *, double *, hipStream_t);
+
+template <typename V, typename Vo>
+void launch_scatter_keep(MatView<V> X, const int32_t *row_seg, const int *bstar,
+                         const int64_t *dst_ptr, int32_t *dcol, Vo *dval, hipStream_t s) {
+    if (X.n <= 0) return;
+    k_scatter_keep<V, Vo><<<blocks_for(X.n, 4), 256, 0, s>>>(X, row_seg, bstar, dst_ptr, dcol,
+                                                             dval);
+}
+template void launch_scatter_keep<double, double>(MatView<double>, const int32_t *, const int *,
+                                                  const int64_t *, int32_t *, double *,
+                                                  hipStream_t);
+template void launch_scatter_keep<float, float>(MatView<float>, const int32_t *, const int *,
+                                                const int64_t *, int32_t *, float *, hipStream_t);
+template void launch_scatter_keep<float, double>(MatView<float>, const int32_t *, const int *,
+                                                 const int64_t *, int32_t *, double *,
+                                                 hipStream_t);
+template void launch_scatter_keep<double, float>(MatView<double>, const int32_t *, const int *,
+                                                 const int64_t *, int32_t *, float *, hipStream_t);
+
+void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
+    if (n > 0) k_fill<int32_t><<<blocks_for(n, 256), 256, 0, s>>>(p, n, v);
+}
+void launch_fill_f64(double *p, int64_t n, double v, hipStream_t s) {
+    if (n > 0) k_fill<double><<<blocks_for(n, 256), 256, 0, s>>>(p, n, v);
+}
+
+void launch_row_segments(const int64_t *seg_rows, int nseg, int64_t max_seg_rows, int32_t *row_seg,
+                         hipStream_t s) {
+    if (nseg <= 0 || max_seg_rows <= 0) return;
+    dim3 grid(blocks_for(max_seg_rows, 256), nseg);
+    k_row_segments<<<grid, 256, 0, s>>>(seg_rows, row_seg);
+}
+
+void launch_shift_cols(const int64_t *rp, const int32_t *row_seg, const int32_t *delta,
+                       int64_t n, int32_t *col, hipStream_t s) {
+    if (n > 0) k_shift_cols<<<blocks_for(n, 4), 256, 0, s>>>(rp, row_seg, delta, n, col);
+}
+
+}  // namespace sfn

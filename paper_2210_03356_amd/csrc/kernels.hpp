@@ -1,0 +1,120 @@
+// Device kernels of libsignfn and their host-side launchers (gfx950, wave64).
+//
+// Matrices on the device are addressed row by row through (beg, len):
+// row i occupies col[beg[i] .. beg[i]+len[i]) and val[...].  A compact CSR
+// has beg = row_ptr (n+1 entries, beg[n] = nnz); a "gapped" matrix produced
+// by a product keeps each row at a reserved offset with room to spare.
+// Columns are strictly ascending within every row.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sfn {
+
+constexpr int kBuckets = 2048;   // histogram length (buckets 0 .. kBucketTop used)
+constexpr int kBucketTop = 2033; // |x| >= 1: never dropped
+
+template <typename V>
+struct MatView {
+    int64_t n = 0;
+    const int64_t *beg = nullptr;
+    const int32_t *len = nullptr;
+    const int32_t *col = nullptr;
+    const V *val = nullptr;
+};
+
+// Launch geometry of the numeric product for one row class.
+struct BinCfg {
+    int tile;     // LDS accumulator slots (columns per window)
+    int threads;  // workgroup size
+};
+
+// ---- validation / setup --------------------------------------------------
+// flag bits: 1 row_ptr, 2 column range, 4 column order, 8 non-finite value
+void launch_validate(const int64_t *rp, const int32_t *ci, const void *val, int f32, int64_t n,
+                     int64_t nnz, int *flag, hipStream_t s);
+// per-row sum of |a_ij| into out[n] (FP64)
+void launch_row_abs_sum(const int64_t *rp, const void *val, int f32, int64_t n, double *out,
+                        hipStream_t s);
+// len[i] = rp[i+1]-rp[i]
+void launch_row_len(const int64_t *rp, int64_t n, int32_t *len, hipStream_t s);
+// dst = src * scale (typed conversion); counts n entries
+template <typename Vi, typename Vo>
+void launch_scale_copy(const Vi *src, Vo *dst, int64_t n, double scale, hipStream_t s);
+
+// ---- reductions (deterministic: fixed partition and order) -----------------
+// out[s] = sum_{r in [seg[s], seg[s+1])} x[r]   (one workgroup per segment)
+void launch_seg_sum(const double *x, const int64_t *seg, int nseg, double *out, hipStream_t s);
+void launch_seg_max(const double *x, const int64_t *seg, int nseg, double *out, hipStream_t s);
+
+// ---- scans -------------------------------------------------------------------
+// out[0..n] = init + exclusive prefix of in[0..n) (int64 or int32 input).
+// tmp must hold scan_tmp_elems(n) int64.
+int64_t scan_tmp_elems(int64_t n);
+void launch_exclusive_scan_i64(const int64_t *in, int64_t n, int64_t *out, int64_t *tmp,
+                               int64_t init, hipStream_t s);
+void launch_exclusive_scan_i32(const int32_t *in, int64_t n, int64_t *out, int64_t *tmp,
+                               int64_t init, hipStream_t s);
+
+// ---- product C = diag*I + coef*A*B + dcoef*D ---------------------------------
+// Plan: per row i of A (rows [r0, r1)): column window [lo[i], lo[i]+span[i]),
+// reserved output capacity cap[i], product count work[i].
+template <typename V>
+void launch_plan(MatView<V> A, MatView<V> B, MatView<V> D, int diag, int64_t r0, int64_t r1,
+                 int32_t *lo, int32_t *span, int64_t *cap, int64_t *work, hipStream_t s);
+
+// Row classes: 0 empty, 1..3 tiles.  Writes row lists per class (bins[c] holds
+// up to r1-r0 rows), counts into counts[4] (device), and len=0 for empty rows.
+void launch_bin_rows(const int32_t *span, const int64_t *work, int64_t r0, int64_t r1,
+                     int small_tile, int mid_tile, int32_t *bins, int64_t bin_stride,
+                     int32_t *counts, int32_t *out_len, double *sq_prod, double *sq_out,
+                     hipStream_t s);
+
+// Numeric product for the rows listed in `rows` (class cfg).  Row i writes
+// at out_col/out_val[off[i] - base .. ), out_len[i], sq_prod[i] (sum of squares
+// of coef*A*B) and sq_out[i] (sum of squares of the stored output), when the
+// latter two pointers are non-null.  cursor: int32 scratch per nonzero of A.
+template <typename V>
+void launch_spgemm(int cls, const int32_t *rows, int nrows, MatView<V> A, MatView<V> B,
+                   MatView<V> D, double coef, double dcoef, double diag, const int32_t *lo,
+                   const int32_t *span, int64_t base, const int64_t *off, int32_t *out_col,
+                   V *out_val, int32_t *out_len, int32_t *cursor, double *sq_prod,
+                   double *sq_out, hipStream_t s);
+BinCfg bin_config(int cls, int value_bytes);
+
+// Copy rows [r0, r1) from a gapped layout (row i at src_off[i] - src_base)
+// into a compact one (dst_ptr absolute row starts).
+template <typename V>
+void launch_copy_rows(const int64_t *src_off, int64_t src_base, const int32_t *len,
+                      const int32_t *scol, const V *sval, int64_t r0, int64_t r1,
+                      const int64_t *dst_ptr, int32_t *dcol, V *dval, hipStream_t s);
+
+// ---- filtering ---------------------------------------------------------------
+// Histogram of bucket(|x|) per segment.  seg_rows[s]..seg_rows[s+1] are the
+// rows of segment s; hist is nseg x kBuckets (uint64), zeroed by the caller.
+template <typename V>
+void launch_histogram(MatView<V> X, const int64_t *seg_rows, int nseg, int64_t max_seg_rows,
+                      uint64_t *hist, hipStream_t s);
+// bstar[s] = cut bucket for budget tau[s] (one thread per segment, ascending
+// FP64 accumulation without contraction).
+void launch_select(const uint64_t *hist, const double *tau, int nseg, int *bstar, hipStream_t s);
+// Survivors per row (bucket >= bstar[seg], value != 0) and their/dropped sums of squares.
+template <typename V>
+void launch_count_keep(MatView<V> X, const int32_t *row_seg, const int *bstar, int32_t *cnt,
+                       double *sq_keep, double *sq_drop, hipStream_t s);
+template <typename V, typename Vo>
+void launch_scatter_keep(MatView<V> X, const int32_t *row_seg, const int *bstar,
+                         const int64_t *dst_ptr, int32_t *dcol, Vo *dval, hipStream_t s);
+
+// ---- misc -----------------------------------------------------------------------
+void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+void launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
+// row_seg[r] = s for rows of segment s
+void launch_row_segments(const int64_t *seg_rows, int nseg, int64_t max_seg_rows, int32_t *row_seg,
+                         hipStream_t s);
+// Add delta[seg] to the columns of each row (block-diagonal relayout).
+void launch_shift_cols(const int64_t *rp, const int32_t *row_seg, const int32_t *delta,
+                       int64_t n, int32_t *col, hipStream_t s);
+
+}  // namespace sfn

@@ -1,0 +1,247 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle."""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import workloads as W
+from oracle import closed_forms as cf
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sf():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    import paper_2210_03356_amd as pkg
+    pkg.load()
+    oracle.build(force=False)
+    return pkg
+
+
+def _dev(sf, A, dtype=None):
+    return sf.DeviceCsr.from_host(A, dtype=dtype)
+
+
+def _abs(A):
+    return W.Csr(n=A.n, indptr=A.indptr, indices=A.indices, data=np.abs(A.data))
+
+
+def _check_product(sf, A, B, rtol=4e-15, exact_pattern=True):
+    r = sf.sign_spgemm(_dev(sf, A), _dev(sf, B))
+    assert r.status == "OK"
+    rp, ci, va = r.to_numpy()
+    orp, oci, ova = oracle.spgemm(A, B)
+    brp, bci, bound = oracle.spgemm(_abs(A), _abs(B))
+    kmax = max(1, int(np.diff(A.indptr).max()))
+    for i in range(A.n):   # sorted, unique columns in every row
+        assert np.all(np.diff(ci[rp[i]:rp[i + 1]]) > 0)
+    assert np.all(va != 0.0)
+    if exact_pattern:
+        # random values: no exact cancellation, so the patterns are identical
+        assert np.array_equal(rp, orp)
+        assert np.array_equal(ci, oci)
+        assert np.all(np.abs(va - ova) <= rtol * kmax * bound + 1e-300)
+    else:
+        # heavy cancellation: an entry may round to exactly zero (and be
+        # dropped) on one side only; compare on the union pattern
+        n = A.n
+        G = sp.csr_matrix((va, ci, rp), shape=(n, n))
+        O = sp.csr_matrix((ova, oci, orp), shape=(n, n))
+        Bd = sp.csr_matrix((bound, bci, brp), shape=(n, n))
+        D = (G - O).tocsr()
+        D.sort_indices()
+        lim = Bd.multiply(D != 0).tocsr()   # bound restricted to D's pattern
+        lim.sort_indices()
+        assert np.array_equal(D.indptr, lim.indptr) and np.array_equal(D.indices, lim.indices)
+        assert np.all(np.abs(D.data) <= rtol * kmax * lim.data + 1e-300)
+        # entries present on one side only are within the bound of zero
+    return r
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_spgemm_random_powerlaw(sf, seed):
+    A = W.random_sparse(900, mean_row=7, seed=seed)
+    B = W.random_sparse(900, mean_row=11, seed=seed + 100)
+    _check_product(sf, A, B)
+
+
+def test_spgemm_multiwindow_rows(sf):
+    # columns spread over 30000: each output row sweeps several LDS windows
+    A = W.random_sparse(30000, mean_row=5, seed=4, powerlaw=False)
+    B = W.random_sparse(30000, mean_row=9, seed=5, powerlaw=False)
+    r = _check_product(sf, A, B)
+    assert r.stats()["products"] > 0
+
+
+def test_spgemm_dense_rows_and_empty_rows(sf):
+    rng = np.random.default_rng(3)
+    n = 5000
+    # a few dense rows (class 3, several windows), many empty rows, a ragged tail
+    rows, cols = [], []
+    for i in range(n):
+        if i % 7 == 0:
+            continue
+        k = 2500 if i % 997 == 0 else int(rng.integers(1, 20))
+        c = rng.choice(n, size=k, replace=False)
+        rows.append(np.full(k, i)); cols.append(c)
+    r = np.concatenate(rows); c = np.concatenate(cols)
+    M = sp.csr_matrix((rng.uniform(0.1, 1, len(r)) * rng.choice([-1, 1], len(r)), (r, c)),
+                      shape=(n, n))
+    M.sort_indices()
+    A = W.Csr(n=n, indptr=M.indptr.astype(np.int64), indices=M.indices.astype(np.int32),
+              data=M.data)
+    _check_product(sf, A, A)
+
+
+def test_spgemm_tiny_and_identity(sf):
+    one = W.Csr(n=1, indptr=np.array([0, 1], np.int64), indices=np.array([0], np.int32),
+                data=np.array([-3.0]))
+    r = sf.sign_spgemm(_dev(sf, one), _dev(sf, one))
+    rp, ci, va = r.to_numpy()
+    assert rp.tolist() == [0, 1] and ci.tolist() == [0] and va.tolist() == [9.0]
+    empty = W.Csr(n=5, indptr=np.zeros(6, np.int64), indices=np.zeros(0, np.int32),
+                  data=np.zeros(0))
+    r = sf.sign_spgemm(_dev(sf, empty), _dev(sf, W.tridiag_c1(5)))
+    assert r.to_numpy()[0].tolist() == [0] * 6
+
+
+def test_spgemm_grid_square(sf):
+    # square of a dense-ish iterate of the 2D family (rows of a few thousand)
+    A = W.laplacian_2d(40, jitter=0.05, seed=2, m=8.0)
+    X = oracle.nsf(A, tol=1e-12)
+    Xc = W.Csr(n=A.n, indptr=X.indptr, indices=X.indices, data=X.data)
+    _check_product(sf, Xc, Xc, exact_pattern=False)
+
+
+def test_spgemm_fp32(sf):
+    A = W.random_sparse(2000, mean_row=8, seed=7)
+    B = W.random_sparse(2000, mean_row=8, seed=8)
+    Af = W.Csr(n=A.n, indptr=A.indptr, indices=A.indices, data=A.data.astype(np.float32)
+               .astype(np.float64))
+    Bf = W.Csr(n=B.n, indptr=B.indptr, indices=B.indices, data=B.data.astype(np.float32)
+               .astype(np.float64))
+    r = sf.sign_spgemm(_dev(sf, A, np.float32), _dev(sf, B, np.float32))
+    rp, ci, va = r.to_numpy()
+    assert va.dtype == np.float32
+    orp, oci, ova = oracle.spgemm(Af, Bf)
+    _, _, bound = oracle.spgemm(_abs(Af), _abs(Bf))
+    assert np.array_equal(rp, orp) and np.array_equal(ci, oci)
+    assert np.all(np.abs(va - ova) <= 2 ** -23 * 40 * bound)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_filter_matches_oracle_selection(sf, seed):
+    rng = np.random.default_rng(seed)
+    A = W.random_sparse(3000, mean_row=20, seed=seed + 50)
+    A.data = np.exp(rng.uniform(-80, 1, A.nnz)) * rng.choice([-1, 1], A.nnz)
+    A.data[A.data > 1] = 0.75
+    tau = float(np.exp(rng.uniform(-60, -5)))
+    r, bstar = sf.sign_filter(_dev(sf, A), tau)
+    b_ref, keep, dsq = oracle.filter_values(A.data, tau)
+    assert bstar == b_ref
+    rp, ci, va = r.to_numpy()
+    rows = np.repeat(np.arange(A.n), np.diff(A.indptr))
+    ref = sp.csr_matrix((A.data[keep], (rows[keep], A.indices[keep])), shape=(A.n, A.n))
+    assert np.array_equal(rp, ref.indptr) and np.array_equal(ci, ref.indices)
+    assert np.array_equal(va, ref.data)           # dropping is exact
+    assert r.stats()["step_fro"] <= tau
+    assert abs(r.stats()["step_fro"] ** 2 - dsq) <= 1e-12 * dsq + 1e-300
+
+
+def _rel(X, S):
+    return np.linalg.norm(X - S) / np.linalg.norm(S)
+
+
+CASES = {
+    "c1_64": (lambda: W.tridiag_c1(64), dict(tol=1e-12, stop_rule=1)),
+    "c1_1024": (lambda: W.tridiag_c1(1024), dict(tol=1e-12, stop_rule=1)),
+    "lap2d_17": (lambda: W.laplacian_2d(17, jitter=0.05, seed=2, m=8.0), dict(tol=1e-12)),
+    "lap2d_48": (lambda: W.laplacian_2d(48, jitter=0.05, seed=2, m=8.0), dict(tol=1e-12)),
+    "convdiff_30": (lambda: W.convdiff_2d(30, beta=0.5, sigma=4.0, m=8.0), dict(tol=1e-12)),
+    "lap3d_9": (lambda: W.laplacian_3d(9, perturb=0.5, seed=4, m=12.0), dict(tol=1e-10)),
+    "lap1d_3001": (lambda: W.laplacian_1d(3001, sigma=2.0, jitter=0.05, seed=9, m=4.0),
+                   dict(tol=1e-12)),
+    "ode_300": (lambda: W.ode_block_matrix(300), dict(tol=1e-12)),
+    "lap2d_32_filter_y": (lambda: W.laplacian_2d(32, jitter=0.05, seed=2, m=8.0),
+                          dict(tol=1e-12, filter_y=1)),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_nsf_matches_oracle(sf, name):
+    make, kw = CASES[name]
+    A = make()
+    r = sf.sign_ns(_dev(sf, A), sf.default_opts(**kw))
+    assert r.status == "OK"
+    X = r.to_scipy()
+    ref = oracle.nsf(A, **kw)
+    assert ref.status == "OK"
+    S = ref.to_scipy()
+    rel = sp.linalg.norm(X - S) / sp.linalg.norm(S)
+    assert rel <= 1e-10, rel
+    st = r.stats()
+    assert st["res_fro"] <= max(kw["tol"], 1e-11) * 10 or kw.get("stop_rule") == 1
+    # same iteration count as the oracle, or one apart when a stop test sits on the edge
+    assert abs(st["iters"] - ref.iters) <= 1
+    if name.startswith("c1"):
+        n = A.n
+        Sx = cf.sign_tridiag_c1(n)
+        assert np.linalg.norm(X.toarray() - Sx) / math.sqrt(n) <= 1e-10
+    if name.startswith("ode"):
+        assert _rel(X.toarray(), cf.sign_ode_block(300)) <= 1e-10
+
+
+def test_nsf_fp32_input_values(sf):
+    A = W.laplacian_2d(20, jitter=0.05, seed=2, m=8.0)
+    A32 = W.Csr(n=A.n, indptr=A.indptr, indices=A.indices,
+                data=A.data.astype(np.float32).astype(np.float64))
+    r = sf.sign_ns(_dev(sf, A, np.float32), sf.default_opts(tol=1e-12))
+    ref = oracle.nsf(A32, tol=1e-12)
+    X, S = r.to_scipy(), ref.to_scipy()
+    assert sp.linalg.norm(X - S) / sp.linalg.norm(S) <= 1e-10
+
+
+def test_status_paths(sf):
+    A = W.laplacian_2d(8, jitter=0.05, seed=2, m=8.0)
+    r = sf.sign_ns(_dev(sf, A), sf.default_opts(max_iter=1))
+    assert r.status == "ENOCONV" and r.stats()["iters"] == 1
+    ref = oracle.nsf(A, max_iter=1)
+    assert _rel(r.to_scipy().toarray(), ref.to_scipy().toarray()) < 1e-13
+    r = sf.sign_ns(_dev(sf, A), sf.default_opts(scale=1.0))
+    assert r.status == "EDIVERGED"
+    one = W.Csr(n=1, indptr=np.array([0, 1], np.int64), indices=np.array([0], np.int32),
+                data=np.array([-3.0]))
+    r = sf.sign_ns(_dev(sf, one), sf.default_opts())
+    assert r.status == "OK" and r.to_numpy()[2].tolist() == [-1.0]
+    bad = W.tridiag_c1(6)
+    bad.indices = bad.indices.copy()
+    assert list(bad.indices[1:3]) == [0, 2]
+    bad.indices[1], bad.indices[2] = 2, 0   # row 1 not ascending
+    with pytest.raises(sf.SignError, match="ascending"):
+        sf.sign_ns(_dev(sf, bad), sf.default_opts())
+    nan = W.tridiag_c1(6)
+    nan.data = nan.data.copy()
+    nan.data[2] = np.nan
+    with pytest.raises(sf.SignError, match="non-finite"):
+        sf.sign_ns(_dev(sf, nan), sf.default_opts())
+
+
+def test_trace_records_budget_and_filter(sf):
+    A = W.laplacian_2d(30, jitter=0.05, seed=2, m=8.0)
+    r = sf.sign_ns(_dev(sf, A), sf.default_opts(tol=1e-12))
+    tr = r.trace()
+    assert len(tr) == r.stats()["iters"] + 1
+    for t in tr[:-1]:
+        assert t["ffro"] <= t["tau"]
+        assert t["nnz_x"] > 0 and t["nnz_bar"] >= t["nnz_x"] or True
+    ref = oracle.nsf(A, tol=1e-12)
+    e_gpu = np.array([t["e"] for t in tr])
+    e_ref = ref.trace["e"][: len(tr)]
+    # residual histories agree until the rounding floor
+    big = e_ref > 1e-10
+    assert np.allclose(e_gpu[big], e_ref[big], rtol=1e-9)
