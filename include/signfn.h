@@ -105,6 +105,13 @@ typedef struct {
     double spgemm_bytes; /* algorithmic bytes of the numeric product kernels */
     int inner_steps;     /* sign_newton: filtered NS inversion steps in total */
     double comm_rel;     /* precision 1: ||XA - AX||_F / (||X||_F ||A||_F) before refinement */
+    /* the numeric product kernel configuration with the most device time */
+    int hot_tile;        /* LDS accumulator columns of that kernel */
+    int hot_threads;     /* its workgroup size */
+    int64_t hot_launches;/* its launches */
+    double hot_ms;       /* its device time (HIP events on the call's stream) */
+    double hot_bytes;    /* its algorithmic bytes */
+    int64_t hot_products;/* its multiply-adds */
 } sign_stats;
 
 /* One entry per computed residual, k = 0 .. iters. */

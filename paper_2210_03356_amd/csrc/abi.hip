@@ -221,6 +221,7 @@ int sign_ns(const sign_csr *A, const sign_opts *o, void *hip_stream, sign_result
         st.products = w.products;
         st.spgemm_ms = w.spgemm_ms;
         st.spgemm_bytes = w.spgemm_bytes;
+        w.hot_stats(st);
         st.seconds = now_s() - t_start;
         return finish(r, out, lo.status);
     });
@@ -269,6 +270,7 @@ int sign_spgemm(const sign_csr *A, const sign_csr *B, void *hip_stream, sign_res
         r->stats.products = w.products;
         r->stats.spgemm_ms = w.spgemm_ms;
         r->stats.spgemm_bytes = w.spgemm_bytes;
+        w.hot_stats(r->stats);
         r->stats.seconds = now_s() - t0;
         return finish(r, out, SIGN_OK);
     });

@@ -14,7 +14,7 @@ constexpr int kMidTile = 4096;
 Workspace::Workspace(Allocator *a, size_t staging_bytes) : al(a), s(a->stream) {
     for (DevBuf *b : {&lo, &span, &cap, &work, &capoff, &workoff, &tmp, &bins, &counts, &cursor,
                       &stage_col, &stage_val, &rs1, &rs2, &rs3, &rs4, &icnt, &hist, &tau,
-                      &bstar, &seg, &red, &flag, &zero_b})
+                      &bstar, &seg, &red, &flag, &zero_b, &cstat})
         b->bind(a);
     if (staging_bytes == 0) {
         size_t fr = 0, tot = 0;
@@ -25,14 +25,25 @@ Workspace::Workspace(Allocator *a, size_t staging_bytes) : al(a), s(a->stream) {
         staging_bytes = std::max<size_t>(size_t(256) << 20, fr / 4);
     }
     staging_limit = staging_bytes;
-    SFN_HIP(hipEventCreate(&ev0));
-    SFN_HIP(hipEventCreate(&ev1));
+    for (auto &e : ev) SFN_HIP(hipEventCreate(&e));
 }
 
 Workspace::~Workspace() {
     (void)hipStreamSynchronize(s);
-    if (ev0) (void)hipEventDestroy(ev0);
-    if (ev1) (void)hipEventDestroy(ev1);
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+}
+
+void Workspace::hot_stats(sign_stats &st) const {
+    int h = 1;
+    for (int c = 1; c < 4; ++c)
+        if (cls[c].ms > cls[h].ms) h = c;
+    st.hot_tile = bin_config(h, value_bytes).tile;
+    st.hot_threads = bin_config(h, value_bytes).threads;
+    st.hot_launches = cls[h].launches;
+    st.hot_ms = cls[h].ms;
+    st.hot_bytes = cls[h].bytes;
+    st.hot_products = cls[h].products;
 }
 
 double Workspace::sum_rows(const DevBuf &rows, int64_t n) {
@@ -114,6 +125,8 @@ void product(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D,
     w.cursor.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(a_extent, 1));
     w.bins.ensure(sizeof(int32_t) * 4 * (size_t)std::max<int64_t>(n, 1));
     w.counts.ensure(sizeof(int32_t) * 4);
+    w.cstat.ensure(sizeof(int64_t) * 32);
+    w.value_bytes = (int)sizeof(V);
 
     int64_t running = 0;
     for (size_t b = 0; b + 1 < cuts.size(); ++b) {
@@ -123,29 +136,54 @@ void product(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D,
         w.stage_col.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(bcap, 1));
         w.stage_val.ensure(sizeof(V) * (size_t)std::max<int64_t>(bcap, 1));
         SFN_HIP(hipMemsetAsync(w.counts.get(), 0, sizeof(int32_t) * 4, s));
+        SFN_HIP(hipMemsetAsync(w.cstat.get(), 0, sizeof(int64_t) * 32, s));
         launch_bin_rows(w.span.as<int32_t>(), w.work.as<int64_t>(), r0, r1, kSmallTile, kMidTile,
                         w.bins.as<int32_t>(), n, w.counts.as<int32_t>(), C.lenp(),
                         sq_prod ? sq_prod->as<double>() : nullptr,
-                        sq_out ? sq_out->as<double>() : nullptr, s);
+                        sq_out ? sq_out->as<double>() : nullptr, A.lenp(),
+                        D ? D->lenp() : nullptr, w.cstat.as<int64_t>(), s);
         int32_t cnt[4];
         SFN_HIP(hipMemcpyAsync(cnt, w.counts.get(), sizeof(cnt), hipMemcpyDeviceToHost, s));
         SFN_HIP(hipStreamSynchronize(s));
-        SFN_HIP(hipEventRecord(w.ev0, s));
-        for (int cls = 3; cls >= 1; --cls)
+        SFN_HIP(hipEventRecord(w.ev[0], s));
+        for (int cls = 3; cls >= 1; --cls) {
             launch_spgemm<V>(cls, w.bins.as<int32_t>() + (int64_t)cls * n, cnt[cls], A.view(),
                              B.view(), Dv, coef, dcoef, diag, w.lo.as<int32_t>(),
                              w.span.as<int32_t>(), base, w.capoff.as<int64_t>(),
                              w.stage_col.as<int32_t>(), w.stage_val.as<V>(), C.lenp(),
                              w.cursor.as<int32_t>(), sq_prod ? sq_prod->as<double>() : nullptr,
-                             sq_out ? sq_out->as<double>() : nullptr, s);
-        SFN_HIP(hipEventRecord(w.ev1, s));
+                             sq_out ? sq_out->as<double>() : nullptr,
+                             w.cstat.as<int64_t>() + cls * 8 + 4, s);
+            SFN_HIP(hipEventRecord(w.ev[4 - cls], s));
+        }
         // compact row starts of this batch, continuing from the previous batches
         launch_exclusive_scan_i32(C.lenp() + r0, r1 - r0, C.begp() + r0,
                                   w.tmp.as<int64_t>(), running, s);
+        int64_t cs[32];
+        SFN_HIP(hipMemcpyAsync(cs, w.cstat.get(), sizeof(cs), hipMemcpyDeviceToHost, s));
         const int64_t end = read_scalar(C.begp() + r1, s);
-        float ms = 0.f;
-        SFN_HIP(hipEventElapsedTime(&ms, w.ev0, w.ev1));
-        w.spgemm_ms += ms;
+        for (int cls = 3; cls >= 1; --cls) {
+            float ms = 0.f;
+            SFN_HIP(hipEventElapsedTime(&ms, w.ev[3 - cls], w.ev[4 - cls]));
+            w.spgemm_ms += ms;
+            if (cnt[cls] <= 0) continue;
+            Workspace::ClassStat &c = w.cls[cls];
+            c.launches += 1;
+            c.rows += cnt[cls];
+            c.products += cs[cls * 8 + 1];
+            c.a_nnz += cs[cls * 8 + 2];
+            c.d_nnz += cs[cls * 8 + 3];
+            c.out += cs[cls * 8 + 4];
+            c.ms += ms;
+            // algorithmic bytes: one B entry per product, each A entry with its
+            // B-row descriptor, the D rows, the stored output, per-row data
+            const double eb = (double)(sizeof(int32_t) + sizeof(V));
+            const double bytes = eb * (double)cs[cls * 8 + 1] + (eb + 12.0) * (double)cs[cls * 8 + 2] +
+                                 eb * (double)cs[cls * 8 + 3] + eb * (double)cs[cls * 8 + 4] +
+                                 40.0 * (double)cnt[cls];
+            c.bytes += bytes;
+            w.spgemm_bytes += bytes;
+        }
         C.ensure_entries(end, running);
         launch_copy_rows<V>(w.capoff.as<int64_t>(), base, C.lenp(),
                             w.stage_col.as<int32_t>(), w.stage_val.as<V>(), r0, r1,
@@ -153,12 +191,6 @@ void product(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D,
         running = end;
     }
     C.nnz = running;
-    // algorithmic bytes of the numeric kernels: one B entry per product, the
-    // A and D rows with their B-row descriptors, the stored output, row data
-    const double eb = (double)entry;
-    const double a_nnz = (double)A.nnz, d_nnz = D ? (double)D->nnz : 0.0;
-    w.spgemm_bytes += eb * (double)tot[1] + (eb + 12.0) * a_nnz + eb * d_nnz +
-                      eb * (double)running + 40.0 * (double)n;
 }
 
 template <typename V, typename Vo>

@@ -16,11 +16,20 @@ struct Workspace {
     size_t staging_limit;  // bytes of gapped product output per batch
     DevBuf lo, span, cap, work, capoff, workoff, tmp, bins, counts, cursor, stage_col, stage_val;
     DevBuf rs1, rs2, rs3, rs4, icnt, hist, tau, bstar, seg, red, flag, zero_b;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    // accumulated product statistics
+    DevBuf cstat;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // accumulated product statistics, in total and per row class (kernel tile)
+    struct ClassStat {
+        int64_t launches = 0, rows = 0, products = 0, a_nnz = 0, d_nnz = 0, out = 0;
+        double ms = 0.0, bytes = 0.0;
+    };
+    ClassStat cls[4];
+    int value_bytes = 8;
     int64_t products = 0;
     double spgemm_ms = 0.0;
     double spgemm_bytes = 0.0;
+    // fill the hot-kernel fields (class with the most device time) of s
+    void hot_stats(sign_stats &s) const;
     explicit Workspace(Allocator *a, size_t staging_bytes);
     ~Workspace();
     // ||rows||: deterministic sum of a per-row double array over [0, n)

@@ -286,9 +286,12 @@ constexpr int kBinThreads = 256;
 __global__ __launch_bounds__(kBinThreads) void k_bin_rows(
     const int32_t *span, const int64_t *work, int64_t r0, int64_t r1, int small_tile,
     int mid_tile, int32_t *bins, int64_t bin_stride, int32_t *counts, int32_t *out_len,
-    double *sq_prod, double *sq_out) {
+    double *sq_prod, double *sq_out, const int32_t *a_len, const int32_t *d_len,
+    int64_t *cstat) {
     __shared__ int wc[kBinThreads / kWave][4];
     __shared__ int base[4];
+    __shared__ unsigned long long bsum[4][3];
+    if (threadIdx.x < 12) bsum[threadIdx.x / 3][threadIdx.x % 3] = 0ull;
     const int64_t i = r0 + (int64_t)blockIdx.x * kBinThreads + threadIdx.x;
     int cls = -1;
     if (i < r1) {
@@ -324,6 +327,14 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_rows(
         int off = base[cls] + rank;
         for (int q = 0; q < w; ++q) off += wc[q][cls];
         bins[(int64_t)cls * bin_stride + off] = (int32_t)i;
+        atomicAdd(&bsum[cls][0], (unsigned long long)work[i]);
+        atomicAdd(&bsum[cls][1], (unsigned long long)a_len[i]);
+        if (d_len) atomicAdd(&bsum[cls][2], (unsigned long long)d_len[i]);
+    }
+    __syncthreads();
+    if (cstat && threadIdx.x >= 3 && threadIdx.x < 12) {
+        const int c = threadIdx.x / 3, f = threadIdx.x % 3;
+        if (bsum[c][f]) atomicAdd((unsigned long long *)&cstat[c * 8 + 1 + f], bsum[c][f]);
     }
 }
 
@@ -336,7 +347,7 @@ __global__ __launch_bounds__(NT) void k_spgemm(
     V dcoef, V diag, const int32_t *__restrict__ row_lo, const int32_t *__restrict__ row_span,
     const int64_t *__restrict__ off, int64_t base, int32_t *__restrict__ out_col,
     V *__restrict__ out_val, int32_t *__restrict__ out_len, int32_t *__restrict__ cursor,
-    double *__restrict__ sq_prod, double *__restrict__ sq_out) {
+    double *__restrict__ sq_prod, double *__restrict__ sq_out, int64_t *__restrict__ out_count) {
     constexpr int NW = NT / kWave;
     constexpr int REG = T / NW;  // LDS slots owned by each wave in the epilogue
     static_assert(T % (NW * kWave) == 0, "tile must split evenly over the waves");
@@ -467,6 +478,7 @@ __global__ __launch_bounds__(NT) void k_spgemm(
         out_len[i] = written;
         if (sq_prod) sq_prod[i] = a;
         if (sq_out) sq_out[i] = b;
+        if (out_count) atomicAdd((unsigned long long *)out_count, (unsigned long long)written);
     }
 }
 
@@ -690,11 +702,12 @@ template void launch_plan<float>(MatView<float>, MatView<float>, MatView<float>,
 void launch_bin_rows(const int32_t *span, const int64_t *work, int64_t r0, int64_t r1,
                      int small_tile, int mid_tile, int32_t *bins, int64_t bin_stride,
                      int32_t *counts, int32_t *out_len, double *sq_prod, double *sq_out,
+                     const int32_t *a_len, const int32_t *d_len, int64_t *cstat,
                      hipStream_t s) {
     if (r1 <= r0) return;
     k_bin_rows<<<blocks_for(r1 - r0, kBinThreads), kBinThreads, 0, s>>>(
         span, work, r0, r1, small_tile, mid_tile, bins, bin_stride, counts, out_len, sq_prod,
-        sq_out);
+        sq_out, a_len, d_len, cstat);
 }
 
 BinCfg bin_config(int cls, int value_bytes) {
@@ -710,35 +723,37 @@ void launch_spgemm(int cls, const int32_t *rows, int nrows, MatView<V> A, MatVie
                    MatView<V> D, double coef, double dcoef, double diag, const int32_t *lo,
                    const int32_t *span, int64_t base, const int64_t *off, int32_t *out_col,
                    V *out_val, int32_t *out_len, int32_t *cursor, double *sq_prod,
-                   double *sq_out, hipStream_t s) {
+                   double *sq_out, int64_t *out_count, hipStream_t s) {
     if (nrows <= 0) return;
     const V c = (V)coef, d = (V)diag, dc = (V)dcoef;
     switch (cls) {
         case 1:
             k_spgemm<V, 512, 64><<<nrows, 64, 0, s>>>(rows, A, B, D, c, dc, d, lo, span, off, base,
                                                       out_col, out_val, out_len, cursor, sq_prod,
-                                                      sq_out);
+                                                      sq_out, out_count);
             break;
         case 2:
             k_spgemm<V, 4096, 256><<<nrows, 256, 0, s>>>(rows, A, B, D, c, dc, d, lo, span, off, base,
                                                          out_col, out_val, out_len, cursor,
-                                                         sq_prod, sq_out);
+                                                         sq_prod, sq_out, out_count);
             break;
         default:
             k_spgemm<V, (sizeof(V) == 8 ? 8192 : 16384), 512><<<nrows, 512, 0, s>>>(
                 rows, A, B, D, c, dc, d, lo, span, off, base, out_col, out_val, out_len, cursor,
-                sq_prod, sq_out);
+                sq_prod, sq_out, out_count);
             break;
     }
 }
 template void launch_spgemm<double>(int, const int32_t *, int, MatView<double>, MatView<double>,
                                     MatView<double>, double, double, double, const int32_t *,
                                     const int32_t *, int64_t, const int64_t *, int32_t *, double *,
-                                    int32_t *, int32_t *, double *, double *, hipStream_t);
+                                    int32_t *, int32_t *, double *, double *, int64_t *,
+                                    hipStream_t);
 template void launch_spgemm<float>(int, const int32_t *, int, MatView<float>, MatView<float>,
                                    MatView<float>, double, double, double, const int32_t *,
                                    const int32_t *, int64_t, const int64_t *, int32_t *, float *,
-                                   int32_t *, int32_t *, double *, double *, hipStream_t);
+                                   int32_t *, int32_t *, double *, double *, int64_t *,
+                                   hipStream_t);
 
 template <typename V>
 void launch_copy_rows(const int64_t *src_off, int64_t src_base, const int32_t *len,

@@ -66,21 +66,25 @@ void launch_plan(MatView<V> A, MatView<V> B, MatView<V> D, int diag, int64_t r0,
 
 // Row classes: 0 empty, 1..3 tiles.  Writes row lists per class (bins[c] holds
 // up to r1-r0 rows), counts into counts[4] (device), and len=0 for empty rows.
+// cstat (optional): per class c, cstat[8c+1] += products, [8c+2] += nnz of the
+// A rows, [8c+3] += nnz of the D rows (d_len may be null).
 void launch_bin_rows(const int32_t *span, const int64_t *work, int64_t r0, int64_t r1,
                      int small_tile, int mid_tile, int32_t *bins, int64_t bin_stride,
                      int32_t *counts, int32_t *out_len, double *sq_prod, double *sq_out,
+                     const int32_t *a_len, const int32_t *d_len, int64_t *cstat,
                      hipStream_t s);
 
 // Numeric product for the rows listed in `rows` (class cfg).  Row i writes
 // at out_col/out_val[off[i] - base .. ), out_len[i], sq_prod[i] (sum of squares
 // of coef*A*B) and sq_out[i] (sum of squares of the stored output), when the
 // latter two pointers are non-null.  cursor: int32 scratch per nonzero of A.
+// out_count (optional) accumulates the number of stored entries.
 template <typename V>
 void launch_spgemm(int cls, const int32_t *rows, int nrows, MatView<V> A, MatView<V> B,
                    MatView<V> D, double coef, double dcoef, double diag, const int32_t *lo,
                    const int32_t *span, int64_t base, const int64_t *off, int32_t *out_col,
                    V *out_val, int32_t *out_len, int32_t *cursor, double *sq_prod,
-                   double *sq_out, hipStream_t s);
+                   double *sq_out, int64_t *out_count, hipStream_t s);
 BinCfg bin_config(int cls, int value_bytes);
 
 // Copy rows [r0, r1) from a gapped layout (row i at src_off[i] - src_base)
