@@ -176,6 +176,11 @@ def main():
     t1 = time.perf_counter()
     ms_per_step = 1e3 * (t1 - t0) / max(args.steps, 1)
     st = res.stats()
+    for k, it in enumerate(res.trace()):
+        print(f"#   k={k + 1} {'fp32' if it['fp32'] else 'fp64'} e={it['e']:.3e} "
+              f"nnz_x/row={it['nnz_x'] / A.n:.0f} nnz_r/row={it['nnz_r'] / A.n:.0f} "
+              f"nnz_bar/row={it['nnz_bar'] / A.n:.0f} tau={it['tau']:.2e} b*={it['bstar']} "
+              f"ms={it['ms']:.1f}", file=sys.stderr, flush=True)
     tile = st["hot_tile"]
     launches = max(agg["hot_launches"], 1)
     avg_ms = agg["hot_ms"] / launches
@@ -239,7 +244,7 @@ def main():
         if agg["spgemm_ms"] > 0 else None,
         "roofline": {
             "bound": "hbm",
-            "kernel": f"k_spgemm<{'double' if args.precision == 0 else 'float'},{tile},"
+            "kernel": f"k_spgemm<{'float' if st['hot_fp32'] else 'double'},{tile},"
                       f"{st['hot_threads']}>",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,

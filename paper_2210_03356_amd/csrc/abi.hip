@@ -8,21 +8,19 @@ using namespace sfn;
 
 namespace {
 
-thread_local std::string t_err;
-
 template <typename F>
 int guarded(F &&f) {
     try {
-        t_err.clear();
+        set_last_error("");
         return f();
     } catch (const Error &e) {
-        t_err = e.what();
+        set_last_error(e.what());
         return e.status;
     } catch (const std::bad_alloc &) {
-        t_err = "host allocation failed";
+        set_last_error("host allocation failed");
         return SIGN_ENOMEM;
     } catch (const std::exception &e) {
-        t_err = e.what();
+        set_last_error(e.what());
         return SIGN_EDEVICE;
     }
 }
@@ -113,6 +111,73 @@ void convert(Workspace &w, const DMat<Vi> &In, DMat<Vo> &Out) {
     Out.nnz = In.nnz;
 }
 
+// Mixed precision (precision 1):
+//  1. the NSF loop in FP32 values / FP32 accumulation (FP64 norms, budget and
+//     scaling) to its rounding floor, tol32 = max(tol, 32 u32 sqrt(n)), with
+//     the budget c_fixed*tol32 that matches FP32 resolution;
+//  2. one FP64 Newton-Schulz step (removes the error part that commutes with
+//     the sign);
+//  3. commutator refinement: the error part E that anticommutes with S is a
+//     neutral direction of every Newton-type sign iteration, but [A, X] =
+//     S(|A|E + E|A|), so X <- X - w X [A, X] with w = 1/(2 mean|lambda|)
+//     contracts it by about (kappa-1)/(kappa+1) per sweep;
+//  4. FP64 Newton-Schulz steps until e <= tol.
+LoopOut mixed_precision(Workspace &w, const sign_csr *A, double c, const sign_opts &o,
+                        DMat<double> &X, std::vector<sign_iter_stats> &trace, double &comm_rel) {
+    const int64_t n = A->n;
+    DMat<float> X32;
+    X32.bind(w.al);
+    load_scaled<float>(w, A, 1.0 / c, X32);
+    LoopParams p32{o.tol, o.c_fixed, o.switch_res, 0, o.max_iter, o.filter_y, 1};
+    p32.tol = std::max(o.tol, 32.0 * 5.960464477539063e-08 * std::sqrt((double)n));
+    const LoopOut l32 = nsf_loop<float>(w, X32, p32, trace);
+    convert<float, double>(w, X32, X);
+    X32 = DMat<float>();
+    if (l32.status == SIGN_EDIVERGED) return l32;
+    // polishing and refinement keep the fixed FP64 budget c_fixed*tol: the
+    // FP32 phase ends below the switch residual, and the eq. 1.18 budget there
+    // (proportional to e^2) would stop filtering altogether
+    LoopParams p64{o.tol, o.c_fixed, 0.0, 0, 0, o.filter_y, 0};
+    int iters = l32.iters;
+    LoopOut lo;
+    if (o.polish_steps > 0) {
+        p64.max_iter = 1;
+        lo = nsf_loop<double>(w, X, p64, trace);
+        iters += lo.iters;
+    }
+    if (o.refine_steps > 0) {
+        DMat<double> As, P, Cm, Xb, Xn;
+        for (DMat<double> *m : {&As, &P, &Cm, &Xb, &Xn}) m->bind(w.al);
+        load_scaled<double>(w, A, 1.0 / c, As);
+        row_sumsq(w, As, w.rs3);
+        const double af = std::sqrt(w.sum_rows(w.rs3, n));
+        for (int sweep = 0; sweep < o.refine_steps; ++sweep) {
+            product<double>(w, As, X, nullptr, 1.0, 0.0, 0.0, P, nullptr, nullptr);
+            // C = A X - X A
+            product<double>(w, X, As, &P, -1.0, 1.0, 0.0, Cm, nullptr, &w.rs1);
+            const double cn = std::sqrt(w.sum_rows(w.rs1, n));
+            row_sumsq(w, X, w.rs3);
+            const double xf = std::sqrt(w.sum_rows(w.rs3, n));
+            w.rs2.ensure(sizeof(double) * n);
+            launch_diag<double>(P.view(), w.rs2.as<double>(), w.s);
+            const double mean_abs = w.sum_rows(w.rs2, n) / (double)n;  // trace(|A|)/n
+            if (sweep == 0) comm_rel = cn / (xf * af);
+            if (!(mean_abs > 0.0)) break;
+            // estimated relative error of X: ||E|| ~ ||C|| / (2 mean|lambda|)
+            if (cn / (2.0 * mean_abs * xf) < 1e-11) break;
+            const double omega = 1.0 / (2.0 * mean_abs);
+            product<double>(w, X, Cm, &X, -omega, 1.0, 0.0, Xb, nullptr, nullptr);
+            filter<double, double>(w, Xb, o.c_fixed * o.tol, Xn, nullptr, nullptr);
+            std::swap(X, Xn);
+        }
+    }
+    p64.max_iter = std::max(1, o.polish_steps - 1);
+    const LoopOut l2 = nsf_loop<double>(w, X, p64, trace);
+    LoopOut out = l2;
+    out.iters = iters + l2.iters;
+    return out;
+}
+
 Allocator make_alloc(const sign_opts *o, hipStream_t s) {
     Allocator a;
     if (o && o->alloc) {
@@ -166,7 +231,7 @@ void sign_opts_default(sign_opts *o) {
     o->staging_bytes = 0;
 }
 
-const char *sign_last_error(void) { return t_err.c_str(); }
+const char *sign_last_error(void) { return last_error(); }
 
 int sign_ns(const sign_csr *A, const sign_opts *o, void *hip_stream, sign_result **out) {
     if (out) *out = nullptr;
@@ -178,34 +243,19 @@ int sign_ns(const sign_csr *A, const sign_opts *o, void *hip_stream, sign_result
         Allocator al = make_alloc(o, s);
         Workspace w(&al, o->staging_bytes);
         validate(w, A);
-        const int64_t n = A->n;
         const double c = o->scale > 0.0 ? o->scale : norm_inf(w, A);
         if (!(c > 0.0) || !std::isfinite(c)) throw Error(SIGN_EINVAL, "scale is zero (A = 0?)");
         std::vector<sign_iter_stats> trace;
         LoopParams p{o->tol, o->c_fixed, o->switch_res, o->stop_rule, o->max_iter, o->filter_y, 0};
         LoopOut lo;
+        double comm_rel = 0.0;
         DMat<double> X;
         X.bind(&al);
         if (o->precision == 0) {
             load_scaled<double>(w, A, 1.0 / c, X);
             lo = nsf_loop<double>(w, X, p, trace);
         } else {
-            // FP32 phase to its rounding floor, then FP64 polishing steps
-            DMat<float> X32;
-            X32.bind(&al);
-            load_scaled<float>(w, A, 1.0 / c, X32);
-            LoopParams p32 = p;
-            p32.fp32 = 1;
-            p32.tol = std::max(o->tol, 32.0 * 5.960464477539063e-08 * std::sqrt((double)n));
-            p32.stop_rule = 0;
-            const LoopOut l32 = nsf_loop<float>(w, X32, p32, trace);
-            convert<float, double>(w, X32, X);
-            X32 = DMat<float>();
-            LoopParams p64 = p;
-            p64.max_iter = o->polish_steps;
-            lo = nsf_loop<double>(w, X, p64, trace);
-            lo.iters += l32.iters;
-            if (l32.status == SIGN_EDIVERGED) lo.status = SIGN_EDIVERGED;
+            lo = mixed_precision(w, A, c, *o, X, trace, comm_rel);
         }
         SFN_HIP(hipStreamSynchronize(s));
         sign_result *r = make_result<double>(al, X);
@@ -221,6 +271,7 @@ int sign_ns(const sign_csr *A, const sign_opts *o, void *hip_stream, sign_result
         st.products = w.products;
         st.spgemm_ms = w.spgemm_ms;
         st.spgemm_bytes = w.spgemm_bytes;
+        st.comm_rel = comm_rel;
         w.hot_stats(st);
         st.seconds = now_s() - t_start;
         return finish(r, out, lo.status);
@@ -230,9 +281,41 @@ int sign_ns(const sign_csr *A, const sign_opts *o, void *hip_stream, sign_result
 int sign_newton(const sign_csr *A, const sign_opts *o, void *hip_stream, sign_result **out) {
     if (out) *out = nullptr;
     return guarded([&]() -> int {
-        (void)A; (void)o; (void)hip_stream;
-        throw Error(SIGN_EINVAL, "sign_newton: not available in this build");
-        return SIGN_EINVAL;
+        if (!out) throw Error(SIGN_EINVAL, "out is NULL");
+        check_opts(o);
+        if (o->precision != 0) throw Error(SIGN_EINVAL, "sign_newton supports precision 0 only");
+        const double t_start = now_s();
+        hipStream_t s = (hipStream_t)hip_stream;
+        Allocator al = make_alloc(o, s);
+        Workspace w(&al, o->staging_bytes);
+        validate(w, A);
+        // the paper starts Newton from X_1 = A; scale > 0 overrides
+        const double c = o->scale > 0.0 ? o->scale : 1.0;
+        std::vector<sign_iter_stats> trace;
+        LoopParams p{o->tol, o->c_fixed, o->switch_res, 0, o->max_iter, 0, 0};
+        DMat<double> X;
+        X.bind(&al);
+        load_scaled<double>(w, A, 1.0 / c, X);
+        int inner = 0;
+        const LoopOut lo = nmf_loop(w, X, p, trace, inner);
+        SFN_HIP(hipStreamSynchronize(s));
+        sign_result *r = make_result<double>(al, X);
+        r->trace = std::move(trace);
+        sign_stats &st = r->stats;
+        st.status = lo.status;
+        st.iters = lo.iters;
+        st.stagnated = lo.stagnated;
+        st.scale = c;
+        st.res_fro = lo.e;
+        st.step_fro = lo.d;
+        st.nnz = r->nnz;
+        st.products = w.products;
+        st.spgemm_ms = w.spgemm_ms;
+        st.spgemm_bytes = w.spgemm_bytes;
+        st.inner_steps = inner;
+        w.hot_stats(st);
+        st.seconds = now_s() - t_start;
+        return finish(r, out, lo.status);
     });
 }
 

@@ -35,15 +35,18 @@ Workspace::~Workspace() {
 }
 
 void Workspace::hot_stats(sign_stats &st) const {
-    int h = 1;
-    for (int c = 1; c < 4; ++c)
-        if (cls[c].ms > cls[h].ms) h = c;
-    st.hot_tile = bin_config(h, value_bytes).tile;
-    st.hot_threads = bin_config(h, value_bytes).threads;
-    st.hot_launches = cls[h].launches;
-    st.hot_ms = cls[h].ms;
-    st.hot_bytes = cls[h].bytes;
-    st.hot_products = cls[h].products;
+    int hv = 0, h = 1;
+    for (int v = 0; v < 2; ++v)
+        for (int c = 1; c < 4; ++c)
+            if (cls[v][c].ms > cls[hv][h].ms) { hv = v; h = c; }
+    const ClassStat &c = cls[hv][h];
+    st.hot_tile = bin_config(h, hv ? 4 : 8).tile;
+    st.hot_threads = bin_config(h, hv ? 4 : 8).threads;
+    st.hot_fp32 = hv;
+    st.hot_launches = c.launches;
+    st.hot_ms = c.ms;
+    st.hot_bytes = c.bytes;
+    st.hot_products = c.products;
 }
 
 double Workspace::sum_rows(const DevBuf &rows, int64_t n) {
@@ -84,7 +87,8 @@ void product(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D,
     MatView<V> Dv;
     if (D) Dv = D->view();
     launch_plan<V>(A.view(), B.view(), Dv, diag != 0.0, 0, n, w.lo.as<int32_t>(),
-                   w.span.as<int32_t>(), w.cap.as<int64_t>(), w.work.as<int64_t>(), s);
+                   w.span.as<int32_t>(), w.cap.as<int64_t>(), w.work.as<int64_t>(), w.row_skip,
+                   s);
     launch_exclusive_scan_i64(w.cap.as<int64_t>(), n, w.capoff.as<int64_t>(), w.tmp.as<int64_t>(),
                               0, s);
     launch_exclusive_scan_i64(w.work.as<int64_t>(), n, w.workoff.as<int64_t>(),
@@ -126,7 +130,6 @@ void product(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D,
     w.bins.ensure(sizeof(int32_t) * 4 * (size_t)std::max<int64_t>(n, 1));
     w.counts.ensure(sizeof(int32_t) * 4);
     w.cstat.ensure(sizeof(int64_t) * 32);
-    w.value_bytes = (int)sizeof(V);
 
     int64_t running = 0;
     for (size_t b = 0; b + 1 < cuts.size(); ++b) {
@@ -167,7 +170,7 @@ void product(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D,
             SFN_HIP(hipEventElapsedTime(&ms, w.ev[3 - cls], w.ev[4 - cls]));
             w.spgemm_ms += ms;
             if (cnt[cls] <= 0) continue;
-            Workspace::ClassStat &c = w.cls[cls];
+            Workspace::ClassStat &c = w.cls[sizeof(V) == 4 ? 1 : 0][cls];
             c.launches += 1;
             c.rows += cnt[cls];
             c.products += cs[cls * 8 + 1];
@@ -228,6 +231,53 @@ int filter(Workspace &w, const DMat<V> &In, double tau, DMat<Vo> &Out, DevBuf *s
                                Out.colp(), Out.valp(), s);
     Out.nnz = total;
     return bstar;
+}
+
+void filter_seg(Workspace &w, const DMat<double> &In, const std::vector<int64_t> &seg_h,
+                const int64_t *seg_d, const int32_t *row_seg, const std::vector<double> &tau_h,
+                DMat<double> &Out, DevBuf *sq_keep, DevBuf *sq_drop, std::vector<int> &bstar_h) {
+    const int64_t n = In.n;
+    const int nseg = (int)tau_h.size();
+    hipStream_t s = w.s;
+    Out.ensure_rows(n);
+    w.hist.ensure(sizeof(uint64_t) * kBuckets * nseg);
+    w.tau.ensure(sizeof(double) * nseg);
+    w.bstar.ensure(sizeof(int) * nseg);
+    w.tmp.ensure(sizeof(int64_t) * scan_tmp_elems(n));
+    if (sq_keep) sq_keep->ensure(sizeof(double) * n);
+    if (sq_drop) sq_drop->ensure(sizeof(double) * n);
+    int64_t maxrows = 0;
+    for (int q = 0; q < nseg; ++q) maxrows = std::max(maxrows, seg_h[q + 1] - seg_h[q]);
+    SFN_HIP(hipMemcpyAsync(w.tau.get(), tau_h.data(), sizeof(double) * nseg,
+                           hipMemcpyHostToDevice, s));
+    SFN_HIP(hipMemsetAsync(w.hist.get(), 0, sizeof(uint64_t) * kBuckets * nseg, s));
+    launch_histogram<double>(In.view(), seg_d, nseg, maxrows, w.hist.as<uint64_t>(), s);
+    launch_select(w.hist.as<uint64_t>(), w.tau.as<double>(), nseg, w.bstar.as<int>(), s);
+    launch_count_keep<double>(In.view(), row_seg, w.bstar.as<int>(), Out.lenp(),
+                              sq_keep ? sq_keep->as<double>() : nullptr,
+                              sq_drop ? sq_drop->as<double>() : nullptr, s);
+    launch_exclusive_scan_i32(Out.lenp(), n, Out.begp(), w.tmp.as<int64_t>(), 0, s);
+    int64_t total;
+    bstar_h.resize(nseg);
+    SFN_HIP(hipMemcpyAsync(&total, Out.begp() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SFN_HIP(hipMemcpyAsync(bstar_h.data(), w.bstar.get(), sizeof(int) * nseg,
+                           hipMemcpyDeviceToHost, s));
+    SFN_HIP(hipStreamSynchronize(s));
+    Out.ensure_entries(total);
+    launch_scatter_keep<double, double>(In.view(), row_seg, w.bstar.as<int>(), Out.begp(),
+                                        Out.colp(), Out.valp(), s);
+    Out.nnz = total;
+}
+
+std::vector<double> seg_sums(Workspace &w, const DevBuf &rows, const int64_t *seg_d, int nseg) {
+    std::vector<double> h(nseg);
+    if (nseg == 0) return h;
+    w.red.ensure(sizeof(double) * nseg);
+    launch_seg_sum(rows.as<double>(), seg_d, nseg, w.red.as<double>(), w.s);
+    SFN_HIP(hipMemcpyAsync(h.data(), w.red.get(), sizeof(double) * nseg, hipMemcpyDeviceToHost,
+                           w.s));
+    SFN_HIP(hipStreamSynchronize(w.s));
+    return h;
 }
 
 template <typename V>
@@ -310,6 +360,137 @@ LoopOut nsf_loop(Workspace &w, DMat<V> &X, const LoopParams &p,
         std::swap(X, Xn);
         xf = xf_new;
         d_prev = d;
+        out.d = d;
+    }
+    return out;
+}
+
+void transpose(Workspace &w, const DMat<double> &X, DMat<double> &Out) {
+    const int64_t n = X.n;
+    hipStream_t s = w.s;
+    Out.ensure_rows(n);
+    Out.ensure_entries(X.nnz);
+    w.icnt.ensure(sizeof(int32_t) * std::max<int64_t>(n, 1));
+    w.tmp.ensure(sizeof(int64_t) * scan_tmp_elems(n));
+    w.flag.ensure(sizeof(int));
+    SFN_HIP(hipMemsetAsync(w.icnt.get(), 0, sizeof(int32_t) * n, s));
+    SFN_HIP(hipMemsetAsync(w.flag.get(), 0, sizeof(int), s));
+    launch_transpose_count<double>(X.view(), w.icnt.as<int32_t>(), s);
+    launch_exclusive_scan_i32(w.icnt.as<int32_t>(), n, Out.begp(), w.tmp.as<int64_t>(), 0, s);
+    SFN_HIP(hipMemcpyAsync(Out.lenp(), w.icnt.get(), sizeof(int32_t) * n, hipMemcpyDeviceToDevice,
+                           s));
+    SFN_HIP(hipMemsetAsync(w.icnt.get(), 0, sizeof(int32_t) * n, s));
+    launch_transpose_fill<double>(X.view(), Out.begp(), w.icnt.as<int32_t>(), Out.colp(),
+                                  Out.valp(), s);
+    launch_sort_rows<double>(Out.begp(), Out.colp(), Out.valp(), n, w.flag.as<int>(), s);
+    if (read_scalar(w.flag.as<int>(), s))
+        throw Error(SIGN_EINVAL, "transpose: a row is longer than " +
+                                     std::to_string(sort_rows_max()) + " entries");
+    Out.nnz = X.nnz;
+}
+
+namespace {
+// ||X||_1 * ||X||_inf of a compact FP64 matrix
+double norm_one_inf(Workspace &w, const DMat<double> &X) {
+    const int64_t n = X.n;
+    w.rs4.ensure(sizeof(double) * n);
+    SFN_HIP(hipMemsetAsync(w.rs4.get(), 0, sizeof(double) * n, w.s));
+    launch_col_abs_sum<double>(X.view(), w.rs4.as<double>(), w.s);
+    const double one = w.max_rows(w.rs4, n);
+    launch_row_abs_sum(X.begp(), X.valp(), 0, n, w.rs4.as<double>(), w.s);
+    const double inf = w.max_rows(w.rs4, n);
+    return one * inf;
+}
+}  // namespace
+
+LoopOut nmf_loop(Workspace &w, DMat<double> &X, const LoopParams &p,
+                 std::vector<sign_iter_stats> &trace, int &inner_steps) {
+    const int64_t n = X.n;
+    DMat<double> I, R, Z, T, Zb, Xb, Xn, D;
+    for (DMat<double> *m : {&I, &R, &Z, &T, &Zb, &Xb, &Xn, &D}) m->bind(w.al);
+    I.ensure_rows(n);
+    I.ensure_entries(n);
+    launch_identity(n, I.begp(), I.lenp(), I.colp(), I.valp(), w.s);
+    I.nnz = n;
+    LoopOut out;
+    row_sumsq(w, X, w.rs3);
+    double xf = std::sqrt(w.sum_rows(w.rs3, n));
+    int n_up = 0, n_flat = 0;
+    bool have_z = false;
+    std::vector<double> es;
+    const double target = 0.1 * p.tol;
+    const double tau_z = p.c_fixed * p.tol;
+    for (int k = 1;; ++k) {
+        const double t0 = now_s();
+        // residual R^_k = I - X^_k^2 (Alg. 3.1.1 steps 1 and 5)
+        product<double>(w, X, X, nullptr, -1.0, 0.0, 1.0, R, nullptr, &w.rs1);
+        const double e = std::sqrt(w.sum_rows(w.rs1, n));
+        es.push_back(e);
+        sign_iter_stats it{};
+        it.e = e; it.xfro = xf; it.nnz_x = X.nnz; it.nnz_r = R.nnz;
+        out.iters = k - 1; out.e = e; out.xfro = xf;
+        bool stop = e <= p.tol;
+        if (stop) out.status = SIGN_OK;
+        if (!stop) {
+            if (!std::isfinite(e)) { out.status = SIGN_EDIVERGED; stop = true; }
+            else if (k >= 2) {
+                const double ep = es[k - 2];
+                n_up = (e > ep && e > 1.0) ? n_up + 1 : 0;
+                n_flat = (e < 1e-8 && e > 0.5 * ep) ? n_flat + 1 : 0;
+                if (n_up >= 3) { out.status = SIGN_EDIVERGED; stop = true; }
+                else if (n_flat >= 2) { out.status = SIGN_OK; out.stagnated = 1; stop = true; }
+            }
+            if (!stop && k - 1 >= p.max_iter) { out.status = SIGN_ENOCONV; stop = true; }
+        }
+        if (stop) {
+            it.ms = 1e3 * (now_s() - t0);
+            trace.push_back(it);
+            break;
+        }
+        // Z ~ X^_k^{-1} by filtered Newton-Schulz inversion Z <- Z + Z (I - X^_k Z)
+        double r = std::numeric_limits<double>::infinity();
+        if (have_z) {
+            product<double>(w, X, Z, nullptr, -1.0, 0.0, 1.0, T, nullptr, &w.rs1);
+            r = std::sqrt(w.sum_rows(w.rs1, n));
+            if (!(r < 0.5)) have_z = false;
+        }
+        if (!have_z) {
+            // Z_0 = X^T / (||X||_1 ||X||_inf): ||I - X Z_0||_2 < 1 for nonsingular X
+            const double sc = norm_one_inf(w, X);
+            transpose(w, X, Z);
+            launch_scale_copy<double, double>(Z.valp(), Z.valp(), Z.nnz, 1.0 / sc, w.s);
+            product<double>(w, X, Z, nullptr, -1.0, 0.0, 1.0, T, nullptr, &w.rs1);
+            r = std::sqrt(w.sum_rows(w.rs1, n));
+        }
+        int steps = 0;
+        double r_prev = std::numeric_limits<double>::infinity();
+        while (r > target && steps < 200 && !(r < 1e-8 && r > 0.5 * r_prev)) {
+            r_prev = r;
+            product<double>(w, Z, T, &Z, 1.0, 1.0, 0.0, Zb, nullptr, nullptr);
+            filter<double, double>(w, Zb, tau_z, Z, nullptr, nullptr);
+            product<double>(w, X, Z, nullptr, -1.0, 0.0, 1.0, T, nullptr, &w.rs1);
+            r = std::sqrt(w.sum_rows(w.rs1, n));
+            ++steps;
+            if (!std::isfinite(r)) break;
+        }
+        inner_steps += steps;
+        have_z = true;
+        row_sumsq(w, Z, w.rs2);
+        const double zf = std::sqrt(w.sum_rows(w.rs2, n));
+        // Xbar_{k+1} = 1/2 (X^_k + X^_k^{-1})  (Alg. 3.1.1 step 3)
+        product<double>(w, X, I, &Z, 0.5, 0.5, 0.0, Xb, nullptr, nullptr);
+        // X^_{k+1} = Xbar_{k+1} - F_{k+1}, budget eq. 1.13 / fixed (step 4)
+        const double tau = nmf_budget(e, xf, zf, p.tol, p.c_fixed, p.switch_res);
+        const int bstar = filter<double, double>(w, Xb, tau, Xn, &w.rs3, &w.rs4);
+        const double xf_new = std::sqrt(w.sum_rows(w.rs3, n));
+        const double ff = std::sqrt(w.sum_rows(w.rs4, n));
+        product<double>(w, Xn, I, &X, 1.0, -1.0, 0.0, D, nullptr, &w.rs1);
+        const double d = std::sqrt(w.sum_rows(w.rs1, n));
+        it.d = d; it.tau = tau; it.ffro = ff; it.nnz_bar = Xb.nnz; it.bstar = bstar;
+        it.ms = 1e3 * (now_s() - t0);
+        trace.push_back(it);
+        std::swap(X, Xn);
+        xf = xf_new;
         out.d = d;
     }
     return out;

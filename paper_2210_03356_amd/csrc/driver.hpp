@@ -17,14 +17,14 @@ struct Workspace {
     DevBuf lo, span, cap, work, capoff, workoff, tmp, bins, counts, cursor, stage_col, stage_val;
     DevBuf rs1, rs2, rs3, rs4, icnt, hist, tau, bstar, seg, red, flag, zero_b;
     DevBuf cstat;
+    const uint8_t *row_skip = nullptr;  // optional row mask for products (serving)
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     // accumulated product statistics, in total and per row class (kernel tile)
     struct ClassStat {
         int64_t launches = 0, rows = 0, products = 0, a_nnz = 0, d_nnz = 0, out = 0;
         double ms = 0.0, bytes = 0.0;
     };
-    ClassStat cls[4];
-    int value_bytes = 8;
+    ClassStat cls[2][4];  // [FP64, FP32][row class]
     int64_t products = 0;
     double spgemm_ms = 0.0;
     double spgemm_bytes = 0.0;
@@ -50,6 +50,16 @@ void product(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D,
 template <typename V, typename Vo>
 int filter(Workspace &w, const DMat<V> &In, double tau, DMat<Vo> &Out, DevBuf *sq_keep,
            DevBuf *sq_drop);
+
+// Filtering of a block-diagonal batch: segment s owns rows [seg_h[s], seg_h[s+1])
+// (seg_d: the same boundaries on the device, row_seg: segment of every row)
+// and is cut with its own budget tau_h[s].  bstar_h receives the cuts.
+void filter_seg(Workspace &w, const DMat<double> &In, const std::vector<int64_t> &seg_h,
+                const int64_t *seg_d, const int32_t *row_seg, const std::vector<double> &tau_h,
+                DMat<double> &Out, DevBuf *sq_keep, DevBuf *sq_drop, std::vector<int> &bstar_h);
+
+// Per-segment sums of a per-row FP64 array (deterministic).
+std::vector<double> seg_sums(Workspace &w, const DevBuf &rows, const int64_t *seg_d, int nseg);
 
 // ||X||_F^2 per row into rows (via the survivor pass with an all-keeping cut).
 template <typename V>
@@ -77,6 +87,14 @@ struct LoopOut {
 template <typename V>
 LoopOut nsf_loop(Workspace &w, DMat<V> &X, const LoopParams &p,
                  std::vector<sign_iter_stats> &trace);
+
+// Algorithm 3.1.1 on X (FP64, compact, modified in place to the final iterate);
+// the inverse of each iterate by filtered Newton-Schulz inversion.
+LoopOut nmf_loop(Workspace &w, DMat<double> &X, const LoopParams &p,
+                 std::vector<sign_iter_stats> &trace, int &inner_steps);
+
+// Out = X^T (compact, sorted rows).
+void transpose(Workspace &w, const DMat<double> &X, DMat<double> &Out);
 
 inline double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())

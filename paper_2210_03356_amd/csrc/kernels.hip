@@ -20,6 +20,7 @@ namespace sfn {
 namespace {
 
 constexpr int kWave = 64;
+constexpr int kUnroll = 4;  // 64-entry chunks of a B row gathered per sweep step
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 __device__ __forceinline__ int wave_id() { return threadIdx.x / kWave; }
@@ -35,6 +36,33 @@ __device__ __forceinline__ double rl_val(double v, int l) {
 }
 __device__ __forceinline__ float rl_val(float v, int l) {
     return __int_as_float(rl_i32(__float_as_int(v), l));
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (id b runs on XCD
+// b % 8).  Neighbouring output rows gather nearly the same rows of B, so the
+// row list is dealt out in chunks of kXcdChunk consecutive rows, chunk c to
+// XCD c % 8: the workgroups resident on one XCD then work on consecutive rows
+// (their gathers hit that XCD's L2), and the eight XCDs together work on
+// 8*kXcdChunk consecutive rows (their misses share the Infinity Cache).  The
+// tail that does not fill a whole round is split into eight contiguous bands.
+// A bijection of [0, nb) for every nb.
+constexpr int kXcdChunk = 64;
+
+__device__ __forceinline__ int xcd_band(int b, int nb) {
+    const int per = (nb + 7) >> 3;
+    const int full = 8 - (8 * per - nb);  // XCDs whose band holds `per` rows
+    const int x = b & 7, q = b >> 3;
+    return x * per - max(0, x - full) + q;
+}
+
+__device__ __forceinline__ int xcd_row(int b, int nb) {
+    constexpr int round = 8 * kXcdChunk;
+    const int full = nb / round;
+    if (b < full * round) {
+        const int x = b & 7, q = b >> 3;
+        return (q / kXcdChunk) * round + x * kXcdChunk + (q % kXcdChunk);
+    }
+    return full * round + xcd_band(b - full * round, nb - full * round);
 }
 
 // number of set bits of m in lanes below the calling lane
@@ -232,10 +260,15 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_final(const T *in, int64_
 // ---------------------------------------------------------------------------
 template <typename V>
 __global__ void k_plan(MatView<V> A, MatView<V> B, MatView<V> D, int diag, int64_t r0,
-                       int64_t r1, int32_t *lo, int32_t *span, int64_t *cap, int64_t *work) {
+                       int64_t r1, int32_t *lo, int32_t *span, int64_t *cap, int64_t *work,
+                       const uint8_t *skip) {
     const int64_t i = r0 + (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
     if (i >= r1) return;  // uniform per wave
     const int lane = lane_id();
+    if (skip && skip[i]) {  // masked row: empty output, no work
+        if (lane == 0) { lo[i] = 0; span[i] = 0; cap[i] = 0; work[i] = 0; }
+        return;
+    }
     const int64_t ab = A.beg[i];
     const int al = A.len[i];
     int64_t u = 0;
@@ -356,7 +389,7 @@ __global__ __launch_bounds__(NT) void k_spgemm(
     __shared__ double wsum[2][NW];
 
     const int lane = lane_id(), wave = wave_id();
-    const int i = rows[blockIdx.x];
+    const int i = rows[xcd_row(blockIdx.x, gridDim.x)];
     const int lo = row_lo[i], span = row_span[i];
     const int64_t abeg = A.beg[i];
     const int alen = A.len[i];
@@ -397,19 +430,31 @@ __global__ __launch_bounds__(NT) void k_spgemm(
                 if (p < blq) {
                     const int64_t bbq = rl_i64(bb, q);
                     const V aq = rl_val(a, q);
+                    // kUnroll chunks of 64 entries in flight per wave; B rows
+                    // are sorted, so the in-window entries form a prefix and
+                    // the sweep stops at the first chunk that is not full
                     while (true) {
-                        const int pos = p + lane;
-                        int c = INT_MAX;
-                        V bv = V(0);
-                        if (pos < blq) {
-                            c = B.col[bbq + pos];
-                            bv = B.val[bbq + pos];
+                        int c[kUnroll];
+                        V bv[kUnroll];
+#pragma unroll
+                        for (int u = 0; u < kUnroll; ++u) {
+                            const int pos = p + u * kWave + lane;
+                            c[u] = INT_MAX;
+                            bv[u] = V(0);
+                            if (pos < blq) {
+                                c[u] = B.col[bbq + pos];
+                                bv[u] = B.val[bbq + pos];
+                            }
                         }
-                        const bool in = c < whi;
-                        if (in) atomicAdd(&acc[c - wlo], aq * bv);
-                        const int np = __popcll(__ballot(in));
-                        p += np;
-                        if (np < kWave) break;
+                        int got = 0;
+#pragma unroll
+                        for (int u = 0; u < kUnroll; ++u) {
+                            const bool in = c[u] < whi;
+                            if (in) atomicAdd(&acc[c[u] - wlo], aq * bv[u]);
+                            got += __popcll(__ballot(in));
+                        }
+                        p += got;
+                        if (got < kUnroll * kWave) break;
                     }
                 }
                 if (multi && lane == q) cur = p;
@@ -627,9 +672,155 @@ __global__ void k_shift_cols(const int64_t *rp, const int32_t *row_seg, const in
     for (int64_t p = rp[i] + lane_id(); p < rp[i + 1]; p += kWave) col[p] += d;
 }
 
+// ---------------------------------------------------------------------------
+// identity, column norms, transpose (filtered Newton: inverse start)
+// ---------------------------------------------------------------------------
+__global__ void k_identity(int64_t n, int64_t *beg, int32_t *len, int32_t *col, double *val) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    beg[i] = i;
+    if (i == n) return;
+    len[i] = 1;
+    col[i] = (int32_t)i;
+    val[i] = 1.0;
+}
+
+template <typename V>
+__global__ void k_col_abs_sum(MatView<V> X, double *colsum) {
+    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
+    if (i >= X.n) return;
+    const int64_t b = X.beg[i];
+    for (int p = lane_id(); p < X.len[i]; p += kWave)
+        atomicAdd(&colsum[X.col[b + p]], fabs(as_f64(X.val[b + p])));
+}
+
+template <typename V>
+__global__ void k_transpose_count(MatView<V> X, int32_t *cnt) {
+    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
+    if (i >= X.n) return;
+    const int64_t b = X.beg[i];
+    for (int p = lane_id(); p < X.len[i]; p += kWave) atomicAdd(&cnt[X.col[b + p]], 1);
+}
+
+template <typename V>
+__global__ void k_transpose_fill(MatView<V> X, const int64_t *tp, int32_t *fill, int32_t *tcol,
+                                 V *tval) {
+    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
+    if (i >= X.n) return;
+    const int64_t b = X.beg[i];
+    for (int p = lane_id(); p < X.len[i]; p += kWave) {
+        const int j = X.col[b + p];
+        const int64_t w = tp[j] + atomicAdd(&fill[j], 1);
+        tcol[w] = (int32_t)i;
+        tval[w] = X.val[b + p];
+    }
+}
+
+// Sort each row of a compact CSR by column: bitonic sort of (col, val) pairs
+// in LDS, one workgroup per row; rows longer than kSortMax are flagged.
+constexpr int kSortMax = 8192;
+constexpr int kSortThreads = 512;
+
+template <typename V>
+__global__ __launch_bounds__(kSortThreads) void k_sort_rows(const int64_t *rp, int32_t *col,
+                                                            V *val, int64_t n, int *flag) {
+    __shared__ int32_t kc[kSortMax];
+    __shared__ V kv[kSortMax];
+    const int64_t i = blockIdx.x;
+    if (i >= n) return;
+    const int64_t b = rp[i];
+    const int l = (int)(rp[i + 1] - b);
+    if (l <= 1) return;
+    if (l > kSortMax) {
+        if (threadIdx.x == 0) atomicOr(flag, 1);
+        return;
+    }
+    int m = 1;
+    while (m < l) m <<= 1;
+    for (int t = threadIdx.x; t < m; t += kSortThreads) {
+        kc[t] = t < l ? col[b + t] : INT_MAX;
+        kv[t] = t < l ? val[b + t] : V(0);
+    }
+    __syncthreads();
+    for (int k = 2; k <= m; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = threadIdx.x; t < m; t += kSortThreads) {
+                const int u = t ^ j;
+                if (u > t) {
+                    const bool up = (t & k) == 0;
+                    const int32_t a = kc[t], c = kc[u];
+                    if ((a > c) == up) {
+                        kc[t] = c; kc[u] = a;
+                        const V va = kv[t]; kv[t] = kv[u]; kv[u] = va;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int t = threadIdx.x; t < l; t += kSortThreads) {
+        col[b + t] = kc[t];
+        val[b + t] = kv[t];
+    }
+}
+
+// diag[i] = X_ii (0 if absent), wave per row, binary search in the sorted row
+template <typename V>
+__global__ void k_diag(MatView<V> X, double *diag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= X.n) return;
+    const int64_t b = X.beg[i];
+    int lo = 0, hi = X.len[i];
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (X.col[b + mid] < i) lo = mid + 1;
+        else hi = mid;
+    }
+    diag[i] = (lo < X.len[i] && X.col[b + lo] == i) ? as_f64(X.val[b + lo]) : 0.0;
+}
+
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 }  // namespace
+
+template <typename V>
+void launch_diag(MatView<V> X, double *diag, hipStream_t s) {
+    if (X.n > 0) k_diag<V><<<blocks_for(X.n, 256), 256, 0, s>>>(X, diag);
+}
+template void launch_diag<double>(MatView<double>, double *, hipStream_t);
+template void launch_diag<float>(MatView<float>, double *, hipStream_t);
+
+void launch_identity(int64_t n, int64_t *beg, int32_t *len, int32_t *col, double *val,
+                     hipStream_t s) {
+    k_identity<<<blocks_for(n + 1, 256), 256, 0, s>>>(n, beg, len, col, val);
+}
+
+template <typename V>
+void launch_col_abs_sum(MatView<V> X, double *colsum, hipStream_t s) {
+    if (X.n > 0) k_col_abs_sum<V><<<blocks_for(X.n, 4), 256, 0, s>>>(X, colsum);
+}
+template void launch_col_abs_sum<double>(MatView<double>, double *, hipStream_t);
+
+template <typename V>
+void launch_transpose_count(MatView<V> X, int32_t *cnt, hipStream_t s) {
+    if (X.n > 0) k_transpose_count<V><<<blocks_for(X.n, 4), 256, 0, s>>>(X, cnt);
+}
+template <typename V>
+void launch_transpose_fill(MatView<V> X, const int64_t *tp, int32_t *fill, int32_t *tcol, V *tval,
+                           hipStream_t s) {
+    if (X.n > 0) k_transpose_fill<V><<<blocks_for(X.n, 4), 256, 0, s>>>(X, tp, fill, tcol, tval);
+}
+template <typename V>
+void launch_sort_rows(const int64_t *rp, int32_t *col, V *val, int64_t n, int *flag,
+                      hipStream_t s) {
+    if (n > 0) k_sort_rows<V><<<(unsigned)n, kSortThreads, 0, s>>>(rp, col, val, n, flag);
+}
+template void launch_transpose_count<double>(MatView<double>, int32_t *, hipStream_t);
+template void launch_transpose_fill<double>(MatView<double>, const int64_t *, int32_t *, int32_t *,
+                                            double *, hipStream_t);
+template void launch_sort_rows<double>(const int64_t *, int32_t *, double *, int64_t, int *,
+                                       hipStream_t);
+int sort_rows_max() { return kSortMax; }
 
 // ===========================================================================
 // launchers
@@ -690,14 +881,57 @@ void launch_exclusive_scan_i32(const int32_t *in, int64_t n, int64_t *out, int64
 
 template <typename V>
 void launch_plan(MatView<V> A, MatView<V> B, MatView<V> D, int diag, int64_t r0, int64_t r1,
-                 int32_t *lo, int32_t *span, int64_t *cap, int64_t *work, hipStream_t s) {
+                 int32_t *lo, int32_t *span, int64_t *cap, int64_t *work, const uint8_t *skip,
+                 hipStream_t s) {
     if (r1 <= r0) return;
-    k_plan<V><<<blocks_for(r1 - r0, 4), 256, 0, s>>>(A, B, D, diag, r0, r1, lo, span, cap, work);
+    k_plan<V><<<blocks_for(r1 - r0, 4), 256, 0, s>>>(A, B, D, diag, r0, r1, lo, span, cap, work,
+                                                     skip);
 }
 template void launch_plan<double>(MatView<double>, MatView<double>, MatView<double>, int, int64_t,
-                                  int64_t, int32_t *, int32_t *, int64_t *, int64_t *, hipStream_t);
+                                  int64_t, int32_t *, int32_t *, int64_t *, int64_t *,
+                                  const uint8_t *, hipStream_t);
 template void launch_plan<float>(MatView<float>, MatView<float>, MatView<float>, int, int64_t,
-                                 int64_t, int32_t *, int32_t *, int64_t *, int64_t *, hipStream_t);
+                                 int64_t, int32_t *, int32_t *, int64_t *, int64_t *,
+                                 const uint8_t *, hipStream_t);
+
+// ---- batch relayout for serving -------------------------------------------------
+__global__ void k_move_len(const SegMove *t, int32_t *dst_len) {
+    const SegMove m = t[blockIdx.y];
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < m.nrows) dst_len[m.dst_row + r] = m.src.len[m.src_row + r];
+}
+
+__global__ void k_move_rows(const SegMove *t, const int64_t *dst_beg, int32_t *dst_col,
+                            double *dst_val) {
+    const SegMove m = t[blockIdx.y];
+    const int64_t r = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
+    if (r >= m.nrows) return;
+    const int64_t sb = m.src.beg[m.src_row + r], db = dst_beg[m.dst_row + r];
+    const int l = m.src.len[m.src_row + r];
+    for (int p = lane_id(); p < l; p += kWave) {
+        dst_col[db + p] = (int32_t)(m.src.col[sb + p] + m.col_shift);
+        dst_val[db + p] = m.src.val[sb + p];
+    }
+}
+
+__global__ void k_fill_u8(uint8_t *p, int64_t lo, int64_t hi, uint8_t v) {
+    const int64_t i = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < hi) p[i] = v;
+}
+
+void launch_move_len(const SegMove *t, int nseg, int64_t max_rows, int32_t *dst_len,
+                     hipStream_t s) {
+    if (nseg <= 0 || max_rows <= 0) return;
+    k_move_len<<<dim3(blocks_for(max_rows, 256), nseg), 256, 0, s>>>(t, dst_len);
+}
+void launch_move_rows(const SegMove *t, int nseg, int64_t max_rows, const int64_t *dst_beg,
+                      int32_t *dst_col, double *dst_val, hipStream_t s) {
+    if (nseg <= 0 || max_rows <= 0) return;
+    k_move_rows<<<dim3(blocks_for(max_rows, 4), nseg), 256, 0, s>>>(t, dst_beg, dst_col, dst_val);
+}
+void launch_fill_u8(uint8_t *p, int64_t lo, int64_t hi, uint8_t v, hipStream_t s) {
+    if (hi > lo) k_fill_u8<<<blocks_for(hi - lo, 256), 256, 0, s>>>(p, lo, hi, v);
+}
 
 void launch_bin_rows(const int32_t *span, const int64_t *work, int64_t r0, int64_t r1,
                      int small_tile, int mid_tile, int32_t *bins, int64_t bin_stride,

@@ -60,9 +60,11 @@ void launch_exclusive_scan_i32(const int32_t *in, int64_t n, int64_t *out, int64
 // ---- product C = diag*I + coef*A*B + dcoef*D ---------------------------------
 // Plan: per row i of A (rows [r0, r1)): column window [lo[i], lo[i]+span[i]),
 // reserved output capacity cap[i], product count work[i].
+// Rows with skip[i] != 0 (skip may be null) get an empty output and no work.
 template <typename V>
 void launch_plan(MatView<V> A, MatView<V> B, MatView<V> D, int diag, int64_t r0, int64_t r1,
-                 int32_t *lo, int32_t *span, int64_t *cap, int64_t *work, hipStream_t s);
+                 int32_t *lo, int32_t *span, int64_t *cap, int64_t *work, const uint8_t *skip,
+                 hipStream_t s);
 
 // Row classes: 0 empty, 1..3 tiles.  Writes row lists per class (bins[c] holds
 // up to r1-r0 rows), counts into counts[4] (device), and len=0 for empty rows.
@@ -120,5 +122,42 @@ void launch_row_segments(const int64_t *seg_rows, int nseg, int64_t max_seg_rows
 // Add delta[seg] to the columns of each row (block-diagonal relayout).
 void launch_shift_cols(const int64_t *rp, const int32_t *row_seg, const int32_t *delta,
                        int64_t n, int32_t *col, hipStream_t s);
+
+// ---- batch relayout (serving) -------------------------------------------------
+// Row block [src_row, src_row + nrows) of src moves to [dst_row, ...) of the
+// destination with every column index shifted by col_shift.
+struct SegMove {
+    MatView<double> src;
+    int64_t src_row, dst_row, nrows, col_shift;
+};
+void launch_move_len(const SegMove *t, int nseg, int64_t max_rows, int32_t *dst_len,
+                     hipStream_t s);
+void launch_move_rows(const SegMove *t, int nseg, int64_t max_rows, const int64_t *dst_beg,
+                      int32_t *dst_col, double *dst_val, hipStream_t s);
+void launch_fill_u8(uint8_t *p, int64_t lo, int64_t hi, uint8_t v, hipStream_t s);
+
+// ---- filtered Newton support ---------------------------------------------------
+// beg[0..n] = 0..n, len = 1, col = i, val = 1 (identity of order n, compact)
+void launch_identity(int64_t n, int64_t *beg, int32_t *len, int32_t *col, double *val,
+                     hipStream_t s);
+// colsum[j] += |x_ij| (colsum zeroed by the caller)
+template <typename V>
+void launch_col_abs_sum(MatView<V> X, double *colsum, hipStream_t s);
+// transpose: count per column, then fill rows of X^T at tp[j] + atomic slot;
+// rows of the result are unordered until launch_sort_rows
+template <typename V>
+void launch_transpose_count(MatView<V> X, int32_t *cnt, hipStream_t s);
+template <typename V>
+void launch_transpose_fill(MatView<V> X, const int64_t *tp, int32_t *fill, int32_t *tcol, V *tval,
+                           hipStream_t s);
+// sort every row of a compact CSR by column; rows longer than sort_rows_max()
+// set *flag and are left unsorted
+template <typename V>
+void launch_sort_rows(const int64_t *rp, int32_t *col, V *val, int64_t n, int *flag,
+                      hipStream_t s);
+int sort_rows_max();
+// diag[i] = X_ii in FP64 (0 when not stored)
+template <typename V>
+void launch_diag(MatView<V> X, double *diag, hipStream_t s);
 
 }  // namespace sfn

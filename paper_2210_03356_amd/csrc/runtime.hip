@@ -17,6 +17,7 @@ size_t round_bytes(size_t b) {
 }  // namespace
 
 void set_last_error(const std::string &m) { g_last_error = m; }
+const char *last_error() { return g_last_error.c_str(); }
 
 Pool &Pool::instance() {
     static Pool *p = new Pool();  // never destroyed: blocks live until process exit

@@ -130,7 +130,9 @@ inline void write_scalar(T *dev, T v, hipStream_t s) {
     SFN_HIP(hipStreamSynchronize(s));
 }
 
+// Thread-local message of the last failing ABI call.
 void set_last_error(const std::string &m);
+const char *last_error();
 
 }  // namespace sfn
 

@@ -245,3 +245,66 @@ def test_trace_records_budget_and_filter(sf):
     # residual histories agree until the rounding floor
     big = e_ref > 1e-10
     assert np.allclose(e_gpu[big], e_ref[big], rtol=1e-9)
+
+
+NMF_CASES = {
+    "lap2d_10": (lambda: W.laplacian_2d(10, jitter=0.05, seed=2, m=8.0), {}),
+    "lap2d_24": (lambda: W.laplacian_2d(24, jitter=0.05, seed=2, m=8.0), {}),
+    "convdiff_12": (lambda: W.convdiff_2d(12, beta=0.5, sigma=4.0, m=8.0), {}),
+    "ode_100": (lambda: W.ode_block_matrix(100), {}),
+}
+
+
+@pytest.mark.parametrize("name", list(NMF_CASES))
+def test_newton_matches_oracle(sf, name):
+    make, kw = NMF_CASES[name]
+    A = make()
+    r = sf.sign_newton(_dev(sf, A), sf.default_opts(tol=1e-12, **kw))
+    assert r.status == "OK"
+    ref = oracle.nmf(A, tol=1e-12)
+    assert ref.status == "OK"
+    X, S = r.to_scipy(), ref.to_scipy()
+    assert sp.linalg.norm(X - S) / sp.linalg.norm(S) <= 1e-10
+    st = r.stats()
+    assert st["inner_steps"] > 0
+    assert abs(st["iters"] - ref.iters) <= 1
+    if name.startswith("ode"):
+        assert _rel(X.toarray(), cf.sign_ode_block(100)) <= 1e-10
+
+
+def test_newton_agrees_with_ns_on_gpu(sf):
+    A = W.laplacian_2d(30, jitter=0.05, seed=2, m=8.0)
+    a = sf.sign_ns(_dev(sf, A), sf.default_opts(tol=1e-12)).to_scipy()
+    b = sf.sign_newton(_dev(sf, A), sf.default_opts(tol=1e-12)).to_scipy()
+    assert sp.linalg.norm(a - b) / sp.linalg.norm(a) <= 1e-10
+
+
+MIXED_CASES = {
+    "convdiff_40": (lambda: W.convdiff_2d(40, beta=0.5, sigma=4.0, m=8.0),
+                    dict(tol=1e-12, filter_y=1)),
+    "lap3d_10": (lambda: W.laplacian_3d(10, perturb=0.5, seed=4, m=12.0),
+                 dict(tol=1e-10, filter_y=1)),
+    "lap2d_48": (lambda: W.laplacian_2d(48, jitter=0.05, seed=2, m=8.0), dict(tol=1e-12)),
+}
+
+
+@pytest.mark.parametrize("name", list(MIXED_CASES))
+def test_mixed_precision_matches_fp64_oracle(sf, name):
+    """FP32 bulk + FP64 polish and commutator refinement reaches 1e-8 of the FP64 oracle."""
+    make, kw = MIXED_CASES[name]
+    A = make()
+    r = sf.sign_ns(_dev(sf, A), sf.default_opts(precision=1, **kw))
+    assert r.status == "OK"
+    ref = oracle.nsf(A, tol=1e-12, filter_y=kw.get("filter_y", 0))
+    X, S = r.to_scipy(), ref.to_scipy()
+    rel = sp.linalg.norm(X - S) / sp.linalg.norm(S)
+    assert rel <= 1e-8, rel
+    tr = r.trace()
+    assert any(t["fp32"] for t in tr) and not tr[-1]["fp32"]
+    st = r.stats()
+    assert st["res_fro"] <= 10 * kw["tol"]
+    assert st["comm_rel"] > 0.0
+    # the refinement is what removes the error part that Newton-Schulz keeps
+    r0 = sf.sign_ns(_dev(sf, A), sf.default_opts(precision=1, refine_steps=0, **kw))
+    rel0 = sp.linalg.norm(r0.to_scipy() - S) / sp.linalg.norm(S)
+    assert rel <= rel0

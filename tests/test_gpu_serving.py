@@ -1,0 +1,131 @@
+"""Continuous-batching server (sign_server_*) through the C ABI."""
+import time
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sf():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    import paper_2210_03356_amd as pkg
+    pkg.load()
+    oracle.build(force=False)
+    return pkg
+
+
+def _requests():
+    return [
+        (W.laplacian_1d(700, sigma=2.0, jitter=0.05, seed=11, m=4.0), 1e-10),
+        (W.laplacian_2d(20, jitter=0.05, seed=12, m=8.0), 1e-6),
+        (W.convdiff_2d(18, beta=0.5, sigma=4.0, m=8.0, jitter=0.05, seed=13), 1e-10),
+        (W.laplacian_2d(33, jitter=0.05, seed=14, m=8.0), 1e-10),
+        (W.laplacian_1d(2048, sigma=2.0, jitter=0.05, seed=15, m=4.0), 1e-6),
+        (W.convdiff_2d(25, beta=0.5, sigma=4.0, m=8.0, jitter=0.05, seed=16), 1e-6),
+    ]
+
+
+def _wait(srv, tickets, timeout=120.0):
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets):
+        for t in tickets:
+            if t in out:
+                continue
+            r = srv.poll(t)
+            if r is not None:
+                out[t] = r
+        if time.time() - t0 > timeout:
+            raise TimeoutError(f"{len(out)}/{len(tickets)} done")
+        time.sleep(0.002)
+    return out
+
+
+def _rel(a, b):
+    return sp.linalg.norm(a - b) / sp.linalg.norm(b)
+
+
+def test_served_results_equal_solo_results(sf):
+    reqs = _requests()
+    srv = sf.Server()
+    try:
+        tickets = [srv.submit(A, sf.default_opts(tol=tol)) for A, tol in reqs]
+        res = _wait(srv, tickets)
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert st["completed"] == len(reqs) and st["max_active"] >= 2
+    for (A, tol), t in zip(reqs, tickets):
+        r = res[t]
+        assert r.status == "OK"
+        X = r.to_scipy()
+        solo = sf.sign_ns(sf.DeviceCsr.from_host(A), sf.default_opts(tol=tol)).to_scipy()
+        # same arithmetic alone and in the mix, up to the order of LDS additions
+        assert _rel(X, solo) <= 1e-12
+        ref = oracle.nsf(A, tol=tol).to_scipy()
+        assert _rel(X, ref) <= max(1e-10, 10 * tol)
+        assert r.stats()["res_fro"] <= tol
+
+
+def test_late_arrivals_join_the_running_batch(sf):
+    reqs = _requests()
+    srv = sf.Server()
+    try:
+        first = [srv.submit(A, sf.default_opts(tol=tol)) for A, tol in reqs[:3]]
+        t0 = time.time()
+        while srv.stats()["ticks"] == 0 and time.time() - t0 < 30:
+            time.sleep(0.001)
+        late = [srv.submit(A, sf.default_opts(tol=tol)) for A, tol in reqs[3:]]
+        res = _wait(srv, first + late)
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert st["completed"] == 6
+    for (A, tol), t in zip(reqs, first + late):
+        ref = oracle.nsf(A, tol=tol).to_scipy()
+        assert _rel(res[t].to_scipy(), ref) <= max(1e-10, 10 * tol)
+    assert 0 < st["p50_ms"] <= st["p99_ms"]
+
+
+def test_memory_admission_serialises_under_a_tiny_budget(sf):
+    reqs = _requests()[:3]
+    srv = sf.Server(hbm_budget_bytes=1)
+    try:
+        tickets = [srv.submit(A, sf.default_opts(tol=tol)) for A, tol in reqs]
+        res = _wait(srv, tickets)
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert st["max_active"] == 1          # one request at a time fits the budget
+    for (A, tol), t in zip(reqs, tickets):
+        assert res[t].status == "OK"
+
+
+def test_poll_and_submit_errors(sf):
+    srv = sf.Server(max_slots=2)
+    try:
+        with pytest.raises(sf.SignError):
+            srv.poll(12345)
+        bad = W.tridiag_c1(6)
+        bad.indices = bad.indices.copy()
+        bad.indices[1], bad.indices[2] = 2, 0
+        with pytest.raises(sf.SignError, match="ascending"):
+            srv.submit(bad)
+        A = W.laplacian_2d(8, jitter=0.05, seed=2, m=8.0)
+        t = srv.submit(A, sf.default_opts(max_iter=1))
+        r = _wait(srv, [t])[t]
+        assert r.status == "ENOCONV"
+        with pytest.raises(sf.SignError):
+            srv.poll(t)                   # collected already
+        with pytest.raises(sf.SignError):
+            srv.submit(A, sf.default_opts(precision=1))
+    finally:
+        srv.close()
