@@ -108,6 +108,115 @@ def cpu_baseline(cfg, grid_full, n_full):
                        f"{n_full}/{A.n} rows")}
 
 
+def serve_bench(args):
+    """Served stream: Poisson arrivals of 1D/2D/conv-diff requests (n log-uniform in
+    [1024, 65536], tol in {1e-6, 1e-10}) through the continuous-batching server, next to
+    the same requests solved one after another with sign_ns on the same GPU."""
+    import numpy as np
+    import torch
+    import paper_2210_03356_amd as sf
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    sf.load()
+    reqs = W.served_stream(count=args.serve_count, rate=args.serve_rate, seed=5)
+    mats = [W.request_matrix(r) for r in reqs]
+    print(f"# served stream: {len(reqs)} requests over {reqs[-1]['arrival']:.2f} s of arrivals",
+          file=sys.stderr, flush=True)
+    # warm the library (pool, code objects) outside the measured window
+    sf.sign_ns(sf.DeviceCsr.from_host(mats[0]), sf.default_opts(tol=reqs[0]["tol"]))
+    srv = sf.Server(max_slots=args.serve_slots)
+    done, tickets, i = {}, [], 0
+    t0 = time.perf_counter()
+    while len(done) < len(reqs):
+        now = time.perf_counter() - t0
+        while i < len(reqs) and reqs[i]["arrival"] <= now:
+            tickets.append((srv.submit(mats[i], sf.default_opts(tol=reqs[i]["tol"])), i))
+            i += 1
+        for t, j in tickets:
+            if t not in done:
+                r = srv.poll(t)
+                if r is not None:
+                    done[t] = (j, r.status, r.stats()["res_fro"])
+                    del r
+        time.sleep(0.0005)
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    ok = sum(1 for j, status, e in done.values() if status == "OK" and e <= reqs[j]["tol"])
+    # the same requests solved one by one (no batching), same GPU and tolerances
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for A, r in zip(mats, reqs):
+        res = sf.sign_ns(sf.DeviceCsr.from_host(A), sf.default_opts(tol=r["tol"]))
+        del res
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t1
+    line = {
+        "metric": "served p50/p99 latency and solves/s",
+        "value": round(len(reqs) / wall, 3), "unit": "solves/s", "n_gpus": 1,
+        "higher_is_better": True, "data": "synthetic", "dtype": "f64",
+        "p50_ms": round(st["p50_ms"], 1), "p99_ms": round(st["p99_ms"], 1),
+        "requests": len(reqs), "arrival_rate_per_s": args.serve_rate,
+        "wall_s": round(wall, 2), "ok_within_tol": ok, "ticks": st["ticks"],
+        "max_active": st["max_active"], "busy_s": round(st["busy_seconds"], 2),
+        "sequential_sign_ns_solves_per_s": round(len(reqs) / seq, 3),
+        "offered_load_vs_sequential": round(args.serve_rate * seq / len(reqs), 2),
+        "config": {"workload": "c5: Poisson stream, 1D (sigma=2, m=4) / 2D (sigma=4, m=8) / "
+                               "conv-diff (m=8), jitter U[-.05,.05] seed 5000+id, seed 5",
+                   "max_slots": args.serve_slots},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def ode_bench(args):
+    """Section 4.2 matrix [[0, B], [I, 0]], B = tridiag(1/16, 7/8, 1/16): NSF and
+    unfiltered NS on the GPU, error against the closed form of eq. 1.26, and the
+    paper's MATLAB times (Table 4.2.1) as context."""
+    import numpy as np
+    import torch
+    import paper_2210_03356_amd as sf
+    import workloads as W
+    from oracle import closed_forms as cf
+
+    torch.cuda.set_device(0)
+    sf.load()
+    paper = {}
+    for l in open(os.path.join(ROOT, "tests", "golden", "table_4_2_1.txt")):
+        if l.strip() and not l.startswith("#"):
+            f = l.split()
+            paper[int(f[0])] = dict(nsf_et=float(f[1]), nsf_ae=float(f[2]), ns_et=float(f[3]))
+    for nB in (args.ode_sizes or [500, 1000, 3000, 5000]):
+        A = W.ode_block_matrix(nB)
+        dA = sf.DeviceCsr.from_host(A)
+        times = {}
+        res = {}
+        for name, kw in (("nsf", {}), ("ns", dict(c_fixed=0.0, switch_res=0.0))):
+            o = sf.default_opts(tol=1e-12, **kw)
+            sf.sign_ns(dA, o)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(args.steps):
+                r = sf.sign_ns(dA, o)
+            torch.cuda.synchronize()
+            times[name] = (time.perf_counter() - t) / args.steps
+            res[name] = r.to_scipy()
+        ae = float(np.sqrt(((res["nsf"] - res["ns"]).multiply(res["nsf"] - res["ns"])).sum()))
+        half, mhalf = cf.ode_sqrt_blocks(nB)
+        S = res["nsf"].toarray()
+        err = float(np.sqrt(np.linalg.norm(S[:nB, nB:] - half) ** 2 +
+                            np.linalg.norm(S[nB:, :nB] - mhalf) ** 2) /
+                    np.sqrt(np.linalg.norm(half) ** 2 + np.linalg.norm(mhalf) ** 2))
+        line = {"metric": "sign(A) time-to-solution, Section 4.2 matrix", "value": round(times["nsf"], 5),
+                "unit": "s", "higher_is_better": False, "n_gpus": 1, "dtype": "f64",
+                "data": "synthetic", "config": {"workload": f"ode: [[0,B],[I,0]], n_B={nB}",
+                                                 "n": 2 * nB, "tol": 1e-12},
+                "ns_unfiltered_s": round(times["ns"], 5), "ae_nsf_vs_ns_fro": ae,
+                "rel_err_vs_closed_form": err, "nnz_result": int(res["nsf"].nnz),
+                "paper_matlab_i7_10750h": paper.get(nB)}
+        print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,12 +230,22 @@ def main():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--copy-calib-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (counter calibration)")
+    ap.add_argument("--serve", action="store_true", help="served-stream benchmark instead")
+    ap.add_argument("--serve-count", type=int, default=300)
+    ap.add_argument("--serve-rate", type=float, default=50.0)
+    ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--ode", action="store_true", help="Section 4.2 matrix benchmark instead")
+    ap.add_argument("--ode-sizes", type=int, nargs="*", default=None)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
               "sharding of this path is a design, not a measured configuration.",
               file=sys.stderr)
         sys.exit(2)
+    if args.serve:
+        return serve_bench(args)
+    if args.ode:
+        return ode_bench(args)
 
     import numpy as np
     import torch
