@@ -363,8 +363,8 @@ def main():
         if agg["spgemm_ms"] > 0 else None,
         "roofline": {
             "bound": "hbm",
-            "kernel": f"k_spgemm<{'float' if st['hot_fp32'] else 'double'},{tile},"
-                      f"{st['hot_threads']}>",
+            "kernel": f"k_spgemm{'_pair' if st['hot_pair'] else ''}<"
+                      f"{'float' if st['hot_fp32'] else 'double'},{tile},{st['hot_threads']}>",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

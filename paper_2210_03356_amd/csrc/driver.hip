@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <limits>
 
 namespace sfn {
@@ -14,15 +15,21 @@ constexpr int kMidTile = 4096;
 Workspace::Workspace(Allocator *a, size_t staging_bytes) : al(a), s(a->stream) {
     for (DevBuf *b : {&lo, &span, &cap, &work, &capoff, &workoff, &tmp, &bins, &counts, &cursor,
                       &stage_col, &stage_val, &rs1, &rs2, &rs3, &rs4, &icnt, &hist, &tau,
-                      &bstar, &seg, &red, &flag, &zero_b, &cstat})
+                      &bstar, &seg, &red, &flag, &zero_b, &cstat, &mk, &m0, &m1, &mlen, &cnext})
         b->bind(a);
+    const char *pe = std::getenv("SIGNFN_PAIR_ROWS");
+    pairing = !(pe && pe[0] == '0');
     if (staging_bytes == 0) {
+        // a quarter of the memory that is free or idle in the caching pool,
+        // capped so that one reservation stays a modest share of HBM
         size_t fr = 0, tot = 0;
         if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
             (void)hipGetLastError();
             fr = size_t(8) << 30;
         }
-        staging_bytes = std::max<size_t>(size_t(256) << 20, fr / 4);
+        const size_t avail = fr + (a->alloc ? 0 : Pool::instance().cached_bytes());
+        staging_bytes = std::min<size_t>(size_t(48) << 30,
+                                         std::max<size_t>(size_t(256) << 20, avail / 4));
     }
     staging_limit = staging_bytes;
     for (auto &e : ev) SFN_HIP(hipEventCreate(&e));
@@ -37,12 +44,13 @@ Workspace::~Workspace() {
 void Workspace::hot_stats(sign_stats &st) const {
     int hv = 0, h = 1;
     for (int v = 0; v < 2; ++v)
-        for (int c = 1; c < 4; ++c)
+        for (int c = 1; c < kClasses; ++c)
             if (cls[v][c].ms > cls[hv][h].ms) { hv = v; h = c; }
     const ClassStat &c = cls[hv][h];
     st.hot_tile = bin_config(h, hv ? 4 : 8).tile;
     st.hot_threads = bin_config(h, hv ? 4 : 8).threads;
     st.hot_fp32 = hv;
+    st.hot_pair = h == 4;
     st.hot_launches = c.launches;
     st.hot_ms = c.ms;
     st.hot_bytes = c.bytes;
@@ -127,9 +135,19 @@ void product(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D,
     }
     const int64_t a_extent = A.capacity();
     w.cursor.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(a_extent, 1));
-    w.bins.ensure(sizeof(int32_t) * 4 * (size_t)std::max<int64_t>(n, 1));
-    w.counts.ensure(sizeof(int32_t) * 4);
-    w.cstat.ensure(sizeof(int64_t) * 32);
+    w.cnext.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(a_extent, 1));
+    w.bins.ensure(sizeof(int32_t) * kClasses * (size_t)std::max<int64_t>(n, 1));
+    w.counts.ensure(sizeof(int32_t) * kClasses);
+    w.cstat.ensure(sizeof(int64_t) * 8 * kClasses);
+    // pairs need A compact (rows i, i+1 adjacent in storage) -- every matrix
+    // built here is; the merged lists reuse A's index range
+    const bool pairing = w.pairing;
+    if (pairing) {
+        w.mk.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(a_extent, 1));
+        w.m0.ensure(sizeof(V) * (size_t)std::max<int64_t>(a_extent, 1));
+        w.m1.ensure(sizeof(V) * (size_t)std::max<int64_t>(a_extent, 1));
+        w.mlen.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1));
+    }
 
     int64_t running = 0;
     for (size_t b = 0; b + 1 < cuts.size(); ++b) {
@@ -138,52 +156,84 @@ void product(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D,
         const int64_t bcap = capoff_h.empty() ? total_cap : capoff_h[r1] - base;
         w.stage_col.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(bcap, 1));
         w.stage_val.ensure(sizeof(V) * (size_t)std::max<int64_t>(bcap, 1));
-        SFN_HIP(hipMemsetAsync(w.counts.get(), 0, sizeof(int32_t) * 4, s));
-        SFN_HIP(hipMemsetAsync(w.cstat.get(), 0, sizeof(int64_t) * 32, s));
+        SFN_HIP(hipMemsetAsync(w.counts.get(), 0, sizeof(int32_t) * kClasses, s));
+        SFN_HIP(hipMemsetAsync(w.cstat.get(), 0, sizeof(int64_t) * 8 * kClasses, s));
         launch_bin_rows(w.span.as<int32_t>(), w.work.as<int64_t>(), r0, r1, kSmallTile, kMidTile,
-                        w.bins.as<int32_t>(), n, w.counts.as<int32_t>(), C.lenp(),
-                        sq_prod ? sq_prod->as<double>() : nullptr,
+                        pairing ? 1 : 0, w.bins.as<int32_t>(), n, w.counts.as<int32_t>(),
+                        C.lenp(), sq_prod ? sq_prod->as<double>() : nullptr,
                         sq_out ? sq_out->as<double>() : nullptr, A.lenp(),
                         D ? D->lenp() : nullptr, w.cstat.as<int64_t>(), s);
-        int32_t cnt[4];
+        int32_t cnt[kClasses];
         SFN_HIP(hipMemcpyAsync(cnt, w.counts.get(), sizeof(cnt), hipMemcpyDeviceToHost, s));
         SFN_HIP(hipStreamSynchronize(s));
         SFN_HIP(hipEventRecord(w.ev[0], s));
+        if (cnt[4] > 0) {
+            const int32_t *pairs = w.bins.as<int32_t>() + (int64_t)4 * n;
+            launch_merge_pairs<V>(pairs, cnt[4], A.view(), B.view(), w.mk.as<int32_t>(),
+                                  w.m0.as<V>(), w.m1.as<V>(), w.mlen.as<int32_t>(),
+                                  w.cstat.as<int64_t>() + 4 * 8 + 5, s);
+            SFN_HIP(hipEventRecord(w.ev[1], s));
+            launch_spgemm_pair<V>(pairs, cnt[4], w.mk.as<int32_t>(), w.m0.as<V>(), w.m1.as<V>(),
+                                  w.mlen.as<int32_t>(), A.view(), B.view(), Dv, coef, dcoef, diag,
+                                  w.lo.as<int32_t>(), w.span.as<int32_t>(), base,
+                                  w.capoff.as<int64_t>(), w.stage_col.as<int32_t>(),
+                                  w.stage_val.as<V>(), C.lenp(), w.cursor.as<int32_t>(),
+                                  w.cnext.as<int32_t>(), sq_prod ? sq_prod->as<double>() : nullptr,
+                                  sq_out ? sq_out->as<double>() : nullptr,
+                                  w.cstat.as<int64_t>() + 4 * 8 + 4, s);
+        } else {
+            SFN_HIP(hipEventRecord(w.ev[1], s));
+        }
+        SFN_HIP(hipEventRecord(w.ev[2], s));
         for (int cls = 3; cls >= 1; --cls) {
             launch_spgemm<V>(cls, w.bins.as<int32_t>() + (int64_t)cls * n, cnt[cls], A.view(),
                              B.view(), Dv, coef, dcoef, diag, w.lo.as<int32_t>(),
                              w.span.as<int32_t>(), base, w.capoff.as<int64_t>(),
                              w.stage_col.as<int32_t>(), w.stage_val.as<V>(), C.lenp(),
-                             w.cursor.as<int32_t>(), sq_prod ? sq_prod->as<double>() : nullptr,
+                             w.cursor.as<int32_t>(), w.cnext.as<int32_t>(),
+                             sq_prod ? sq_prod->as<double>() : nullptr,
                              sq_out ? sq_out->as<double>() : nullptr,
                              w.cstat.as<int64_t>() + cls * 8 + 4, s);
-            SFN_HIP(hipEventRecord(w.ev[4 - cls], s));
+            SFN_HIP(hipEventRecord(w.ev[6 - cls], s));
         }
         // compact row starts of this batch, continuing from the previous batches
         launch_exclusive_scan_i32(C.lenp() + r0, r1 - r0, C.begp() + r0,
                                   w.tmp.as<int64_t>(), running, s);
-        int64_t cs[32];
+        int64_t cs[8 * kClasses];
         SFN_HIP(hipMemcpyAsync(cs, w.cstat.get(), sizeof(cs), hipMemcpyDeviceToHost, s));
         const int64_t end = read_scalar(C.begp() + r1, s);
-        for (int cls = 3; cls >= 1; --cls) {
+        {
+            float mm = 0.f;
+            SFN_HIP(hipEventElapsedTime(&mm, w.ev[0], w.ev[1]));
+            w.merge_ms += mm;
+        }
+        // event pairs bracketing the numeric launches: class 4 ev[1]..ev[2],
+        // class 3 ev[2]..ev[3], class 2 ev[3]..ev[4], class 1 ev[4]..ev[5]
+        const int evb[kClasses] = {0, 4, 3, 2, 1};
+        for (int cls = 4; cls >= 1; --cls) {
             float ms = 0.f;
-            SFN_HIP(hipEventElapsedTime(&ms, w.ev[3 - cls], w.ev[4 - cls]));
+            SFN_HIP(hipEventElapsedTime(&ms, w.ev[evb[cls]], w.ev[evb[cls] + 1]));
             w.spgemm_ms += ms;
             if (cnt[cls] <= 0) continue;
             Workspace::ClassStat &c = w.cls[sizeof(V) == 4 ? 1 : 0][cls];
+            const int64_t *q = cs + cls * 8;
             c.launches += 1;
-            c.rows += cnt[cls];
-            c.products += cs[cls * 8 + 1];
-            c.a_nnz += cs[cls * 8 + 2];
-            c.d_nnz += cs[cls * 8 + 3];
-            c.out += cs[cls * 8 + 4];
+            c.rows += cls == 4 ? 2 * (int64_t)cnt[cls] : cnt[cls];
+            c.products += q[1];
+            c.a_nnz += q[2];
+            c.d_nnz += q[3];
+            c.out += q[4];
             c.ms += ms;
-            // algorithmic bytes: one B entry per product, each A entry with its
-            // B-row descriptor, the D rows, the stored output, per-row data
+            // algorithmic bytes: each B entry gathered (once per row, or once per
+            // pair from the merged list), each A entry with its B-row descriptor,
+            // the D rows, the stored output, per-row data
             const double eb = (double)(sizeof(int32_t) + sizeof(V));
-            const double bytes = eb * (double)cs[cls * 8 + 1] + (eb + 12.0) * (double)cs[cls * 8 + 2] +
-                                 eb * (double)cs[cls * 8 + 3] + eb * (double)cs[cls * 8 + 4] +
-                                 40.0 * (double)cnt[cls];
+            const double gathered = cls == 4 ? (double)q[5] : (double)q[1];
+            const double a_side = cls == 4 ? (double)(4 + 2 * sizeof(V) + 12) * (double)q[2]
+                                           : (eb + 12.0) * (double)q[2];
+            const double rows_here = cls == 4 ? 2.0 * cnt[cls] : (double)cnt[cls];
+            const double bytes = eb * gathered + a_side + eb * (double)q[3] + eb * (double)q[4] +
+                                 40.0 * rows_here;
             c.bytes += bytes;
             w.spgemm_bytes += bytes;
         }

@@ -16,15 +16,17 @@ struct Workspace {
     size_t staging_limit;  // bytes of gapped product output per batch
     DevBuf lo, span, cap, work, capoff, workoff, tmp, bins, counts, cursor, stage_col, stage_val;
     DevBuf rs1, rs2, rs3, rs4, icnt, hist, tau, bstar, seg, red, flag, zero_b;
-    DevBuf cstat;
+    DevBuf cstat, mk, m0, m1, mlen, cnext;
     const uint8_t *row_skip = nullptr;  // optional row mask for products (serving)
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool pairing = true;                // wide rows computed in pairs (i, i+1)
+    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     // accumulated product statistics, in total and per row class (kernel tile)
     struct ClassStat {
         int64_t launches = 0, rows = 0, products = 0, a_nnz = 0, d_nnz = 0, out = 0;
         double ms = 0.0, bytes = 0.0;
     };
-    ClassStat cls[2][4];  // [FP64, FP32][row class]
+    ClassStat cls[2][kClasses];  // [FP64, FP32][row class]
+    double merge_ms = 0.0;
     int64_t products = 0;
     double spgemm_ms = 0.0;
     double spgemm_bytes = 0.0;

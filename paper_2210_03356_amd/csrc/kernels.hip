@@ -316,41 +316,53 @@ __global__ void k_plan(MatView<V> A, MatView<V> B, MatView<V> D, int diag, int64
 
 constexpr int kBinThreads = 256;
 
+// Row classes: 0 empty, 1 small window, 2 mid window, 3 wide rows swept in
+// 8192-column (FP64) windows, 4 leaders of pairs (i, i+1) of wide rows that are
+// computed together (rows i+1 of pairs get no class of their own).
+__device__ __forceinline__ int row_class(const int32_t *span, const int64_t *work, int64_t i,
+                                         int small_tile, int mid_tile) {
+    const int sp = span[i];
+    if (sp == 0) return 0;
+    if (sp <= small_tile && work[i] <= (int64_t)8 * small_tile) return 1;
+    if (sp <= mid_tile) return 2;
+    return 3;
+}
+
 __global__ __launch_bounds__(kBinThreads) void k_bin_rows(
     const int32_t *span, const int64_t *work, int64_t r0, int64_t r1, int small_tile,
-    int mid_tile, int32_t *bins, int64_t bin_stride, int32_t *counts, int32_t *out_len,
-    double *sq_prod, double *sq_out, const int32_t *a_len, const int32_t *d_len,
-    int64_t *cstat) {
-    __shared__ int wc[kBinThreads / kWave][4];
-    __shared__ int base[4];
-    __shared__ unsigned long long bsum[4][3];
-    if (threadIdx.x < 12) bsum[threadIdx.x / 3][threadIdx.x % 3] = 0ull;
+    int mid_tile, int pairing, int32_t *bins, int64_t bin_stride, int32_t *counts,
+    int32_t *out_len, double *sq_prod, double *sq_out, const int32_t *a_len,
+    const int32_t *d_len, int64_t *cstat) {
+    __shared__ int wc[kBinThreads / kWave][kClasses];
+    __shared__ int base[kClasses];
+    __shared__ unsigned long long bsum[kClasses][3];
+    if (threadIdx.x < 3 * kClasses) bsum[threadIdx.x / 3][threadIdx.x % 3] = 0ull;
     const int64_t i = r0 + (int64_t)blockIdx.x * kBinThreads + threadIdx.x;
     int cls = -1;
     if (i < r1) {
-        const int sp = span[i];
-        if (sp == 0) {
-            cls = 0;
+        cls = row_class(span, work, i, small_tile, mid_tile);
+        if (cls == 0) {
             out_len[i] = 0;
             if (sq_prod) sq_prod[i] = 0.0;
             if (sq_out) sq_out[i] = 0.0;
-        } else if (sp <= small_tile && work[i] <= (int64_t)8 * small_tile) {
-            cls = 1;
-        } else if (sp <= mid_tile) {
-            cls = 2;
-        } else {
-            cls = 3;
+        } else if (cls == 3 && pairing) {
+            // pairs (i, i+1) with i - r0 even, both wide
+            if (((i - r0) & 1) == 0) {
+                if (i + 1 < r1 && row_class(span, work, i + 1, small_tile, mid_tile) == 3) cls = 4;
+            } else if (row_class(span, work, i - 1, small_tile, mid_tile) == 3) {
+                cls = -1;  // computed with its leader i - 1
+            }
         }
     }
     const int lane = lane_id(), w = wave_id();
     int rank = 0;
-    for (int c = 1; c < 4; ++c) {
+    for (int c = 1; c < kClasses; ++c) {
         const uint64_t m = __ballot(cls == c);
         if (cls == c) rank = lanes_below(m);
         if (lane == 0) wc[w][c] = __popcll(m);
     }
     __syncthreads();
-    if (threadIdx.x < 4 && threadIdx.x > 0) {
+    if (threadIdx.x < kClasses && threadIdx.x > 0) {
         int t = 0;
         for (int q = 0; q < kBinThreads / kWave; ++q) t += wc[q][threadIdx.x];
         base[threadIdx.x] = t ? atomicAdd(&counts[threadIdx.x], t) : 0;
@@ -360,15 +372,54 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_rows(
         int off = base[cls] + rank;
         for (int q = 0; q < w; ++q) off += wc[q][cls];
         bins[(int64_t)cls * bin_stride + off] = (int32_t)i;
-        atomicAdd(&bsum[cls][0], (unsigned long long)work[i]);
-        atomicAdd(&bsum[cls][1], (unsigned long long)a_len[i]);
-        if (d_len) atomicAdd(&bsum[cls][2], (unsigned long long)d_len[i]);
+        const int nr = cls == 4 ? 2 : 1;
+        for (int r = 0; r < nr; ++r) {
+            atomicAdd(&bsum[cls][0], (unsigned long long)work[i + r]);
+            atomicAdd(&bsum[cls][1], (unsigned long long)a_len[i + r]);
+            if (d_len) atomicAdd(&bsum[cls][2], (unsigned long long)d_len[i + r]);
+        }
     }
     __syncthreads();
-    if (cstat && threadIdx.x >= 3 && threadIdx.x < 12) {
+    if (cstat && threadIdx.x >= 3 && threadIdx.x < 3 * kClasses) {
         const int c = threadIdx.x / 3, f = threadIdx.x % 3;
         if (bsum[c][f]) atomicAdd((unsigned long long *)&cstat[c * 8 + 1 + f], bsum[c][f]);
     }
+}
+
+// Merged A-row list of a pair (i, i+1): union of the two sorted column lists
+// with both coefficients (0 where a row has no entry), stored in the index
+// range of the two rows in A (compact CSR: the pair occupies [beg[i],
+// beg[i] + len[i] + len[i+1]) and the union is not longer).  One thread per
+// pair, a sequential two-pointer merge.  Also counts the B entries the pair
+// gathers (sum of nnz(B_k) over the union) into *gathered.
+template <typename V>
+__global__ void k_merge_pairs(const int32_t *pairs, int npairs, MatView<V> A, MatView<V> B,
+                              int32_t *mk, V *m0, V *m1, int32_t *mlen,
+                              unsigned long long *gathered) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long g = 0;
+    if (p < npairs) {
+        const int i = pairs[p];
+        int64_t pi = A.beg[i], pj = A.beg[i + 1];
+        const int64_t ei = pi + A.len[i], ej = pj + A.len[i + 1];
+        const int64_t o0 = A.beg[i];
+        int64_t o = o0;
+        while (pi < ei || pj < ej) {
+            const int ki = pi < ei ? A.col[pi] : INT_MAX;
+            const int kj = pj < ej ? A.col[pj] : INT_MAX;
+            int k;
+            V a0 = V(0), a1 = V(0);
+            if (ki < kj) { k = ki; a0 = A.val[pi++]; }
+            else if (kj < ki) { k = kj; a1 = A.val[pj++]; }
+            else { k = ki; a0 = A.val[pi++]; a1 = A.val[pj++]; }
+            mk[o] = k; m0[o] = a0; m1[o] = a1;
+            g += (unsigned long long)B.len[k];
+            ++o;
+        }
+        mlen[i] = (int32_t)(o - o0);
+    }
+    g = wave_sum(g);
+    if (gathered && lane_id() == 0 && g) atomicAdd(gathered, g);
 }
 
 // ---------------------------------------------------------------------------
@@ -379,7 +430,7 @@ __global__ __launch_bounds__(NT) void k_spgemm(
     const int32_t *__restrict__ rows, MatView<V> A, MatView<V> B, MatView<V> D, V coef,
     V dcoef, V diag, const int32_t *__restrict__ row_lo, const int32_t *__restrict__ row_span,
     const int64_t *__restrict__ off, int64_t base, int32_t *__restrict__ out_col,
-    V *__restrict__ out_val, int32_t *__restrict__ out_len, int32_t *__restrict__ cursor,
+    V *__restrict__ out_val, int32_t *__restrict__ out_len, int32_t *__restrict__ cursor, int32_t *__restrict__ cnext,
     double *__restrict__ sq_prod, double *__restrict__ sq_out, int64_t *__restrict__ out_count) {
     constexpr int NW = NT / kWave;
     constexpr int REG = T / NW;  // LDS slots owned by each wave in the epilogue
@@ -412,7 +463,7 @@ __global__ __launch_bounds__(NT) void k_spgemm(
         // holds entry q's B-row descriptor, broadcast through readlane
         for (int t0 = wave * kWave; t0 < alen; t0 += NW * kWave) {
             const int t = t0 + lane;
-            int bl = 0, cur = 0;
+            int bl = 0, cur = 0, nc = INT_MIN;
             int64_t bb = 0;
             V a = V(0);
             if (t < alen) {
@@ -421,13 +472,14 @@ __global__ __launch_bounds__(NT) void k_spgemm(
                 a = coef * A.val[pa];
                 bb = B.beg[k];
                 bl = B.len[k];
-                if (!first) cur = cursor[pa];
+                if (!first) { cur = cursor[pa]; nc = cnext[pa]; }
             }
             const int cnt = min(kWave, alen - t0);
             for (int q = 0; q < cnt; ++q) {
                 const int blq = rl_i32(bl, q);
                 int p = rl_i32(cur, q);
-                if (p < blq) {
+                // B rows with nothing left in this window are skipped without a load
+                if (p < blq && rl_i32(nc, q) < whi) {
                     const int64_t bbq = rl_i64(bb, q);
                     const V aq = rl_val(a, q);
                     // kUnroll chunks of 64 entries in flight per wave; B rows
@@ -454,12 +506,21 @@ __global__ __launch_bounds__(NT) void k_spgemm(
                             got += __popcll(__ballot(in));
                         }
                         p += got;
-                        if (got < kUnroll * kWave) break;
+                        if (got < kUnroll * kWave) {
+                            // column of the first entry beyond the window, for the next one
+                            int cs = INT_MAX;
+#pragma unroll
+                            for (int u = 0; u < kUnroll; ++u)
+                                if (u == (got >> 6)) cs = c[u];
+                            const int nxt = __shfl(cs, got & (kWave - 1));
+                            if (multi && lane == q) nc = nxt;
+                            break;
+                        }
                     }
                 }
                 if (multi && lane == q) cur = p;
             }
-            if (multi && t < alen) cursor[abeg + t] = cur;
+            if (multi && t < alen) { cursor[abeg + t] = cur; cnext[abeg + t] = nc; }
         }
         __syncthreads();
 
@@ -524,6 +585,184 @@ __global__ __launch_bounds__(NT) void k_spgemm(
         if (sq_prod) sq_prod[i] = a;
         if (sq_out) sq_out[i] = b;
         if (out_count) atomicAdd((unsigned long long *)out_count, (unsigned long long)written);
+    }
+}
+
+// Pair variant for wide rows: one workgroup computes output rows i and i+1
+// from their merged A list.  Each chunk of a B row is gathered once and added
+// into both rows' LDS windows (two accumulators of `tile` columns), so the
+// gathered B bytes of the two rows are paid once -- neighbouring rows of these
+// matrices reference almost the same rows of B.
+template <typename V, int T, int NT>
+__global__ __launch_bounds__(NT) void k_spgemm_pair(
+    const int32_t *__restrict__ rows, const int32_t *__restrict__ mk, const V *__restrict__ m0,
+    const V *__restrict__ m1, const int32_t *__restrict__ mlen, MatView<V> A, MatView<V> B,
+    MatView<V> D, V coef, V dcoef, V diag, const int32_t *__restrict__ row_lo,
+    const int32_t *__restrict__ row_span, const int64_t *__restrict__ off, int64_t base,
+    int32_t *__restrict__ out_col, V *__restrict__ out_val, int32_t *__restrict__ out_len,
+    int32_t *__restrict__ cursor, int32_t *__restrict__ cnext, double *__restrict__ sq_prod, double *__restrict__ sq_out,
+    int64_t *__restrict__ out_count) {
+    constexpr int NW = NT / kWave;
+    constexpr int REG = T / NW;
+    static_assert(T % (NW * kWave) == 0, "tile must split evenly over the waves");
+    __shared__ V acc[2][T];
+    __shared__ int wcnt[NW];
+    __shared__ double wsum[4][NW];
+
+    const int lane = lane_id(), wave = wave_id();
+    const int i = rows[xcd_row(blockIdx.x, gridDim.x)];
+    const int lo0 = row_lo[i], sp0 = row_span[i], lo1 = row_lo[i + 1], sp1 = row_span[i + 1];
+    const int lo = min(lo0, lo1);
+    const int hi = max(lo0 + sp0, lo1 + sp1);
+    const int64_t mbeg = A.beg[i];
+    const int ml = mlen[i];
+    const bool multi = hi - lo > T;
+    const bool has_d = D.len != nullptr;
+
+    int written[2] = {0, 0};
+    double sqp[2] = {0.0, 0.0}, sqo[2] = {0.0, 0.0};
+    for (int wlo = lo; wlo < hi; wlo += T) {
+        const int nsl = min(T, hi - wlo);
+        const int whi = wlo + nsl;
+        const bool first = (wlo == lo);
+        for (int s = threadIdx.x; s < nsl; s += NT) { acc[0][s] = V(0); acc[1][s] = V(0); }
+        __syncthreads();
+
+        for (int t0 = wave * kWave; t0 < ml; t0 += NW * kWave) {
+            const int t = t0 + lane;
+            int bl = 0, cur = 0, nc = INT_MIN;
+            int64_t bb = 0;
+            V a0 = V(0), a1 = V(0);
+            if (t < ml) {
+                const int64_t pa = mbeg + t;
+                const int k = mk[pa];
+                a0 = coef * m0[pa];
+                a1 = coef * m1[pa];
+                bb = B.beg[k];
+                bl = B.len[k];
+                if (!first) { cur = cursor[pa]; nc = cnext[pa]; }
+            }
+            const int cnt = min(kWave, ml - t0);
+            for (int q = 0; q < cnt; ++q) {
+                const int blq = rl_i32(bl, q);
+                int p = rl_i32(cur, q);
+                if (p < blq && rl_i32(nc, q) < whi) {
+                    const int64_t bbq = rl_i64(bb, q);
+                    const V a0q = rl_val(a0, q), a1q = rl_val(a1, q);
+                    const bool u0 = a0q != V(0), u1 = a1q != V(0);
+                    while (true) {
+                        int c[kUnroll];
+                        V bv[kUnroll];
+#pragma unroll
+                        for (int u = 0; u < kUnroll; ++u) {
+                            const int pos = p + u * kWave + lane;
+                            c[u] = INT_MAX;
+                            bv[u] = V(0);
+                            if (pos < blq) {
+                                c[u] = B.col[bbq + pos];
+                                bv[u] = B.val[bbq + pos];
+                            }
+                        }
+                        int got = 0;
+#pragma unroll
+                        for (int u = 0; u < kUnroll; ++u) {
+                            const bool in = c[u] < whi;
+                            if (in) {
+                                if (u0) atomicAdd(&acc[0][c[u] - wlo], a0q * bv[u]);
+                                if (u1) atomicAdd(&acc[1][c[u] - wlo], a1q * bv[u]);
+                            }
+                            got += __popcll(__ballot(in));
+                        }
+                        p += got;
+                        if (got < kUnroll * kWave) {
+                            int cs = INT_MAX;
+#pragma unroll
+                            for (int u = 0; u < kUnroll; ++u)
+                                if (u == (got >> 6)) cs = c[u];
+                            const int nxt = __shfl(cs, got & (kWave - 1));
+                            if (multi && lane == q) nc = nxt;
+                            break;
+                        }
+                    }
+                }
+                if (multi && lane == q) cur = p;
+            }
+            if (multi && t < ml) { cursor[mbeg + t] = cur; cnext[mbeg + t] = nc; }
+        }
+        __syncthreads();
+
+        if (sq_prod) {
+            for (int s = threadIdx.x; s < nsl; s += NT) {
+                const double v0 = as_f64(acc[0][s]), v1 = as_f64(acc[1][s]);
+                sqp[0] += v0 * v0;
+                sqp[1] += v1 * v1;
+            }
+            __syncthreads();
+        }
+        if (has_d) {
+            for (int r = 0; r < 2; ++r) {
+                const int dl = D.len[i + r];
+                const int64_t db = D.beg[i + r];
+                for (int q = threadIdx.x; q < dl; q += NT) {
+                    const int c = D.col[db + q];
+                    if (c >= wlo && c < whi) acc[r][c - wlo] += dcoef * D.val[db + q];
+                }
+            }
+            __syncthreads();
+        }
+        if (diag != V(0) && threadIdx.x < 2) {
+            const int r = threadIdx.x, ir = i + r;
+            if (ir >= wlo && ir < whi) acc[r][ir - wlo] += diag;
+        }
+        __syncthreads();
+
+        for (int r = 0; r < 2; ++r) {
+            const int64_t obase = off[i + r] - base;
+            const int rbeg = wave * REG;
+            int cw = 0;
+            for (int s0 = rbeg; s0 < rbeg + REG && s0 < nsl; s0 += kWave) {
+                const int s = s0 + lane;
+                const V v = s < nsl ? acc[r][s] : V(0);
+                cw += __popcll(__ballot(v != V(0)));
+            }
+            if (lane == 0) wcnt[wave] = cw;
+            __syncthreads();
+            int o = written[r], tot = 0;
+            for (int w = 0; w < NW; ++w) {
+                const int c = wcnt[w];
+                if (w < wave) o += c;
+                tot += c;
+            }
+            for (int s0 = rbeg; s0 < rbeg + REG && s0 < nsl; s0 += kWave) {
+                const int s = s0 + lane;
+                const V v = s < nsl ? acc[r][s] : V(0);
+                const bool nz = v != V(0);
+                const uint64_t m = __ballot(nz);
+                if (nz) {
+                    const int64_t pos = obase + o + lanes_below(m);
+                    out_col[pos] = wlo + s;
+                    out_val[pos] = v;
+                    sqo[r] += as_f64(v) * as_f64(v);
+                }
+                o += __popcll(m);
+            }
+            written[r] += tot;
+            __syncthreads();
+        }
+    }
+    for (int r = 0; r < 2; ++r) {
+        const double a = wave_sum(sqp[r]), b = wave_sum(sqo[r]);
+        if (lane == 0) { wsum[2 * r][wave] = a; wsum[2 * r + 1][wave] = b; }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        const int r = threadIdx.x;
+        double a = 0.0, b = 0.0;
+        for (int w = 0; w < NW; ++w) { a += wsum[2 * r][w]; b += wsum[2 * r + 1][w]; }
+        out_len[i + r] = written[r];
+        if (sq_prod) sq_prod[i + r] = a;
+        if (sq_out) sq_out[i + r] = b;
+        if (out_count) atomicAdd((unsigned long long *)out_count, (unsigned long long)written[r]);
     }
 }
 
@@ -934,59 +1173,100 @@ void launch_fill_u8(uint8_t *p, int64_t lo, int64_t hi, uint8_t v, hipStream_t s
 }
 
 void launch_bin_rows(const int32_t *span, const int64_t *work, int64_t r0, int64_t r1,
-                     int small_tile, int mid_tile, int32_t *bins, int64_t bin_stride,
+                     int small_tile, int mid_tile, int pairing, int32_t *bins, int64_t bin_stride,
                      int32_t *counts, int32_t *out_len, double *sq_prod, double *sq_out,
                      const int32_t *a_len, const int32_t *d_len, int64_t *cstat,
                      hipStream_t s) {
     if (r1 <= r0) return;
     k_bin_rows<<<blocks_for(r1 - r0, kBinThreads), kBinThreads, 0, s>>>(
-        span, work, r0, r1, small_tile, mid_tile, bins, bin_stride, counts, out_len, sq_prod,
-        sq_out, a_len, d_len, cstat);
+        span, work, r0, r1, small_tile, mid_tile, pairing, bins, bin_stride, counts, out_len,
+        sq_prod, sq_out, a_len, d_len, cstat);
 }
 
 BinCfg bin_config(int cls, int value_bytes) {
     switch (cls) {
         case 1: return {512, 64};
         case 2: return {4096, 256};
+        case 4: return {value_bytes == 8 ? 4096 : 8192, 512};
         default: return {value_bytes == 8 ? 8192 : 16384, 512};
     }
 }
 
 template <typename V>
+void launch_merge_pairs(const int32_t *pairs, int npairs, MatView<V> A, MatView<V> B, int32_t *mk,
+                        V *m0, V *m1, int32_t *mlen, int64_t *gathered, hipStream_t s) {
+    if (npairs <= 0) return;
+    k_merge_pairs<V><<<blocks_for(npairs, 64), 64, 0, s>>>(
+        pairs, npairs, A, B, mk, m0, m1, mlen, (unsigned long long *)gathered);
+}
+template void launch_merge_pairs<double>(const int32_t *, int, MatView<double>, MatView<double>,
+                                         int32_t *, double *, double *, int32_t *, int64_t *,
+                                         hipStream_t);
+template void launch_merge_pairs<float>(const int32_t *, int, MatView<float>, MatView<float>,
+                                        int32_t *, float *, float *, int32_t *, int64_t *,
+                                        hipStream_t);
+
+template <typename V>
+void launch_spgemm_pair(const int32_t *pairs, int npairs, const int32_t *mk, const V *m0,
+                        const V *m1, const int32_t *mlen, MatView<V> A, MatView<V> B, MatView<V> D,
+                        double coef, double dcoef, double diag, const int32_t *lo,
+                        const int32_t *span, int64_t base, const int64_t *off, int32_t *out_col,
+                        V *out_val, int32_t *out_len, int32_t *cursor, int32_t *cnext,
+                        double *sq_prod, double *sq_out, int64_t *out_count, hipStream_t s) {
+    if (npairs <= 0) return;
+    k_spgemm_pair<V, (sizeof(V) == 8 ? 4096 : 8192), 512><<<npairs, 512, 0, s>>>(
+        pairs, mk, m0, m1, mlen, A, B, D, (V)coef, (V)dcoef, (V)diag, lo, span, off, base, out_col,
+        out_val, out_len, cursor, cnext, sq_prod, sq_out, out_count);
+}
+template void launch_spgemm_pair<double>(const int32_t *, int, const int32_t *, const double *,
+                                         const double *, const int32_t *, MatView<double>,
+                                         MatView<double>, MatView<double>, double, double, double,
+                                         const int32_t *, const int32_t *, int64_t,
+                                         const int64_t *, int32_t *, double *, int32_t *,
+                                         int32_t *, int32_t *, double *, double *, int64_t *,
+                                         hipStream_t);
+template void launch_spgemm_pair<float>(const int32_t *, int, const int32_t *, const float *,
+                                        const float *, const int32_t *, MatView<float>,
+                                        MatView<float>, MatView<float>, double, double, double,
+                                        const int32_t *, const int32_t *, int64_t, const int64_t *,
+                                        int32_t *, float *, int32_t *, int32_t *, int32_t *,
+                                        double *, double *, int64_t *, hipStream_t);
+
+template <typename V>
 void launch_spgemm(int cls, const int32_t *rows, int nrows, MatView<V> A, MatView<V> B,
                    MatView<V> D, double coef, double dcoef, double diag, const int32_t *lo,
                    const int32_t *span, int64_t base, const int64_t *off, int32_t *out_col,
-                   V *out_val, int32_t *out_len, int32_t *cursor, double *sq_prod,
+                   V *out_val, int32_t *out_len, int32_t *cursor, int32_t *cnext, double *sq_prod,
                    double *sq_out, int64_t *out_count, hipStream_t s) {
     if (nrows <= 0) return;
     const V c = (V)coef, d = (V)diag, dc = (V)dcoef;
     switch (cls) {
         case 1:
             k_spgemm<V, 512, 64><<<nrows, 64, 0, s>>>(rows, A, B, D, c, dc, d, lo, span, off, base,
-                                                      out_col, out_val, out_len, cursor, sq_prod,
-                                                      sq_out, out_count);
+                                                      out_col, out_val, out_len, cursor, cnext,
+                                                      sq_prod, sq_out, out_count);
             break;
         case 2:
             k_spgemm<V, 4096, 256><<<nrows, 256, 0, s>>>(rows, A, B, D, c, dc, d, lo, span, off, base,
                                                          out_col, out_val, out_len, cursor,
-                                                         sq_prod, sq_out, out_count);
+                                                         cnext, sq_prod, sq_out, out_count);
             break;
         default:
             k_spgemm<V, (sizeof(V) == 8 ? 8192 : 16384), 512><<<nrows, 512, 0, s>>>(
                 rows, A, B, D, c, dc, d, lo, span, off, base, out_col, out_val, out_len, cursor,
-                sq_prod, sq_out, out_count);
+                cnext, sq_prod, sq_out, out_count);
             break;
     }
 }
 template void launch_spgemm<double>(int, const int32_t *, int, MatView<double>, MatView<double>,
                                     MatView<double>, double, double, double, const int32_t *,
                                     const int32_t *, int64_t, const int64_t *, int32_t *, double *,
-                                    int32_t *, int32_t *, double *, double *, int64_t *,
+                                    int32_t *, int32_t *, int32_t *, double *, double *, int64_t *,
                                     hipStream_t);
 template void launch_spgemm<float>(int, const int32_t *, int, MatView<float>, MatView<float>,
                                    MatView<float>, double, double, double, const int32_t *,
                                    const int32_t *, int64_t, const int64_t *, int32_t *, float *,
-                                   int32_t *, int32_t *, double *, double *, int64_t *,
+                                   int32_t *, int32_t *, int32_t *, double *, double *, int64_t *,
                                    hipStream_t);
 
 template <typename V>

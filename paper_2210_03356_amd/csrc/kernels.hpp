@@ -13,6 +13,7 @@
 namespace sfn {
 
 constexpr int kBuckets = 2048;   // histogram length (buckets 0 .. kBucketTop used)
+constexpr int kClasses = 5;      // row classes of the numeric product (0 = empty)
 constexpr int kBucketTop = 2033; // |x| >= 1: never dropped
 
 template <typename V>
@@ -68,24 +69,39 @@ void launch_plan(MatView<V> A, MatView<V> B, MatView<V> D, int diag, int64_t r0,
 
 // Row classes: 0 empty, 1..3 tiles.  Writes row lists per class (bins[c] holds
 // up to r1-r0 rows), counts into counts[4] (device), and len=0 for empty rows.
+// Row classes 1..3 by column span (and work), class 4 = leaders i of pairs
+// (i, i+1) of wide rows (when `pairing`; rows i+1 are then listed nowhere).
 // cstat (optional): per class c, cstat[8c+1] += products, [8c+2] += nnz of the
 // A rows, [8c+3] += nnz of the D rows (d_len may be null).
 void launch_bin_rows(const int32_t *span, const int64_t *work, int64_t r0, int64_t r1,
-                     int small_tile, int mid_tile, int32_t *bins, int64_t bin_stride,
+                     int small_tile, int mid_tile, int pairing, int32_t *bins, int64_t bin_stride,
                      int32_t *counts, int32_t *out_len, double *sq_prod, double *sq_out,
                      const int32_t *a_len, const int32_t *d_len, int64_t *cstat,
                      hipStream_t s);
+// Pairs: merged (k, a_i, a_{i+1}) lists stored in the index range of rows i, i+1
+// of A (A must be compact); *gathered += sum of nnz(B_k) over the merged lists.
+template <typename V>
+void launch_merge_pairs(const int32_t *pairs, int npairs, MatView<V> A, MatView<V> B, int32_t *mk,
+                        V *m0, V *m1, int32_t *mlen, int64_t *gathered, hipStream_t s);
+template <typename V>
+void launch_spgemm_pair(const int32_t *pairs, int npairs, const int32_t *mk, const V *m0,
+                        const V *m1, const int32_t *mlen, MatView<V> A, MatView<V> B, MatView<V> D,
+                        double coef, double dcoef, double diag, const int32_t *lo,
+                        const int32_t *span, int64_t base, const int64_t *off, int32_t *out_col,
+                        V *out_val, int32_t *out_len, int32_t *cursor, int32_t *cnext,
+                        double *sq_prod, double *sq_out, int64_t *out_count, hipStream_t s);
 
 // Numeric product for the rows listed in `rows` (class cfg).  Row i writes
 // at out_col/out_val[off[i] - base .. ), out_len[i], sq_prod[i] (sum of squares
 // of coef*A*B) and sq_out[i] (sum of squares of the stored output), when the
-// latter two pointers are non-null.  cursor: int32 scratch per nonzero of A.
+// latter two pointers are non-null.  cursor, cnext: int32 scratch per nonzero of
+// A (sweep position in B_k and the column found there, for multi-window rows).
 // out_count (optional) accumulates the number of stored entries.
 template <typename V>
 void launch_spgemm(int cls, const int32_t *rows, int nrows, MatView<V> A, MatView<V> B,
                    MatView<V> D, double coef, double dcoef, double diag, const int32_t *lo,
                    const int32_t *span, int64_t base, const int64_t *off, int32_t *out_col,
-                   V *out_val, int32_t *out_len, int32_t *cursor, double *sq_prod,
+                   V *out_val, int32_t *out_len, int32_t *cursor, int32_t *cnext, double *sq_prod,
                    double *sq_out, int64_t *out_count, hipStream_t s);
 BinCfg bin_config(int cls, int value_bytes);
 

@@ -1,5 +1,6 @@
 // Device memory for libsignfn: caching pool, allocator hooks, grow-only buffers.
 #include <algorithm>
+#include <iterator>
 
 #include "runtime.hpp"
 
@@ -8,67 +9,132 @@ namespace sfn {
 namespace {
 thread_local std::string g_last_error;
 
-size_t round_bytes(size_t b) {
-    if (b == 0) b = 1;
-    const size_t big = size_t(2) << 20;
-    if (b >= big) return (b + big - 1) / big * big;
-    return (b + 255) / 256 * 256;
-}
 }  // namespace
 
 void set_last_error(const std::string &m) { g_last_error = m; }
 const char *last_error() { return g_last_error.c_str(); }
 
 Pool &Pool::instance() {
-    static Pool *p = new Pool();  // never destroyed: blocks live until process exit
+    static Pool *p = new Pool();  // never destroyed: segments live until process exit
     return *p;
 }
 
-void *Pool::get(size_t bytes) {
-    const size_t b = round_bytes(bytes);
-    {
-        std::lock_guard<std::mutex> lk(mu_);
-        auto it = free_.lower_bound(b);
-        if (it != free_.end() && it->first <= 2 * b) {
-            void *p = it->second;
-            cached_ -= it->first;
+namespace {
+constexpr size_t kAlign = 512;                     // sub-allocation granularity
+constexpr size_t kMinSplit = size_t(1) << 20;      // smallest remainder kept as a block
+constexpr size_t kSegment = size_t(2) << 30;       // segment size for small requests
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+}  // namespace
+
+void Pool::insert_free(Block *b) {
+    b->free = true;
+    free_.emplace(b->size, b);
+    cached_ += b->size;
+}
+
+void Pool::erase_free(Block *b) {
+    auto range = free_.equal_range(b->size);
+    for (auto it = range.first; it != range.second; ++it)
+        if (it->second == b) {
             free_.erase(it);
-            return p;
+            break;
         }
+    cached_ -= b->size;
+    b->free = false;
+}
+
+// Free whole segments with no used block (largest first) until `need` bytes
+// have been returned, or none is left.  Caller holds mu_.
+bool Pool::release_free_segments(size_t need) {
+    size_t got = 0;
+    for (;;) {
+        int best = -1;
+        for (int sgi = 0; sgi < (int)segs_.size(); ++sgi) {
+            Block *h = seg_head_[sgi];
+            if (!segs_[sgi].first || !h || !h->free || h->next) continue;  // not a single free block
+            if (best < 0 || segs_[sgi].second > segs_[best].second) best = sgi;
+        }
+        if (best < 0) return got > 0;
+        Block *h = seg_head_[best];
+        erase_free(h);
+        (void)hipFree(segs_[best].first);
+        got += segs_[best].second;
+        segs_[best].first = nullptr;
+        seg_head_[best] = nullptr;
+        delete h;
+        if (got >= need) return true;
     }
-    void *p = nullptr;
-    hipError_t e = hipMalloc(&p, b);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        trim();
-        e = hipMalloc(&p, b);
+}
+
+void *Pool::get(size_t bytes) {
+    const size_t b = align_up(bytes ? bytes : 1, kAlign);
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = free_.lower_bound(b);
+    if (it == free_.end()) {
+        // a new segment: exactly the request when large, else a shared segment
+        const size_t want = b >= kSegment ? align_up(b, size_t(2) << 20) : kSegment;
+        char *p = nullptr;
+        hipError_t e = hipMalloc((void **)&p, want);
+        while (e != hipSuccess) {
+            (void)hipGetLastError();
+            if (!release_free_segments(want)) break;
+            e = hipMalloc((void **)&p, want);
+        }
         if (e != hipSuccess) {
             (void)hipGetLastError();
-            throw Error(SIGN_ENOMEM, "device allocation of " + std::to_string(b) + " bytes failed");
+            throw Error(SIGN_ENOMEM, "device allocation of " + std::to_string(want) +
+                                         " bytes failed");
         }
+        Block *blk = new Block{p, want, false, nullptr, nullptr, (int)segs_.size()};
+        segs_.push_back({p, want});
+        seg_head_.push_back(blk);
+        insert_free(blk);
+        it = free_.lower_bound(b);
     }
-    std::lock_guard<std::mutex> lk(mu_);
-    size_[p] = b;
-    return p;
+    Block *blk = it->second;
+    erase_free(blk);
+    if (blk->size - b >= kMinSplit) {  // split off the tail as a free block
+        Block *rest = new Block{blk->ptr + b, blk->size - b, false, blk, blk->next, blk->seg};
+        if (blk->next) blk->next->prev = rest;
+        blk->next = rest;
+        blk->size = b;
+        insert_free(rest);
+    }
+    used_[blk->ptr] = blk;
+    return blk->ptr;
 }
 
 void Pool::put(void *p) {
     if (!p) return;
     std::lock_guard<std::mutex> lk(mu_);
-    auto it = size_.find(p);
-    if (it == size_.end()) return;
-    free_.emplace(it->second, p);
-    cached_ += it->second;
+    auto u = used_.find(p);
+    if (u == used_.end()) return;
+    Block *blk = u->second;
+    used_.erase(u);
+    // coalesce with free neighbours
+    if (blk->next && blk->next->free) {
+        Block *n = blk->next;
+        erase_free(n);
+        blk->size += n->size;
+        blk->next = n->next;
+        if (n->next) n->next->prev = blk;
+        delete n;
+    }
+    if (blk->prev && blk->prev->free) {
+        Block *pv = blk->prev;
+        erase_free(pv);
+        pv->size += blk->size;
+        pv->next = blk->next;
+        if (blk->next) blk->next->prev = pv;
+        delete blk;
+        blk = pv;
+    }
+    insert_free(blk);
 }
 
 void Pool::trim() {
     std::lock_guard<std::mutex> lk(mu_);
-    for (auto &kv : free_) {
-        (void)hipFree(kv.second);
-        size_.erase(kv.second);
-    }
-    free_.clear();
-    cached_ = 0;
+    release_free_segments(~size_t(0));
 }
 
 size_t Pool::cached_bytes() {

@@ -31,21 +31,37 @@ struct Error : std::runtime_error {
                                                  hipGetErrorString(e_));                  \
     } while (0)
 
-// Device memory: either the caller's hooks or a process-wide caching pool
-// (hipMalloc-backed, blocks reused by size; idle blocks only, since every
-// call synchronises its stream before handing its workspace back).
+// Device memory: either the caller's hooks or a process-wide pool.  The pool
+// takes large segments from hipMalloc and sub-allocates them best-fit, with
+// block splitting and coalescing of free neighbours, so that the growing and
+// shrinking matrices of repeated solves are served without further calls to
+// hipMalloc/hipFree (each of which maps or unmaps gigabytes).  Blocks handed
+// back are idle: every call synchronises its stream before returning its
+// workspace.
 class Pool {
   public:
     static Pool &instance();
     void *get(size_t bytes);
     void put(void *p);
-    void trim();
-    size_t cached_bytes();
+    void trim();             // return entirely free segments to the driver
+    size_t cached_bytes();   // free bytes held in segments
 
   private:
+    struct Block {
+        char *ptr;
+        size_t size;
+        bool free;
+        Block *prev, *next;  // address neighbours within the segment
+        int seg;
+    };
+    void insert_free(Block *b);
+    void erase_free(Block *b);
+    bool release_free_segments(size_t need);
     std::mutex mu_;
-    std::multimap<size_t, void *> free_;
-    std::unordered_map<void *, size_t> size_;
+    std::multimap<size_t, Block *> free_;
+    std::unordered_map<void *, Block *> used_;
+    std::vector<std::pair<char *, size_t>> segs_;  // base, size (nullptr once released)
+    std::vector<Block *> seg_head_;
     size_t cached_ = 0;
 };
 

@@ -308,3 +308,22 @@ def test_mixed_precision_matches_fp64_oracle(sf, name):
     r0 = sf.sign_ns(_dev(sf, A), sf.default_opts(precision=1, refine_steps=0, **kw))
     rel0 = sp.linalg.norm(r0.to_scipy() - S) / sp.linalg.norm(S)
     assert rel <= rel0
+
+
+def test_paired_rows_match_single_rows(sf, monkeypatch):
+    """Wide rows computed in pairs (one gather feeding two accumulators) give the
+    products of the one-row kernel, and both match the oracle."""
+    A = W.laplacian_2d(48, jitter=0.05, seed=2, m=8.0)
+    X = oracle.nsf(A, tol=1e-12)
+    Xc = W.Csr(n=A.n, indptr=X.indptr, indices=X.indices, data=X.data)
+    R = W.random_sparse(2304, mean_row=40, seed=9, powerlaw=False)   # odd/even mix of wide rows
+    for left, right in ((Xc, Xc), (R, Xc), (Xc, R)):
+        monkeypatch.setenv("SIGNFN_PAIR_ROWS", "1")
+        a = _check_product(sf, left, right, exact_pattern=False)
+        monkeypatch.setenv("SIGNFN_PAIR_ROWS", "0")
+        b = _check_product(sf, left, right, exact_pattern=False)
+        Pa, Pb = a.to_scipy(), b.to_scipy()
+        assert sp.linalg.norm(Pa - Pb) <= 1e-14 * sp.linalg.norm(Pb)
+    monkeypatch.setenv("SIGNFN_PAIR_ROWS", "1")
+    r = sf.sign_ns(_dev(sf, A), sf.default_opts(tol=1e-12))
+    assert sp.linalg.norm(r.to_scipy() - X.to_scipy()) / sp.linalg.norm(X.to_scipy()) <= 1e-10
