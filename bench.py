@@ -34,9 +34,19 @@ def kernel_hash() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def read_traffic(tile: int):
-    """Per-launch HBM bytes of the hot kernel from the committed counter summary."""
-    if not os.path.exists(TRAFFIC_FILE):
+def kernel_name(st, tile) -> str:
+    """Name and template arguments of the hottest numeric product kernel."""
+    v = "float" if st["hot_fp32"] else "double"
+    if st["hot_group"] > 1:
+        return f"k_spgemm_group<{v},{st['hot_group']},{tile},{st['hot_threads']}>"
+    return f"k_spgemm<{v},{tile},{st['hot_threads']}>"
+
+
+def read_traffic(st, config: str, precision: int):
+    """Per-launch HBM bytes (FETCH + WRITE, copy-calibrated) of the hot kernel from the
+    committed counter summary; None for other workloads or once the kernel source
+    differs from the one the counters were taken on."""
+    if config != "c2" or precision != 0 or not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
     for line in open(TRAFFIC_FILE):
@@ -45,7 +55,9 @@ def read_traffic(tile: int):
             vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256_16") != kernel_hash():
         return None
-    key = f"tile{tile}_hbm_bytes_per_launch"
+    key = ((f"group{st['hot_group']}_" if st["hot_group"] > 1 else "") +
+           ("f32_" if st["hot_fp32"] else "f64_") +
+           f"tile{st['hot_tile']}_hbm_bytes_per_launch")
     return float(vals[key]) if key in vals else None
 
 
@@ -225,6 +237,8 @@ def main():
     ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--grid", type=int, default=None, help="override the grid size")
     ap.add_argument("--precision", type=int, default=0)
+    ap.add_argument("--method", default="ns", choices=["ns", "newton"],
+                    help="filtered Newton-Schulz (Alg. 3.2.1) or filtered Newton (Alg. 3.1.1)")
     ap.add_argument("--filter-y", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
@@ -257,6 +271,7 @@ def main():
     if args.filter_y is not None:
         kw["filter_y"] = args.filter_y
     opts = sf.default_opts(precision=args.precision, **kw)
+    solve = sf.sign_newton if args.method == "newton" else sf.sign_ns
     dA = sf.DeviceCsr.from_host(A, device="cuda:0")
     torch.cuda.synchronize()
     print(f"# workload {args.config} n={A.n} nnz={A.nnz} opts={kw} precision={args.precision}",
@@ -274,7 +289,7 @@ def main():
         del x, y
 
     for w in range(args.warmup):
-        r = sf.sign_ns(dA, opts)
+        r = solve(dA, opts)
         print(f"# warmup {w}: {r.status} {r.stats()['seconds']:.3f} s", file=sys.stderr, flush=True)
         del r
     torch.cuda.synchronize()
@@ -283,7 +298,7 @@ def main():
     res = None
     t0 = time.perf_counter()
     for k in range(args.steps):
-        res = sf.sign_ns(dA, opts)
+        res = solve(dA, opts)
         st = res.stats()
         for key in agg:
             agg[key] += st[key]
@@ -333,7 +348,7 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.config, args.grid, A.n)
 
-    traffic = read_traffic(tile)
+    traffic = read_traffic(st, args.config, args.precision)
     line = {
         "metric": METRIC,
         "value": round(ms_per_step / 1e3, 4),
@@ -353,9 +368,10 @@ def main():
             "c3": "2D upwind conv-diff 512x512, beta*h, - 4 + 8*stagger",
             "c4": "3D 7-point 64^3 - 6 + U[-.5,.5] + 12*stagger"}[args.config],
             "n": A.n, "nnz": A.nnz, "tol": kw["tol"], "stop_rule": kw["stop_rule"],
-            "filter_y": kw["filter_y"], "precision": args.precision},
+            "filter_y": kw["filter_y"], "precision": args.precision, "method": args.method},
         "solves_per_s": round(1e3 / ms_per_step, 4),
         "iters": st["iters"],
+        "inner_steps": st["inner_steps"],
         "nnz_result": st["nnz"],
         "products": int(agg["products"] / max(args.steps, 1)),
         "spgemm_ms_per_step": round(agg["spgemm_ms"] / max(args.steps, 1), 2),
@@ -363,8 +379,7 @@ def main():
         if agg["spgemm_ms"] > 0 else None,
         "roofline": {
             "bound": "hbm",
-            "kernel": f"k_spgemm{'_pair' if st['hot_pair'] else ''}<"
-                      f"{'float' if st['hot_fp32'] else 'double'},{tile},{st['hot_threads']}>",
+            "kernel": kernel_name(st, tile),
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -109,7 +109,7 @@ typedef struct {
     int hot_tile;        /* LDS accumulator columns of that kernel */
     int hot_threads;     /* its workgroup size */
     int hot_fp32;        /* 1 if it is the FP32-value instantiation */
-    int hot_pair;        /* 1 if it is the paired-row kernel (rows i, i+1 together) */
+    int hot_group;       /* output rows per workgroup: 1, or 2 / 4 for the grouped-row kernel */
     int64_t hot_launches;/* its launches */
     double hot_ms;       /* its device time (HIP events on the call's stream) */
     double hot_bytes;    /* its algorithmic bytes */

@@ -15,10 +15,13 @@ constexpr int kMidTile = 4096;
 Workspace::Workspace(Allocator *a, size_t staging_bytes) : al(a), s(a->stream) {
     for (DevBuf *b : {&lo, &span, &cap, &work, &capoff, &workoff, &tmp, &bins, &counts, &cursor,
                       &stage_col, &stage_val, &rs1, &rs2, &rs3, &rs4, &icnt, &hist, &tau,
-                      &bstar, &seg, &red, &flag, &zero_b, &cstat, &mk, &m0, &m1, &mlen, &cnext})
+                      &bstar, &seg, &red, &flag, &zero_b, &cstat, &mk, &mv, &mlen, &cnext})
         b->bind(a);
-    const char *pe = std::getenv("SIGNFN_PAIR_ROWS");
-    pairing = !(pe && pe[0] == '0');
+    // rows per workgroup for wide rows: 1 (off), 2 or 4
+    if (const char *ge = std::getenv("SIGNFN_ROW_GROUP")) {
+        const int g = std::atoi(ge);
+        row_group = (g == 1 || g == 2 || g == 4) ? g : row_group;
+    }
     if (staging_bytes == 0) {
         // a quarter of the memory that is free or idle in the caching pool,
         // capped so that one reservation stays a modest share of HBM
@@ -48,9 +51,9 @@ void Workspace::hot_stats(sign_stats &st) const {
             if (cls[v][c].ms > cls[hv][h].ms) { hv = v; h = c; }
     const ClassStat &c = cls[hv][h];
     st.hot_tile = bin_config(h, hv ? 4 : 8).tile;
-    st.hot_threads = bin_config(h, hv ? 4 : 8).threads;
+    st.hot_threads = h == 4 ? 256 * row_group : bin_config(h, hv ? 4 : 8).threads;
     st.hot_fp32 = hv;
-    st.hot_pair = h == 4;
+    st.hot_group = h == 4 ? row_group : 1;
     st.hot_launches = c.launches;
     st.hot_ms = c.ms;
     st.hot_bytes = c.bytes;
@@ -139,13 +142,12 @@ void product(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D,
     w.bins.ensure(sizeof(int32_t) * kClasses * (size_t)std::max<int64_t>(n, 1));
     w.counts.ensure(sizeof(int32_t) * kClasses);
     w.cstat.ensure(sizeof(int64_t) * 8 * kClasses);
-    // pairs need A compact (rows i, i+1 adjacent in storage) -- every matrix
-    // built here is; the merged lists reuse A's index range
-    const bool pairing = w.pairing;
-    if (pairing) {
+    // row groups need A compact (rows i .. i+g-1 adjacent in storage) -- every
+    // matrix built here is; the merged lists reuse A's index range
+    const int group = w.row_group;
+    if (group > 1) {
         w.mk.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(a_extent, 1));
-        w.m0.ensure(sizeof(V) * (size_t)std::max<int64_t>(a_extent, 1));
-        w.m1.ensure(sizeof(V) * (size_t)std::max<int64_t>(a_extent, 1));
+        w.mv.ensure(sizeof(V) * group * (size_t)std::max<int64_t>(a_extent, 1));
         w.mlen.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1));
     }
 
@@ -159,7 +161,7 @@ void product(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D,
         SFN_HIP(hipMemsetAsync(w.counts.get(), 0, sizeof(int32_t) * kClasses, s));
         SFN_HIP(hipMemsetAsync(w.cstat.get(), 0, sizeof(int64_t) * 8 * kClasses, s));
         launch_bin_rows(w.span.as<int32_t>(), w.work.as<int64_t>(), r0, r1, kSmallTile, kMidTile,
-                        pairing ? 1 : 0, w.bins.as<int32_t>(), n, w.counts.as<int32_t>(),
+                        group, w.bins.as<int32_t>(), n, w.counts.as<int32_t>(),
                         C.lenp(), sq_prod ? sq_prod->as<double>() : nullptr,
                         sq_out ? sq_out->as<double>() : nullptr, A.lenp(),
                         D ? D->lenp() : nullptr, w.cstat.as<int64_t>(), s);
@@ -168,19 +170,20 @@ void product(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D,
         SFN_HIP(hipStreamSynchronize(s));
         SFN_HIP(hipEventRecord(w.ev[0], s));
         if (cnt[4] > 0) {
-            const int32_t *pairs = w.bins.as<int32_t>() + (int64_t)4 * n;
-            launch_merge_pairs<V>(pairs, cnt[4], A.view(), B.view(), w.mk.as<int32_t>(),
-                                  w.m0.as<V>(), w.m1.as<V>(), w.mlen.as<int32_t>(),
+            const int32_t *leads = w.bins.as<int32_t>() + (int64_t)4 * n;
+            launch_merge_group<V>(group, leads, cnt[4], A.view(), B.view(), w.mk.as<int32_t>(),
+                                  w.mv.as<V>(), w.mlen.as<int32_t>(),
                                   w.cstat.as<int64_t>() + 4 * 8 + 5, s);
             SFN_HIP(hipEventRecord(w.ev[1], s));
-            launch_spgemm_pair<V>(pairs, cnt[4], w.mk.as<int32_t>(), w.m0.as<V>(), w.m1.as<V>(),
-                                  w.mlen.as<int32_t>(), A.view(), B.view(), Dv, coef, dcoef, diag,
-                                  w.lo.as<int32_t>(), w.span.as<int32_t>(), base,
-                                  w.capoff.as<int64_t>(), w.stage_col.as<int32_t>(),
-                                  w.stage_val.as<V>(), C.lenp(), w.cursor.as<int32_t>(),
-                                  w.cnext.as<int32_t>(), sq_prod ? sq_prod->as<double>() : nullptr,
-                                  sq_out ? sq_out->as<double>() : nullptr,
-                                  w.cstat.as<int64_t>() + 4 * 8 + 4, s);
+            launch_spgemm_group<V>(group, leads, cnt[4], w.mk.as<int32_t>(), w.mv.as<V>(),
+                                   w.mlen.as<int32_t>(), A.view(), B.view(), Dv, coef, dcoef,
+                                   diag, w.lo.as<int32_t>(), w.span.as<int32_t>(), base,
+                                   w.capoff.as<int64_t>(), w.stage_col.as<int32_t>(),
+                                   w.stage_val.as<V>(), C.lenp(), w.cursor.as<int32_t>(),
+                                   w.cnext.as<int32_t>(),
+                                   sq_prod ? sq_prod->as<double>() : nullptr,
+                                   sq_out ? sq_out->as<double>() : nullptr,
+                                   w.cstat.as<int64_t>() + 4 * 8 + 4, s);
         } else {
             SFN_HIP(hipEventRecord(w.ev[1], s));
         }
@@ -218,20 +221,20 @@ void product(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D,
             Workspace::ClassStat &c = w.cls[sizeof(V) == 4 ? 1 : 0][cls];
             const int64_t *q = cs + cls * 8;
             c.launches += 1;
-            c.rows += cls == 4 ? 2 * (int64_t)cnt[cls] : cnt[cls];
+            c.rows += cls == 4 ? (int64_t)group * cnt[cls] : cnt[cls];
             c.products += q[1];
             c.a_nnz += q[2];
             c.d_nnz += q[3];
             c.out += q[4];
             c.ms += ms;
             // algorithmic bytes: each B entry gathered (once per row, or once per
-            // pair from the merged list), each A entry with its B-row descriptor,
+            // group from the merged list), each A entry with its B-row descriptor,
             // the D rows, the stored output, per-row data
             const double eb = (double)(sizeof(int32_t) + sizeof(V));
             const double gathered = cls == 4 ? (double)q[5] : (double)q[1];
-            const double a_side = cls == 4 ? (double)(4 + 2 * sizeof(V) + 12) * (double)q[2]
+            const double a_side = cls == 4 ? (double)(4 + group * sizeof(V) + 12) * (double)q[2]
                                            : (eb + 12.0) * (double)q[2];
-            const double rows_here = cls == 4 ? 2.0 * cnt[cls] : (double)cnt[cls];
+            const double rows_here = cls == 4 ? (double)group * cnt[cls] : (double)cnt[cls];
             const double bytes = eb * gathered + a_side + eb * (double)q[3] + eb * (double)q[4] +
                                  40.0 * rows_here;
             c.bytes += bytes;

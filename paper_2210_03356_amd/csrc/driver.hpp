@@ -16,9 +16,9 @@ struct Workspace {
     size_t staging_limit;  // bytes of gapped product output per batch
     DevBuf lo, span, cap, work, capoff, workoff, tmp, bins, counts, cursor, stage_col, stage_val;
     DevBuf rs1, rs2, rs3, rs4, icnt, hist, tau, bstar, seg, red, flag, zero_b;
-    DevBuf cstat, mk, m0, m1, mlen, cnext;
+    DevBuf cstat, mk, mv, mlen, cnext;
     const uint8_t *row_skip = nullptr;  // optional row mask for products (serving)
-    bool pairing = true;                // wide rows computed in pairs (i, i+1)
+    int row_group = 4;                  // wide rows computed in groups of 1, 2 or 4
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     // accumulated product statistics, in total and per row class (kernel tile)
     struct ClassStat {

@@ -317,8 +317,8 @@ __global__ void k_plan(MatView<V> A, MatView<V> B, MatView<V> D, int diag, int64
 constexpr int kBinThreads = 256;
 
 // Row classes: 0 empty, 1 small window, 2 mid window, 3 wide rows swept in
-// 8192-column (FP64) windows, 4 leaders of pairs (i, i+1) of wide rows that are
-// computed together (rows i+1 of pairs get no class of their own).
+// 8192-column (FP64) windows, 4 leaders of groups of consecutive wide rows that
+// are computed together (the other rows of a group get no class of their own).
 __device__ __forceinline__ int row_class(const int32_t *span, const int64_t *work, int64_t i,
                                          int small_tile, int mid_tile) {
     const int sp = span[i];
@@ -330,7 +330,7 @@ __device__ __forceinline__ int row_class(const int32_t *span, const int64_t *wor
 
 __global__ __launch_bounds__(kBinThreads) void k_bin_rows(
     const int32_t *span, const int64_t *work, int64_t r0, int64_t r1, int small_tile,
-    int mid_tile, int pairing, int32_t *bins, int64_t bin_stride, int32_t *counts,
+    int mid_tile, int group, int32_t *bins, int64_t bin_stride, int32_t *counts,
     int32_t *out_len, double *sq_prod, double *sq_out, const int32_t *a_len,
     const int32_t *d_len, int64_t *cstat) {
     __shared__ int wc[kBinThreads / kWave][kClasses];
@@ -345,13 +345,13 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_rows(
             out_len[i] = 0;
             if (sq_prod) sq_prod[i] = 0.0;
             if (sq_out) sq_out[i] = 0.0;
-        } else if (cls == 3 && pairing) {
-            // pairs (i, i+1) with i - r0 even, both wide
-            if (((i - r0) & 1) == 0) {
-                if (i + 1 < r1 && row_class(span, work, i + 1, small_tile, mid_tile) == 3) cls = 4;
-            } else if (row_class(span, work, i - 1, small_tile, mid_tile) == 3) {
-                cls = -1;  // computed with its leader i - 1
-            }
+        } else if (cls == 3 && group > 1) {
+            // aligned groups of `group` consecutive wide rows are computed together
+            const int64_t lead = r0 + (i - r0) / group * group;
+            bool whole = lead + group <= r1;
+            for (int r = 0; whole && r < group; ++r)
+                whole = row_class(span, work, lead + r, small_tile, mid_tile) == 3;
+            if (whole) cls = (i == lead) ? 4 : -1;  // members are computed by their leader
         }
     }
     const int lane = lane_id(), w = wave_id();
@@ -372,7 +372,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_rows(
         int off = base[cls] + rank;
         for (int q = 0; q < w; ++q) off += wc[q][cls];
         bins[(int64_t)cls * bin_stride + off] = (int32_t)i;
-        const int nr = cls == 4 ? 2 : 1;
+        const int nr = cls == 4 ? group : 1;
         for (int r = 0; r < nr; ++r) {
             atomicAdd(&bsum[cls][0], (unsigned long long)work[i + r]);
             atomicAdd(&bsum[cls][1], (unsigned long long)a_len[i + r]);
@@ -386,33 +386,46 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_rows(
     }
 }
 
-// Merged A-row list of a pair (i, i+1): union of the two sorted column lists
-// with both coefficients (0 where a row has no entry), stored in the index
-// range of the two rows in A (compact CSR: the pair occupies [beg[i],
-// beg[i] + len[i] + len[i+1]) and the union is not longer).  One thread per
-// pair, a sequential two-pointer merge.  Also counts the B entries the pair
-// gathers (sum of nnz(B_k) over the union) into *gathered.
-template <typename V>
-__global__ void k_merge_pairs(const int32_t *pairs, int npairs, MatView<V> A, MatView<V> B,
-                              int32_t *mk, V *m0, V *m1, int32_t *mlen,
-                              unsigned long long *gathered) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+// Merged A-row list of a group of R consecutive rows i .. i+R-1: the union of
+// their sorted column lists, each entry with the R coefficients (0 where a row
+// has no entry), interleaved as mv[pos*R + r].  It is stored in the index range
+// of the group's rows in A (compact CSR: the group occupies [beg[i],
+// beg[i+R]) and the union is not longer).  One thread per group, a sequential
+// R-way merge.  Also counts the B entries the group gathers (sum of nnz(B_k)
+// over the union) into *gathered.
+template <typename V, int R>
+__global__ void k_merge_group(const int32_t *leads, int ngroups, MatView<V> A, MatView<V> B,
+                              int32_t *mk, V *mv, int32_t *mlen, unsigned long long *gathered) {
+    const int g_id = blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long g = 0;
-    if (p < npairs) {
-        const int i = pairs[p];
-        int64_t pi = A.beg[i], pj = A.beg[i + 1];
-        const int64_t ei = pi + A.len[i], ej = pj + A.len[i + 1];
+    if (g_id < ngroups) {
+        const int i = leads[g_id];
+        int64_t p[R], e[R];
+        int cur[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            p[r] = A.beg[i + r];
+            e[r] = p[r] + A.len[i + r];
+            cur[r] = p[r] < e[r] ? A.col[p[r]] : INT_MAX;
+        }
         const int64_t o0 = A.beg[i];
         int64_t o = o0;
-        while (pi < ei || pj < ej) {
-            const int ki = pi < ei ? A.col[pi] : INT_MAX;
-            const int kj = pj < ej ? A.col[pj] : INT_MAX;
-            int k;
-            V a0 = V(0), a1 = V(0);
-            if (ki < kj) { k = ki; a0 = A.val[pi++]; }
-            else if (kj < ki) { k = kj; a1 = A.val[pj++]; }
-            else { k = ki; a0 = A.val[pi++]; a1 = A.val[pj++]; }
-            mk[o] = k; m0[o] = a0; m1[o] = a1;
+        for (;;) {
+            int k = INT_MAX;
+#pragma unroll
+            for (int r = 0; r < R; ++r) k = min(k, cur[r]);
+            if (k == INT_MAX) break;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                V a = V(0);
+                if (cur[r] == k) {
+                    a = A.val[p[r]];
+                    ++p[r];
+                    cur[r] = p[r] < e[r] ? A.col[p[r]] : INT_MAX;
+                }
+                mv[o * R + r] = a;
+            }
+            mk[o] = k;
             g += (unsigned long long)B.len[k];
             ++o;
         }
@@ -588,56 +601,66 @@ __global__ __launch_bounds__(NT) void k_spgemm(
     }
 }
 
-// Pair variant for wide rows: one workgroup computes output rows i and i+1
-// from their merged A list.  Each chunk of a B row is gathered once and added
-// into both rows' LDS windows (two accumulators of `tile` columns), so the
-// gathered B bytes of the two rows are paid once -- neighbouring rows of these
-// matrices reference almost the same rows of B.
-template <typename V, int T, int NT>
-__global__ __launch_bounds__(NT) void k_spgemm_pair(
-    const int32_t *__restrict__ rows, const int32_t *__restrict__ mk, const V *__restrict__ m0,
-    const V *__restrict__ m1, const int32_t *__restrict__ mlen, MatView<V> A, MatView<V> B,
-    MatView<V> D, V coef, V dcoef, V diag, const int32_t *__restrict__ row_lo,
-    const int32_t *__restrict__ row_span, const int64_t *__restrict__ off, int64_t base,
-    int32_t *__restrict__ out_col, V *__restrict__ out_val, int32_t *__restrict__ out_len,
-    int32_t *__restrict__ cursor, int32_t *__restrict__ cnext, double *__restrict__ sq_prod, double *__restrict__ sq_out,
+// Group variant for wide rows: one workgroup computes R consecutive output
+// rows i .. i+R-1 from their merged A list.  Each chunk of a B row is gathered
+// once and added into every row's LDS window that references it (R
+// accumulators of `tile` columns), so the gathered B bytes of the group are
+// paid once -- neighbouring rows of these matrices reference almost the same
+// rows of B.
+template <typename V, int R, int T, int NT>
+__global__ __launch_bounds__(NT) void k_spgemm_group(
+    const int32_t *__restrict__ rows, const int32_t *__restrict__ mk, const V *__restrict__ mv,
+    const int32_t *__restrict__ mlen, MatView<V> A, MatView<V> B, MatView<V> D, V coef,
+    V dcoef, V diag, const int32_t *__restrict__ row_lo, const int32_t *__restrict__ row_span,
+    const int64_t *__restrict__ off, int64_t base, int32_t *__restrict__ out_col,
+    V *__restrict__ out_val, int32_t *__restrict__ out_len, int32_t *__restrict__ cursor,
+    int32_t *__restrict__ cnext, double *__restrict__ sq_prod, double *__restrict__ sq_out,
     int64_t *__restrict__ out_count) {
     constexpr int NW = NT / kWave;
     constexpr int REG = T / NW;
     static_assert(T % (NW * kWave) == 0, "tile must split evenly over the waves");
-    __shared__ V acc[2][T];
+    __shared__ V acc[R][T];
     __shared__ int wcnt[NW];
-    __shared__ double wsum[4][NW];
+    __shared__ double wsum[2 * R][NW];
 
     const int lane = lane_id(), wave = wave_id();
     const int i = rows[xcd_row(blockIdx.x, gridDim.x)];
-    const int lo0 = row_lo[i], sp0 = row_span[i], lo1 = row_lo[i + 1], sp1 = row_span[i + 1];
-    const int lo = min(lo0, lo1);
-    const int hi = max(lo0 + sp0, lo1 + sp1);
+    int lo = INT_MAX, hi = INT_MIN;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        lo = min(lo, row_lo[i + r]);
+        hi = max(hi, row_lo[i + r] + row_span[i + r]);
+    }
     const int64_t mbeg = A.beg[i];
     const int ml = mlen[i];
     const bool multi = hi - lo > T;
     const bool has_d = D.len != nullptr;
 
-    int written[2] = {0, 0};
-    double sqp[2] = {0.0, 0.0}, sqo[2] = {0.0, 0.0};
+    int written[R];
+    double sqp[R], sqo[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) { written[r] = 0; sqp[r] = 0.0; sqo[r] = 0.0; }
     for (int wlo = lo; wlo < hi; wlo += T) {
         const int nsl = min(T, hi - wlo);
         const int whi = wlo + nsl;
         const bool first = (wlo == lo);
-        for (int s = threadIdx.x; s < nsl; s += NT) { acc[0][s] = V(0); acc[1][s] = V(0); }
+        for (int s = threadIdx.x; s < nsl; s += NT)
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r][s] = V(0);
         __syncthreads();
 
         for (int t0 = wave * kWave; t0 < ml; t0 += NW * kWave) {
             const int t = t0 + lane;
             int bl = 0, cur = 0, nc = INT_MIN;
             int64_t bb = 0;
-            V a0 = V(0), a1 = V(0);
+            V a[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) a[r] = V(0);
             if (t < ml) {
                 const int64_t pa = mbeg + t;
                 const int k = mk[pa];
-                a0 = coef * m0[pa];
-                a1 = coef * m1[pa];
+#pragma unroll
+                for (int r = 0; r < R; ++r) a[r] = coef * mv[pa * R + r];
                 bb = B.beg[k];
                 bl = B.len[k];
                 if (!first) { cur = cursor[pa]; nc = cnext[pa]; }
@@ -646,10 +669,12 @@ __global__ __launch_bounds__(NT) void k_spgemm_pair(
             for (int q = 0; q < cnt; ++q) {
                 const int blq = rl_i32(bl, q);
                 int p = rl_i32(cur, q);
+                // B rows with nothing left in this window are skipped without a load
                 if (p < blq && rl_i32(nc, q) < whi) {
                     const int64_t bbq = rl_i64(bb, q);
-                    const V a0q = rl_val(a0, q), a1q = rl_val(a1, q);
-                    const bool u0 = a0q != V(0), u1 = a1q != V(0);
+                    V aq[R];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) aq[r] = rl_val(a[r], q);
                     while (true) {
                         int c[kUnroll];
                         V bv[kUnroll];
@@ -668,13 +693,15 @@ __global__ __launch_bounds__(NT) void k_spgemm_pair(
                         for (int u = 0; u < kUnroll; ++u) {
                             const bool in = c[u] < whi;
                             if (in) {
-                                if (u0) atomicAdd(&acc[0][c[u] - wlo], a0q * bv[u]);
-                                if (u1) atomicAdd(&acc[1][c[u] - wlo], a1q * bv[u]);
+#pragma unroll
+                                for (int r = 0; r < R; ++r)
+                                    if (aq[r] != V(0)) atomicAdd(&acc[r][c[u] - wlo], aq[r] * bv[u]);
                             }
                             got += __popcll(__ballot(in));
                         }
                         p += got;
                         if (got < kUnroll * kWave) {
+                            // column of the first entry beyond the window, for the next one
                             int cs = INT_MAX;
 #pragma unroll
                             for (int u = 0; u < kUnroll; ++u)
@@ -692,15 +719,17 @@ __global__ __launch_bounds__(NT) void k_spgemm_pair(
         __syncthreads();
 
         if (sq_prod) {
-            for (int s = threadIdx.x; s < nsl; s += NT) {
-                const double v0 = as_f64(acc[0][s]), v1 = as_f64(acc[1][s]);
-                sqp[0] += v0 * v0;
-                sqp[1] += v1 * v1;
-            }
+            for (int s = threadIdx.x; s < nsl; s += NT)
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const double v = as_f64(acc[r][s]);
+                    sqp[r] += v * v;
+                }
             __syncthreads();
         }
         if (has_d) {
-            for (int r = 0; r < 2; ++r) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
                 const int dl = D.len[i + r];
                 const int64_t db = D.beg[i + r];
                 for (int q = threadIdx.x; q < dl; q += NT) {
@@ -710,13 +739,14 @@ __global__ __launch_bounds__(NT) void k_spgemm_pair(
             }
             __syncthreads();
         }
-        if (diag != V(0) && threadIdx.x < 2) {
+        if (diag != V(0) && threadIdx.x < R) {
             const int r = threadIdx.x, ir = i + r;
             if (ir >= wlo && ir < whi) acc[r][ir - wlo] += diag;
         }
         __syncthreads();
 
-        for (int r = 0; r < 2; ++r) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
             const int64_t obase = off[i + r] - base;
             const int rbeg = wave * REG;
             int cw = 0;
@@ -750,19 +780,24 @@ __global__ __launch_bounds__(NT) void k_spgemm_pair(
             __syncthreads();
         }
     }
-    for (int r = 0; r < 2; ++r) {
-        const double a = wave_sum(sqp[r]), b = wave_sum(sqo[r]);
-        if (lane == 0) { wsum[2 * r][wave] = a; wsum[2 * r + 1][wave] = b; }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const double x = wave_sum(sqp[r]), y = wave_sum(sqo[r]);
+        if (lane == 0) { wsum[2 * r][wave] = x; wsum[2 * r + 1][wave] = y; }
     }
     __syncthreads();
-    if (threadIdx.x < 2) {
-        const int r = threadIdx.x;
-        double a = 0.0, b = 0.0;
-        for (int w = 0; w < NW; ++w) { a += wsum[2 * r][w]; b += wsum[2 * r + 1][w]; }
-        out_len[i + r] = written[r];
-        if (sq_prod) sq_prod[i + r] = a;
-        if (sq_out) sq_out[i + r] = b;
-        if (out_count) atomicAdd((unsigned long long *)out_count, (unsigned long long)written[r]);
+    if (threadIdx.x == 0) {
+        unsigned long long tw = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            double x = 0.0, y = 0.0;
+            for (int w = 0; w < NW; ++w) { x += wsum[2 * r][w]; y += wsum[2 * r + 1][w]; }
+            out_len[i + r] = written[r];
+            if (sq_prod) sq_prod[i + r] = x;
+            if (sq_out) sq_out[i + r] = y;
+            tw += (unsigned long long)written[r];
+        }
+        if (out_count) atomicAdd((unsigned long long *)out_count, tw);
     }
 }
 
@@ -1173,13 +1208,13 @@ void launch_fill_u8(uint8_t *p, int64_t lo, int64_t hi, uint8_t v, hipStream_t s
 }
 
 void launch_bin_rows(const int32_t *span, const int64_t *work, int64_t r0, int64_t r1,
-                     int small_tile, int mid_tile, int pairing, int32_t *bins, int64_t bin_stride,
+                     int small_tile, int mid_tile, int group, int32_t *bins, int64_t bin_stride,
                      int32_t *counts, int32_t *out_len, double *sq_prod, double *sq_out,
                      const int32_t *a_len, const int32_t *d_len, int64_t *cstat,
                      hipStream_t s) {
     if (r1 <= r0) return;
     k_bin_rows<<<blocks_for(r1 - r0, kBinThreads), kBinThreads, 0, s>>>(
-        span, work, r0, r1, small_tile, mid_tile, pairing, bins, bin_stride, counts, out_len,
+        span, work, r0, r1, small_tile, mid_tile, group, bins, bin_stride, counts, out_len,
         sq_prod, sq_out, a_len, d_len, cstat);
 }
 
@@ -1187,50 +1222,60 @@ BinCfg bin_config(int cls, int value_bytes) {
     switch (cls) {
         case 1: return {512, 64};
         case 2: return {4096, 256};
-        case 4: return {value_bytes == 8 ? 4096 : 8192, 512};
+        case 4: return {value_bytes == 8 ? 4096 : 8192, 1024};
         default: return {value_bytes == 8 ? 8192 : 16384, 512};
     }
 }
 
 template <typename V>
-void launch_merge_pairs(const int32_t *pairs, int npairs, MatView<V> A, MatView<V> B, int32_t *mk,
-                        V *m0, V *m1, int32_t *mlen, int64_t *gathered, hipStream_t s) {
-    if (npairs <= 0) return;
-    k_merge_pairs<V><<<blocks_for(npairs, 64), 64, 0, s>>>(
-        pairs, npairs, A, B, mk, m0, m1, mlen, (unsigned long long *)gathered);
+void launch_merge_group(int group, const int32_t *leads, int ngroups, MatView<V> A, MatView<V> B,
+                        int32_t *mk, V *mv, int32_t *mlen, int64_t *gathered, hipStream_t s) {
+    if (ngroups <= 0) return;
+    unsigned long long *g = (unsigned long long *)gathered;
+    if (group == 2)
+        k_merge_group<V, 2><<<blocks_for(ngroups, 64), 64, 0, s>>>(leads, ngroups, A, B, mk, mv,
+                                                                   mlen, g);
+    else
+        k_merge_group<V, 4><<<blocks_for(ngroups, 64), 64, 0, s>>>(leads, ngroups, A, B, mk, mv,
+                                                                   mlen, g);
 }
-template void launch_merge_pairs<double>(const int32_t *, int, MatView<double>, MatView<double>,
-                                         int32_t *, double *, double *, int32_t *, int64_t *,
-                                         hipStream_t);
-template void launch_merge_pairs<float>(const int32_t *, int, MatView<float>, MatView<float>,
-                                        int32_t *, float *, float *, int32_t *, int64_t *,
-                                        hipStream_t);
+template void launch_merge_group<double>(int, const int32_t *, int, MatView<double>,
+                                         MatView<double>, int32_t *, double *, int32_t *,
+                                         int64_t *, hipStream_t);
+template void launch_merge_group<float>(int, const int32_t *, int, MatView<float>, MatView<float>,
+                                        int32_t *, float *, int32_t *, int64_t *, hipStream_t);
 
 template <typename V>
-void launch_spgemm_pair(const int32_t *pairs, int npairs, const int32_t *mk, const V *m0,
-                        const V *m1, const int32_t *mlen, MatView<V> A, MatView<V> B, MatView<V> D,
-                        double coef, double dcoef, double diag, const int32_t *lo,
-                        const int32_t *span, int64_t base, const int64_t *off, int32_t *out_col,
-                        V *out_val, int32_t *out_len, int32_t *cursor, int32_t *cnext,
-                        double *sq_prod, double *sq_out, int64_t *out_count, hipStream_t s) {
-    if (npairs <= 0) return;
-    k_spgemm_pair<V, (sizeof(V) == 8 ? 4096 : 8192), 512><<<npairs, 512, 0, s>>>(
-        pairs, mk, m0, m1, mlen, A, B, D, (V)coef, (V)dcoef, (V)diag, lo, span, off, base, out_col,
-        out_val, out_len, cursor, cnext, sq_prod, sq_out, out_count);
+void launch_spgemm_group(int group, const int32_t *leads, int ngroups, const int32_t *mk,
+                         const V *mv, const int32_t *mlen, MatView<V> A, MatView<V> B,
+                         MatView<V> D, double coef, double dcoef, double diag, const int32_t *lo,
+                         const int32_t *span, int64_t base, const int64_t *off, int32_t *out_col,
+                         V *out_val, int32_t *out_len, int32_t *cursor, int32_t *cnext,
+                         double *sq_prod, double *sq_out, int64_t *out_count, hipStream_t s) {
+    if (ngroups <= 0) return;
+    constexpr int T2 = sizeof(V) == 8 ? 4096 : 8192;
+    if (group == 2)
+        k_spgemm_group<V, 2, T2, 512><<<ngroups, 512, 0, s>>>(
+            leads, mk, mv, mlen, A, B, D, (V)coef, (V)dcoef, (V)diag, lo, span, off, base, out_col,
+            out_val, out_len, cursor, cnext, sq_prod, sq_out, out_count);
+    else
+        k_spgemm_group<V, 4, T2, 1024><<<ngroups, 1024, 0, s>>>(
+            leads, mk, mv, mlen, A, B, D, (V)coef, (V)dcoef, (V)diag, lo, span, off, base, out_col,
+            out_val, out_len, cursor, cnext, sq_prod, sq_out, out_count);
 }
-template void launch_spgemm_pair<double>(const int32_t *, int, const int32_t *, const double *,
-                                         const double *, const int32_t *, MatView<double>,
-                                         MatView<double>, MatView<double>, double, double, double,
-                                         const int32_t *, const int32_t *, int64_t,
-                                         const int64_t *, int32_t *, double *, int32_t *,
-                                         int32_t *, int32_t *, double *, double *, int64_t *,
-                                         hipStream_t);
-template void launch_spgemm_pair<float>(const int32_t *, int, const int32_t *, const float *,
-                                        const float *, const int32_t *, MatView<float>,
-                                        MatView<float>, MatView<float>, double, double, double,
-                                        const int32_t *, const int32_t *, int64_t, const int64_t *,
-                                        int32_t *, float *, int32_t *, int32_t *, int32_t *,
-                                        double *, double *, int64_t *, hipStream_t);
+template void launch_spgemm_group<double>(int, const int32_t *, int, const int32_t *,
+                                          const double *, const int32_t *, MatView<double>,
+                                          MatView<double>, MatView<double>, double, double, double,
+                                          const int32_t *, const int32_t *, int64_t,
+                                          const int64_t *, int32_t *, double *, int32_t *,
+                                          int32_t *, int32_t *, double *, double *, int64_t *,
+                                          hipStream_t);
+template void launch_spgemm_group<float>(int, const int32_t *, int, const int32_t *, const float *,
+                                         const int32_t *, MatView<float>, MatView<float>,
+                                         MatView<float>, double, double, double, const int32_t *,
+                                         const int32_t *, int64_t, const int64_t *, int32_t *,
+                                         float *, int32_t *, int32_t *, int32_t *, double *,
+                                         double *, int64_t *, hipStream_t);
 
 template <typename V>
 void launch_spgemm(int cls, const int32_t *rows, int nrows, MatView<V> A, MatView<V> B,

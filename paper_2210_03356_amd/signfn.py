@@ -50,7 +50,7 @@ class sign_stats(C.Structure):
                 ("nnz", C.c_int64), ("seconds", C.c_double), ("products", C.c_int64),
                 ("spgemm_ms", C.c_double), ("spgemm_bytes", C.c_double),
                 ("inner_steps", C.c_int), ("comm_rel", C.c_double), ("hot_tile", C.c_int),
-                ("hot_threads", C.c_int), ("hot_fp32", C.c_int), ("hot_pair", C.c_int),
+                ("hot_threads", C.c_int), ("hot_fp32", C.c_int), ("hot_group", C.c_int),
                 ("hot_launches", C.c_int64),
                 ("hot_ms", C.c_double),
                 ("hot_bytes", C.c_double), ("hot_products", C.c_int64)]

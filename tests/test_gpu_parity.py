@@ -310,20 +310,50 @@ def test_mixed_precision_matches_fp64_oracle(sf, name):
     assert rel <= rel0
 
 
-def test_paired_rows_match_single_rows(sf, monkeypatch):
-    """Wide rows computed in pairs (one gather feeding two accumulators) give the
-    products of the one-row kernel, and both match the oracle."""
+def _wide_rows_matrix(nx=203, ny=61, radius=11, seed=21):
+    """Rows of a 2D grid (x fastest) holding every point within Manhattan distance
+    `radius`: interior rows span 2*radius*nx + 1 > 4096 columns (the wide class),
+    rows near the top and bottom edges span fewer, so aligned row groups mix wide
+    and narrower rows; n = nx*ny is odd."""
+    rng = np.random.default_rng(seed)
+    n = nx * ny
+    rows = []
+    for y in range(ny):
+        for x in range(nx):
+            parts = []
+            for dy in range(-radius, radius + 1):
+                yy = y + dy
+                if 0 <= yy < ny:
+                    r = radius - abs(dy)
+                    parts.append(yy * nx + np.arange(max(0, x - r), min(nx - 1, x + r) + 1))
+            rows.append(np.concatenate(parts))
+    indptr = np.zeros(n + 1, np.int64)
+    indptr[1:] = np.cumsum([len(c) for c in rows])
+    indices = np.concatenate(rows).astype(np.int32)
+    data = rng.uniform(0.1, 1.0, len(indices)) * rng.choice([-1.0, 1.0], len(indices))
+    return W.Csr(n=n, indptr=indptr, indices=indices, data=data)
+
+
+@pytest.mark.parametrize("group", [1, 2, 4])
+def test_row_groups_match_oracle(sf, monkeypatch, group):
+    """Wide rows computed in groups (one gather of a B row feeding the
+    accumulators of 2 or 4 consecutive output rows) give the oracle's product,
+    including groups that mix wide and narrower rows and a ragged last group."""
+    monkeypatch.setenv("SIGNFN_ROW_GROUP", str(group))
+    A = _wide_rows_matrix()
+    R = W.random_sparse(A.n, mean_row=6, seed=9, powerlaw=False)
+    for left, right in ((A, A), (A, R)):
+        r = _check_product(sf, left, right)
+        if left is A:
+            st = r.stats()
+            assert st["products"] > 0
+
+
+@pytest.mark.parametrize("group", [1, 2, 4])
+def test_row_groups_nsf(sf, monkeypatch, group):
+    """The whole iteration with each row-group setting matches the oracle."""
+    monkeypatch.setenv("SIGNFN_ROW_GROUP", str(group))
     A = W.laplacian_2d(48, jitter=0.05, seed=2, m=8.0)
     X = oracle.nsf(A, tol=1e-12)
-    Xc = W.Csr(n=A.n, indptr=X.indptr, indices=X.indices, data=X.data)
-    R = W.random_sparse(2304, mean_row=40, seed=9, powerlaw=False)   # odd/even mix of wide rows
-    for left, right in ((Xc, Xc), (R, Xc), (Xc, R)):
-        monkeypatch.setenv("SIGNFN_PAIR_ROWS", "1")
-        a = _check_product(sf, left, right, exact_pattern=False)
-        monkeypatch.setenv("SIGNFN_PAIR_ROWS", "0")
-        b = _check_product(sf, left, right, exact_pattern=False)
-        Pa, Pb = a.to_scipy(), b.to_scipy()
-        assert sp.linalg.norm(Pa - Pb) <= 1e-14 * sp.linalg.norm(Pb)
-    monkeypatch.setenv("SIGNFN_PAIR_ROWS", "1")
     r = sf.sign_ns(_dev(sf, A), sf.default_opts(tol=1e-12))
     assert sp.linalg.norm(r.to_scipy() - X.to_scipy()) / sp.linalg.norm(X.to_scipy()) <= 1e-10
