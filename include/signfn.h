@@ -102,7 +102,8 @@ typedef struct {
     double seconds;      /* wall time of the call */
     int64_t products;    /* scalar multiply-adds in all sparse products */
     double spgemm_ms;    /* device time of the numeric product kernels */
-    double spgemm_bytes; /* algorithmic bytes of the numeric product kernels */
+    double spgemm_bytes; /* algorithmic bytes of the numeric product kernels: A and D rows,
+                            B once per product, stored output, row descriptors */
     int inner_steps;     /* sign_newton: filtered NS inversion steps in total */
     double comm_rel;     /* precision 1: ||XA - AX||_F / (||X||_F ||A||_F) before refinement */
     /* the numeric product kernel configuration with the most device time */
@@ -112,8 +113,10 @@ typedef struct {
     int hot_group;       /* output rows per workgroup: 1, or 2 / 4 for the grouped-row kernel */
     int64_t hot_launches;/* its launches */
     double hot_ms;       /* its device time (HIP events on the call's stream) */
-    double hot_bytes;    /* its algorithmic bytes */
+    double hot_bytes;    /* its algorithmic bytes (as spgemm_bytes) */
     int64_t hot_products;/* its multiply-adds */
+    int64_t hot_gathered;/* B entries it loads (one per multiply-add, or one per slot of the
+                            merged list of a row group) */
 } sign_stats;
 
 /* One entry per computed residual, k = 0 .. iters. */

@@ -15,12 +15,12 @@ constexpr int kMidTile = 4096;
 Workspace::Workspace(Allocator *a, size_t staging_bytes) : al(a), s(a->stream) {
     for (DevBuf *b : {&lo, &span, &cap, &work, &capoff, &workoff, &tmp, &bins, &counts, &cursor,
                       &stage_col, &stage_val, &rs1, &rs2, &rs3, &rs4, &icnt, &hist, &tau,
-                      &bstar, &seg, &red, &flag, &zero_b, &cstat, &mk, &mv, &mlen, &cnext})
+                      &bstar, &seg, &red, &flag, &zero_b, &cstat, &mk, &mm, &mc, &cv, &mlen, &cnext})
         b->bind(a);
-    // rows per workgroup for wide rows: 1 (off), 2 or 4
+    // rows per workgroup for wide rows: 1 (off), 2, 4, 8 or 16
     if (const char *ge = std::getenv("SIGNFN_ROW_GROUP")) {
         const int g = std::atoi(ge);
-        row_group = (g == 1 || g == 2 || g == 4) ? g : row_group;
+        if (g == 1 || g == 2 || g == 4 || g == 8 || g == 16) row_group = g;
     }
     if (staging_bytes == 0) {
         // a quarter of the memory that is free or idle in the caching pool,
@@ -50,14 +50,16 @@ void Workspace::hot_stats(sign_stats &st) const {
         for (int c = 1; c < kClasses; ++c)
             if (cls[v][c].ms > cls[hv][h].ms) { hv = v; h = c; }
     const ClassStat &c = cls[hv][h];
-    st.hot_tile = bin_config(h, hv ? 4 : 8).tile;
-    st.hot_threads = h == 4 ? 256 * row_group : bin_config(h, hv ? 4 : 8).threads;
+    const BinCfg cfg = h == 4 ? group_config(row_group, hv ? 4 : 8) : bin_config(h, hv ? 4 : 8);
+    st.hot_tile = cfg.tile;
+    st.hot_threads = cfg.threads;
     st.hot_fp32 = hv;
     st.hot_group = h == 4 ? row_group : 1;
     st.hot_launches = c.launches;
     st.hot_ms = c.ms;
     st.hot_bytes = c.bytes;
     st.hot_products = c.products;
+    st.hot_gathered = c.gathered;
 }
 
 double Workspace::sum_rows(const DevBuf &rows, int64_t n) {
@@ -146,8 +148,11 @@ void product(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D,
     // matrix built here is; the merged lists reuse A's index range
     const int group = w.row_group;
     if (group > 1) {
-        w.mk.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(a_extent, 1));
-        w.mv.ensure(sizeof(V) * group * (size_t)std::max<int64_t>(a_extent, 1));
+        const size_t ext = (size_t)std::max<int64_t>(a_extent, 1);
+        w.mk.ensure(sizeof(int32_t) * ext);
+        w.mm.ensure(sizeof(uint32_t) * ext);
+        w.mc.ensure(sizeof(int32_t) * ext);
+        w.cv.ensure(sizeof(V) * ext);
         w.mlen.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1));
     }
 
@@ -172,10 +177,11 @@ void product(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D,
         if (cnt[4] > 0) {
             const int32_t *leads = w.bins.as<int32_t>() + (int64_t)4 * n;
             launch_merge_group<V>(group, leads, cnt[4], A.view(), B.view(), w.mk.as<int32_t>(),
-                                  w.mv.as<V>(), w.mlen.as<int32_t>(),
-                                  w.cstat.as<int64_t>() + 4 * 8 + 5, s);
+                                  w.mm.as<uint32_t>(), w.mc.as<int32_t>(), w.cv.as<V>(),
+                                  w.mlen.as<int32_t>(), w.cstat.as<int64_t>() + 4 * 8 + 5, s);
             SFN_HIP(hipEventRecord(w.ev[1], s));
-            launch_spgemm_group<V>(group, leads, cnt[4], w.mk.as<int32_t>(), w.mv.as<V>(),
+            launch_spgemm_group<V>(group, leads, cnt[4], w.mk.as<int32_t>(),
+                                   w.mm.as<uint32_t>(), w.mc.as<int32_t>(), w.cv.as<V>(),
                                    w.mlen.as<int32_t>(), A.view(), B.view(), Dv, coef, dcoef,
                                    diag, w.lo.as<int32_t>(), w.span.as<int32_t>(), base,
                                    w.capoff.as<int64_t>(), w.stage_col.as<int32_t>(),
@@ -227,16 +233,15 @@ void product(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D,
             c.d_nnz += q[3];
             c.out += q[4];
             c.ms += ms;
-            // algorithmic bytes: each B entry gathered (once per row, or once per
-            // group from the merged list), each A entry with its B-row descriptor,
-            // the D rows, the stored output, per-row data
+            // algorithmic (compulsory) bytes: the A and D rows of the launch, its
+            // share of B (each entry once per product, cache-perfect), the stored
+            // output, row descriptors
             const double eb = (double)(sizeof(int32_t) + sizeof(V));
-            const double gathered = cls == 4 ? (double)q[5] : (double)q[1];
-            const double a_side = cls == 4 ? (double)(4 + group * sizeof(V) + 12) * (double)q[2]
-                                           : (eb + 12.0) * (double)q[2];
             const double rows_here = cls == 4 ? (double)group * cnt[cls] : (double)cnt[cls];
-            const double bytes = eb * gathered + a_side + eb * (double)q[3] + eb * (double)q[4] +
-                                 40.0 * rows_here;
+            const double b_share = n > 0 ? (double)B.nnz * rows_here / (double)n : 0.0;
+            const double bytes = eb * ((double)q[2] + (double)q[3] + (double)q[4] + b_share) +
+                                 24.0 * rows_here;
+            c.gathered += cls == 4 ? q[5] : q[1];
             c.bytes += bytes;
             w.spgemm_bytes += bytes;
         }

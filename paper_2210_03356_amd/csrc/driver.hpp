@@ -16,13 +16,14 @@ struct Workspace {
     size_t staging_limit;  // bytes of gapped product output per batch
     DevBuf lo, span, cap, work, capoff, workoff, tmp, bins, counts, cursor, stage_col, stage_val;
     DevBuf rs1, rs2, rs3, rs4, icnt, hist, tau, bstar, seg, red, flag, zero_b;
-    DevBuf cstat, mk, mv, mlen, cnext;
+    DevBuf cstat, mk, mm, mc, cv, mlen, cnext;
     const uint8_t *row_skip = nullptr;  // optional row mask for products (serving)
-    int row_group = 4;                  // wide rows computed in groups of 1, 2 or 4
+    int row_group = 4;                  // wide rows computed in groups of 1, 2, 4, 8 or 16
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     // accumulated product statistics, in total and per row class (kernel tile)
     struct ClassStat {
         int64_t launches = 0, rows = 0, products = 0, a_nnz = 0, d_nnz = 0, out = 0;
+        int64_t gathered = 0;  // B entries loaded (once per slot of a row group)
         double ms = 0.0, bytes = 0.0;
     };
     ClassStat cls[2][kClasses];  // [FP64, FP32][row class]

@@ -21,6 +21,7 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kUnroll = 4;  // 64-entry chunks of a B row gathered per sweep step
+constexpr int kGroupUnroll = 4;  // the same for the row-group kernel
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 __device__ __forceinline__ int wave_id() { return threadIdx.x / kWave; }
@@ -386,53 +387,138 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_rows(
     }
 }
 
-// Merged A-row list of a group of R consecutive rows i .. i+R-1: the union of
-// their sorted column lists, each entry with the R coefficients (0 where a row
-// has no entry), interleaved as mv[pos*R + r].  It is stored in the index range
-// of the group's rows in A (compact CSR: the group occupies [beg[i],
-// beg[i+R]) and the union is not longer).  One thread per group, a sequential
-// R-way merge.  Also counts the B entries the group gathers (sum of nnz(B_k)
-// over the union) into *gathered.
+// Merged A-row list of a group of R consecutive rows i .. i+R-1 (R <= 32), in
+// slot order (ascending column k of the union of the R sorted column lists):
+//   mk[s]  the column k,
+//   mm[s]  bit r set when row i+r has an entry at k,
+//   mc[s]  offset of the slot's first coefficient in cv,
+//   cv     the group's entries ordered by (slot, r), so the coefficient of row
+//          i+r at slot s is cv[mc[s] + popcount(mm[s] & ((1 << r) - 1))].
+// Slots and coefficients are stored from index beg[i] of A's index range: A is
+// compact, so the group owns [beg[i], beg[i+R]) and neither the union nor the
+// entries overflow it.  mlen[i] = number of slots.  One workgroup per group
+// sweeps the columns in chunks: it marks the columns present (LDS bitmasks),
+// scans them into slot positions and coefficient offsets, and writes slots and
+// coefficients.  *gathered += sum of nnz(B_k) over the slots.
+constexpr int kMergeChunk = 4096;
+constexpr int kMergeThreads = 256;
+
 template <typename V, int R>
-__global__ void k_merge_group(const int32_t *leads, int ngroups, MatView<V> A, MatView<V> B,
-                              int32_t *mk, V *mv, int32_t *mlen, unsigned long long *gathered) {
-    const int g_id = blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long g = 0;
-    if (g_id < ngroups) {
-        const int i = leads[g_id];
-        int64_t p[R], e[R];
-        int cur[R];
-#pragma unroll
+__global__ __launch_bounds__(kMergeThreads) void k_merge_group(
+    const int32_t *__restrict__ leads, MatView<V> A, MatView<V> B, int32_t *__restrict__ mk,
+    uint32_t *__restrict__ mm, int32_t *__restrict__ mc, V *__restrict__ cv,
+    int32_t *__restrict__ mlen, unsigned long long *__restrict__ gathered) {
+    static_assert(R >= 2 && R <= 32, "group size");
+    constexpr int NW = kMergeThreads / kWave;
+    constexpr int PER = kMergeChunk / kMergeThreads;  // consecutive columns per thread
+    __shared__ uint32_t mask[kMergeChunk];
+    __shared__ int32_t coff[kMergeChunk];
+    __shared__ int64_t st[R], en[R];
+    __shared__ int fst[R + 1];
+    __shared__ int64_t wt[NW];
+    __shared__ int lohi[2];
+
+    const int i = leads[blockIdx.x];
+    const int lane = lane_id(), wave = wave_id();
+    const int64_t gb = A.beg[i];
+    if (threadIdx.x == 0) {
+        int lo = INT_MAX, hi = INT_MIN;
         for (int r = 0; r < R; ++r) {
-            p[r] = A.beg[i + r];
-            e[r] = p[r] + A.len[i + r];
-            cur[r] = p[r] < e[r] ? A.col[p[r]] : INT_MAX;
-        }
-        const int64_t o0 = A.beg[i];
-        int64_t o = o0;
-        for (;;) {
-            int k = INT_MAX;
-#pragma unroll
-            for (int r = 0; r < R; ++r) k = min(k, cur[r]);
-            if (k == INT_MAX) break;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                V a = V(0);
-                if (cur[r] == k) {
-                    a = A.val[p[r]];
-                    ++p[r];
-                    cur[r] = p[r] < e[r] ? A.col[p[r]] : INT_MAX;
-                }
-                mv[o * R + r] = a;
+            const int l = A.len[i + r];
+            if (l > 0) {
+                lo = min(lo, A.col[A.beg[i + r]]);
+                hi = max(hi, A.col[A.beg[i + r] + l - 1] + 1);
             }
-            mk[o] = k;
-            g += (unsigned long long)B.len[k];
-            ++o;
         }
-        mlen[i] = (int32_t)(o - o0);
+        lohi[0] = lo;
+        lohi[1] = hi;
     }
+    if (threadIdx.x < R) st[threadIdx.x] = A.beg[i + threadIdx.x];
+    __syncthreads();
+    const int64_t lo = lohi[0], hi = lohi[1];
+    int64_t nslot = 0, ncoef = 0;  // slots and coefficients written so far (uniform)
+    unsigned long long g = 0;
+    for (int64_t c0 = lo; c0 < hi; c0 += kMergeChunk) {
+        const int64_t c1 = min(hi, c0 + kMergeChunk);
+        for (int q = threadIdx.x; q < kMergeChunk; q += kMergeThreads) mask[q] = 0u;
+        if (threadIdx.x < R) {
+            // end of list r's entries below c1 (binary search from its chunk start)
+            const int r = threadIdx.x;
+            int64_t a = st[r], b = A.beg[i + r] + A.len[i + r];
+            while (a < b) {
+                const int64_t m = (a + b) >> 1;
+                if (A.col[m] < c1) a = m + 1;
+                else b = m;
+            }
+            en[r] = a;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int f = 0;
+            for (int r = 0; r < R; ++r) {
+                fst[r] = f;
+                f += (int)(en[r] - st[r]);
+            }
+            fst[R] = f;
+        }
+        __syncthreads();
+        const int tot = fst[R];
+        for (int f = threadIdx.x; f < tot; f += kMergeThreads) {
+            int r = 0;
+            while (f >= fst[r + 1]) ++r;
+            const int k = A.col[st[r] + (f - fst[r])];
+            atomicOr(&mask[k - c0], 1u << r);
+        }
+        __syncthreads();
+        // exclusive scan of (slots, coefficients) over the chunk, packed as
+        // (slots << 32 | coefficients): neither field can carry into the other
+        const int q0 = threadIdx.x * PER;
+        int ns = 0, nc = 0;
+        for (int u = 0; u < PER; ++u) {
+            const uint32_t m = mask[q0 + u];
+            ns += m != 0u;
+            nc += __popc(m);
+        }
+        const int64_t pk = ((int64_t)ns << 32) | (int64_t)nc;
+        const int64_t inc = wave_incl_scan(pk);
+        if (lane == kWave - 1) wt[wave] = inc;
+        __syncthreads();
+        int64_t before = inc - pk, total = 0;
+        for (int w = 0; w < NW; ++w) {
+            if (w < wave) before += wt[w];
+            total += wt[w];
+        }
+        int64_t ps = nslot + (before >> 32), pc = ncoef + (before & 0xffffffffll);
+        for (int u = 0; u < PER; ++u) {
+            const uint32_t m = mask[q0 + u];
+            if (m) {
+                const int k = (int)(c0 + q0 + u);
+                mk[gb + ps] = k;
+                mm[gb + ps] = m;
+                mc[gb + ps] = (int32_t)pc;
+                coff[q0 + u] = (int32_t)pc;
+                g += (unsigned long long)B.len[k];
+                ++ps;
+                pc += __popc(m);
+            }
+        }
+        __syncthreads();
+        for (int f = threadIdx.x; f < tot; f += kMergeThreads) {
+            int r = 0;
+            while (f >= fst[r + 1]) ++r;
+            const int64_t e = st[r] + (f - fst[r]);
+            const int q = (int)(A.col[e] - c0);
+            cv[gb + coff[q] + __popc(mask[q] & ((1u << r) - 1u))] = A.val[e];
+        }
+        nslot += total >> 32;
+        ncoef += total & 0xffffffffll;
+        __syncthreads();
+        if (threadIdx.x < R) st[threadIdx.x] = en[threadIdx.x];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) mlen[i] = (int32_t)nslot;
     g = wave_sum(g);
-    if (gathered && lane_id() == 0 && g) atomicAdd(gathered, g);
+    if (gathered && lane == 0 && g) atomicAdd(gathered, g);
 }
 
 // ---------------------------------------------------------------------------
@@ -601,15 +687,70 @@ __global__ __launch_bounds__(NT) void k_spgemm(
     }
 }
 
+// Entries p .. p + U*64 - 1 of a B row (base bb, length bl >= 1), one per lane
+// and step u.  The loads are unconditional (positions clamped to the row's
+// last entry) and their results are not inspected here, so a chunk issues as
+// one straight run of loads whose latency later work can hide; lanes past the
+// row end hold a copy of the last entry and are masked by the consumer.
+template <typename V, int U>
+__device__ __forceinline__ void gather_chunk(const MatView<V> &B, int64_t bb, int p, int bl,
+                                             int lane, int (&c)[U], V (&bv)[U]) {
+    const int32_t *colp = B.col + bb;
+    const V *valp = B.val + bb;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int at = min(p + u * kWave + lane, bl - 1);
+        c[u] = colp[at];
+        bv[u] = valp[at];
+    }
+}
+
+// Adds one chunk loaded by gather_chunk at position p of a B row of length bl
+// (columns c, values bv) times the group's coefficients aq into the rows' LDS
+// windows [wlo, whi) of the rows present at the slot (bits of mq).  Entries
+// outside the window and lanes past the row end go to per-lane sink columns
+// T+lane, which keeps the accumulation free of divergent branches.  Returns the
+// number of the chunk's entries inside the window (a prefix of the chunk) and,
+// in *next, the column of the first entry after them (INT_MAX past the row end).
+template <typename V, int R, int T, int U>
+__device__ __forceinline__ int group_accumulate(V (*acc)[T + kWave], const int (&c)[U],
+                                                const V (&bv)[U], const V (&aq)[R], uint32_t mq,
+                                                int p, int bl, int wlo, int whi, int lane,
+                                                int *next) {
+    int got = 0, slot[U], col[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        col[u] = p + u * kWave + lane < bl ? c[u] : INT_MAX;
+        const bool in = col[u] < whi;
+        slot[u] = in ? col[u] - wlo : T + lane;
+        got += __popcll(__ballot(in));
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (!((mq >> r) & 1u)) continue;  // uniform: row i+r has no entry at this slot
+#pragma unroll
+        for (int u = 0; u < U; ++u) atomicAdd(&acc[r][slot[u]], aq[r] * bv[u]);
+    }
+    if (got < U * kWave) {
+        int cs = INT_MAX;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (u == (got >> 6)) cs = col[u];
+        *next = __shfl(cs, got & (kWave - 1));
+    }
+    return got;
+}
+
 // Group variant for wide rows: one workgroup computes R consecutive output
-// rows i .. i+R-1 from their merged A list.  Each chunk of a B row is gathered
+// rows i .. i+R-1 from their merged A list (k_merge_group).  Each chunk of a B row is gathered
 // once and added into every row's LDS window that references it (R
 // accumulators of `tile` columns), so the gathered B bytes of the group are
 // paid once -- neighbouring rows of these matrices reference almost the same
 // rows of B.
-template <typename V, int R, int T, int NT>
+template <typename V, int R, int T, int NT, int U>
 __global__ __launch_bounds__(NT) void k_spgemm_group(
-    const int32_t *__restrict__ rows, const int32_t *__restrict__ mk, const V *__restrict__ mv,
+    const int32_t *__restrict__ rows, const int32_t *__restrict__ mk,
+    const uint32_t *__restrict__ mm, const int32_t *__restrict__ mc, const V *__restrict__ cv,
     const int32_t *__restrict__ mlen, MatView<V> A, MatView<V> B, MatView<V> D, V coef,
     V dcoef, V diag, const int32_t *__restrict__ row_lo, const int32_t *__restrict__ row_span,
     const int64_t *__restrict__ off, int64_t base, int32_t *__restrict__ out_col,
@@ -619,9 +760,13 @@ __global__ __launch_bounds__(NT) void k_spgemm_group(
     constexpr int NW = NT / kWave;
     constexpr int REG = T / NW;
     static_assert(T % (NW * kWave) == 0, "tile must split evenly over the waves");
-    __shared__ V acc[R][T];
+    // columns T .. T+63 of each row are per-lane sinks: lanes whose entry lies
+    // outside the window, or whose row has no entry at the slot, add there, so
+    // the accumulation runs without branches
+    __shared__ V acc[R][T + kWave];
     __shared__ int wcnt[NW];
-    __shared__ double wsum[2 * R][NW];
+    __shared__ double wsum[2 * R][NW];  // per-wave partial sums of squares, per row
+    __shared__ int wrt[R];              // entries written so far, per row
 
     const int lane = lane_id(), wave = wave_id();
     const int i = rows[xcd_row(blockIdx.x, gridDim.x)];
@@ -636,10 +781,8 @@ __global__ __launch_bounds__(NT) void k_spgemm_group(
     const bool multi = hi - lo > T;
     const bool has_d = D.len != nullptr;
 
-    int written[R];
-    double sqp[R], sqo[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) { written[r] = 0; sqp[r] = 0.0; sqo[r] = 0.0; }
+    for (int q = threadIdx.x; q < 2 * R * NW; q += NT) (&wsum[0][0])[q] = 0.0;
+    if (threadIdx.x < R) wrt[threadIdx.x] = 0;
     for (int wlo = lo; wlo < hi; wlo += T) {
         const int nsl = min(T, hi - wlo);
         const int whi = wlo + nsl;
@@ -651,80 +794,88 @@ __global__ __launch_bounds__(NT) void k_spgemm_group(
 
         for (int t0 = wave * kWave; t0 < ml; t0 += NW * kWave) {
             const int t = t0 + lane;
-            int bl = 0, cur = 0, nc = INT_MIN;
+            int bl = 0, cur = 0, nc = INT_MIN, msk = 0;
             int64_t bb = 0;
-            V a[R];
+            V a[R];  // this lane's slot: coefficient of each row of the group (0 if absent)
 #pragma unroll
             for (int r = 0; r < R; ++r) a[r] = V(0);
             if (t < ml) {
                 const int64_t pa = mbeg + t;
                 const int k = mk[pa];
+                const uint32_t m = mm[pa];
+                const V *cp = cv + mbeg + mc[pa];
+                int j = 0;
 #pragma unroll
-                for (int r = 0; r < R; ++r) a[r] = coef * mv[pa * R + r];
+                for (int r = 0; r < R; ++r)
+                    if ((m >> r) & 1u) a[r] = coef * cp[j++];
+                msk = (int)m;
                 bb = B.beg[k];
                 bl = B.len[k];
                 if (!first) { cur = cursor[pa]; nc = cnext[pa]; }
             }
-            const int cnt = min(kWave, ml - t0);
-            for (int q = 0; q < cnt; ++q) {
-                const int blq = rl_i32(bl, q);
-                int p = rl_i32(cur, q);
-                // B rows with nothing left in this window are skipped without a load
-                if (p < blq && rl_i32(nc, q) < whi) {
-                    const int64_t bbq = rl_i64(bb, q);
+            // slots with B entries left in this window; the others cost nothing
+            uint64_t act = __ballot(t < ml && cur < bl && nc < whi);
+            if (act) {
+                int c[U], cn[U];
+                V bv[U], bn[U];
+                int q = __builtin_ctzll(act);
+                act &= act - 1;
+                int p = rl_i32(cur, q), blq = rl_i32(bl, q);
+                int64_t bbq = rl_i64(bb, q);
+                gather_chunk<V, U>(B, bbq, p, blq, lane, c, bv);
+                while (true) {
+                    // issue the first chunk of the next active slot before this
+                    // slot's accumulation, so its latency overlaps the atomics.  The
+                    // loads are issued on every pass (re-reading this slot's chunk
+                    // when no slot is left) so that all paths wait alike.
+                    const bool more = act != 0;
+                    const int qn = more ? __builtin_ctzll(act) : q;
+                    act &= act - 1;
+                    const int pn = rl_i32(cur, qn), bln = rl_i32(bl, qn);
+                    const int64_t bbn = rl_i64(bb, qn);
+                    gather_chunk<V, U>(B, bbn, pn, bln, lane, cn, bn);
                     V aq[R];
 #pragma unroll
                     for (int r = 0; r < R; ++r) aq[r] = rl_val(a[r], q);
-                    while (true) {
-                        int c[kUnroll];
-                        V bv[kUnroll];
-#pragma unroll
-                        for (int u = 0; u < kUnroll; ++u) {
-                            const int pos = p + u * kWave + lane;
-                            c[u] = INT_MAX;
-                            bv[u] = V(0);
-                            if (pos < blq) {
-                                c[u] = B.col[bbq + pos];
-                                bv[u] = B.val[bbq + pos];
-                            }
-                        }
-                        int got = 0;
-#pragma unroll
-                        for (int u = 0; u < kUnroll; ++u) {
-                            const bool in = c[u] < whi;
-                            if (in) {
-#pragma unroll
-                                for (int r = 0; r < R; ++r)
-                                    if (aq[r] != V(0)) atomicAdd(&acc[r][c[u] - wlo], aq[r] * bv[u]);
-                            }
-                            got += __popcll(__ballot(in));
-                        }
+                    const uint32_t mq = (uint32_t)rl_i32(msk, q);
+                    // the first chunk is accumulated straight after the next slot's
+                    // loads were issued; chunks after it are loaded on demand
+                    int nxt = INT_MAX;
+                    int got = group_accumulate<V, R, T, U>(acc, c, bv, aq, mq, p, blq, wlo,
+                                                           whi, lane, &nxt);
+                    p += got;
+                    while (got == U * kWave) {
+                        gather_chunk<V, U>(B, bbq, p, blq, lane, c, bv);
+                        got = group_accumulate<V, R, T, U>(acc, c, bv, aq, mq, p, blq, wlo,
+                                                               whi, lane, &nxt);
                         p += got;
-                        if (got < kUnroll * kWave) {
-                            // column of the first entry beyond the window, for the next one
-                            int cs = INT_MAX;
-#pragma unroll
-                            for (int u = 0; u < kUnroll; ++u)
-                                if (u == (got >> 6)) cs = c[u];
-                            const int nxt = __shfl(cs, got & (kWave - 1));
-                            if (multi && lane == q) nc = nxt;
-                            break;
-                        }
                     }
+                    // column of the first entry beyond the window, for the next one
+                    if (multi && lane == q) nc = nxt;
+                    if (multi && lane == q) cur = p;
+                    if (!more) break;
+                    q = qn;
+                    p = pn;
+                    blq = bln;
+                    bbq = bbn;
+#pragma unroll
+                    for (int u = 0; u < U; ++u) { c[u] = cn[u]; bv[u] = bn[u]; }
                 }
-                if (multi && lane == q) cur = p;
             }
             if (multi && t < ml) { cursor[mbeg + t] = cur; cnext[mbeg + t] = nc; }
         }
         __syncthreads();
 
         if (sq_prod) {
-            for (int s = threadIdx.x; s < nsl; s += NT)
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
+            for (int r = 0; r < R; ++r) {
+                double x = 0.0;
+                for (int s = threadIdx.x; s < nsl; s += NT) {
                     const double v = as_f64(acc[r][s]);
-                    sqp[r] += v * v;
+                    x += v * v;
                 }
+                x = wave_sum(x);
+                if (lane == 0) wsum[2 * r][wave] += x;
+            }
             __syncthreads();
         }
         if (has_d) {
@@ -745,7 +896,6 @@ __global__ __launch_bounds__(NT) void k_spgemm_group(
         }
         __syncthreads();
 
-#pragma unroll
         for (int r = 0; r < R; ++r) {
             const int64_t obase = off[i + r] - base;
             const int rbeg = wave * REG;
@@ -757,7 +907,8 @@ __global__ __launch_bounds__(NT) void k_spgemm_group(
             }
             if (lane == 0) wcnt[wave] = cw;
             __syncthreads();
-            int o = written[r], tot = 0;
+            int o = wrt[r], tot = 0;
+            double y = 0.0;
             for (int w = 0; w < NW; ++w) {
                 const int c = wcnt[w];
                 if (w < wave) o += c;
@@ -772,30 +923,26 @@ __global__ __launch_bounds__(NT) void k_spgemm_group(
                     const int64_t pos = obase + o + lanes_below(m);
                     out_col[pos] = wlo + s;
                     out_val[pos] = v;
-                    sqo[r] += as_f64(v) * as_f64(v);
+                    y += as_f64(v) * as_f64(v);
                 }
                 o += __popcll(m);
             }
-            written[r] += tot;
-            __syncthreads();
+            y = wave_sum(y);
+            if (lane == 0) wsum[2 * r + 1][wave] += y;
+            __syncthreads();  // every wave has read wrt[r] and wcnt
+            if (threadIdx.x == 0) wrt[r] += tot;
         }
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const double x = wave_sum(sqp[r]), y = wave_sum(sqo[r]);
-        if (lane == 0) { wsum[2 * r][wave] = x; wsum[2 * r + 1][wave] = y; }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long tw = 0;
-#pragma unroll
         for (int r = 0; r < R; ++r) {
             double x = 0.0, y = 0.0;
             for (int w = 0; w < NW; ++w) { x += wsum[2 * r][w]; y += wsum[2 * r + 1][w]; }
-            out_len[i + r] = written[r];
+            out_len[i + r] = wrt[r];
             if (sq_prod) sq_prod[i + r] = x;
             if (sq_out) sq_out[i + r] = y;
-            tw += (unsigned long long)written[r];
+            tw += (unsigned long long)wrt[r];
         }
         if (out_count) atomicAdd((unsigned long long *)out_count, tw);
     }
@@ -1222,55 +1369,95 @@ BinCfg bin_config(int cls, int value_bytes) {
     switch (cls) {
         case 1: return {512, 64};
         case 2: return {4096, 256};
-        case 4: return {value_bytes == 8 ? 4096 : 8192, 1024};
         default: return {value_bytes == 8 ? 8192 : 16384, 512};
     }
 }
 
 template <typename V>
 void launch_merge_group(int group, const int32_t *leads, int ngroups, MatView<V> A, MatView<V> B,
-                        int32_t *mk, V *mv, int32_t *mlen, int64_t *gathered, hipStream_t s) {
+                        int32_t *mk, uint32_t *mm, int32_t *mc, V *cv, int32_t *mlen,
+                        int64_t *gathered, hipStream_t s) {
     if (ngroups <= 0) return;
     unsigned long long *g = (unsigned long long *)gathered;
-    if (group == 2)
-        k_merge_group<V, 2><<<blocks_for(ngroups, 64), 64, 0, s>>>(leads, ngroups, A, B, mk, mv,
+    switch (group) {
+        case 2:
+            k_merge_group<V, 2><<<ngroups, kMergeThreads, 0, s>>>(leads, A, B, mk, mm, mc, cv,
                                                                    mlen, g);
-    else
-        k_merge_group<V, 4><<<blocks_for(ngroups, 64), 64, 0, s>>>(leads, ngroups, A, B, mk, mv,
+            break;
+        case 4:
+            k_merge_group<V, 4><<<ngroups, kMergeThreads, 0, s>>>(leads, A, B, mk, mm, mc, cv,
                                                                    mlen, g);
+            break;
+        case 8:
+            k_merge_group<V, 8><<<ngroups, kMergeThreads, 0, s>>>(leads, A, B, mk, mm, mc, cv,
+                                                                   mlen, g);
+            break;
+        default:
+            k_merge_group<V, 16><<<ngroups, kMergeThreads, 0, s>>>(leads, A, B, mk, mm, mc, cv,
+                                                                    mlen, g);
+            break;
+    }
 }
 template void launch_merge_group<double>(int, const int32_t *, int, MatView<double>,
-                                         MatView<double>, int32_t *, double *, int32_t *,
-                                         int64_t *, hipStream_t);
+                                         MatView<double>, int32_t *, uint32_t *, int32_t *,
+                                         double *, int32_t *, int64_t *, hipStream_t);
 template void launch_merge_group<float>(int, const int32_t *, int, MatView<float>, MatView<float>,
-                                        int32_t *, float *, int32_t *, int64_t *, hipStream_t);
+                                        int32_t *, uint32_t *, int32_t *, float *, int32_t *,
+                                        int64_t *, hipStream_t);
+
+// LDS accumulators of a group kernel: 128 KB for groups of 4 and more (64 KB for
+// pairs), split into `group` windows.
+BinCfg group_config(int group, int value_bytes) {
+    if (group == 2) return {value_bytes == 8 ? 4096 : 8192, 512};
+    return {(value_bytes == 8 ? 16384 : 32768) / group, 1024};
+}
+
+template <typename V, int R>
+static void group_launch(const int32_t *leads, int ngroups, const int32_t *mk, const uint32_t *mm,
+                         const int32_t *mc, const V *cv, const int32_t *mlen, MatView<V> A,
+                         MatView<V> B, MatView<V> D, double coef, double dcoef, double diag,
+                         const int32_t *lo, const int32_t *span, int64_t base, const int64_t *off,
+                         int32_t *out_col, V *out_val, int32_t *out_len, int32_t *cursor,
+                         int32_t *cnext, double *sq_prod, double *sq_out, int64_t *out_count,
+                         hipStream_t s) {
+    constexpr int T = R == 2 ? (sizeof(V) == 8 ? 4096 : 8192)
+                             : (sizeof(V) == 8 ? 16384 : 32768) / R;
+    constexpr int NT = R == 2 ? 512 : 1024;
+    k_spgemm_group<V, R, T, NT, kGroupUnroll><<<ngroups, NT, 0, s>>>(
+        leads, mk, mm, mc, cv, mlen, A, B, D, (V)coef, (V)dcoef, (V)diag, lo, span, off, base,
+        out_col, out_val, out_len, cursor, cnext, sq_prod, sq_out, out_count);
+}
 
 template <typename V>
 void launch_spgemm_group(int group, const int32_t *leads, int ngroups, const int32_t *mk,
-                         const V *mv, const int32_t *mlen, MatView<V> A, MatView<V> B,
-                         MatView<V> D, double coef, double dcoef, double diag, const int32_t *lo,
-                         const int32_t *span, int64_t base, const int64_t *off, int32_t *out_col,
-                         V *out_val, int32_t *out_len, int32_t *cursor, int32_t *cnext,
-                         double *sq_prod, double *sq_out, int64_t *out_count, hipStream_t s) {
+                         const uint32_t *mm, const int32_t *mc, const V *cv, const int32_t *mlen,
+                         MatView<V> A, MatView<V> B, MatView<V> D, double coef, double dcoef,
+                         double diag, const int32_t *lo, const int32_t *span, int64_t base,
+                         const int64_t *off, int32_t *out_col, V *out_val, int32_t *out_len,
+                         int32_t *cursor, int32_t *cnext, double *sq_prod, double *sq_out,
+                         int64_t *out_count, hipStream_t s) {
     if (ngroups <= 0) return;
-    constexpr int T2 = sizeof(V) == 8 ? 4096 : 8192;
-    if (group == 2)
-        k_spgemm_group<V, 2, T2, 512><<<ngroups, 512, 0, s>>>(
-            leads, mk, mv, mlen, A, B, D, (V)coef, (V)dcoef, (V)diag, lo, span, off, base, out_col,
-            out_val, out_len, cursor, cnext, sq_prod, sq_out, out_count);
-    else
-        k_spgemm_group<V, 4, T2, 1024><<<ngroups, 1024, 0, s>>>(
-            leads, mk, mv, mlen, A, B, D, (V)coef, (V)dcoef, (V)diag, lo, span, off, base, out_col,
-            out_val, out_len, cursor, cnext, sq_prod, sq_out, out_count);
+#define SFN_GROUP_ARGS                                                                        \
+    leads, ngroups, mk, mm, mc, cv, mlen, A, B, D, coef, dcoef, diag, lo, span, base, off,    \
+        out_col, out_val, out_len, cursor, cnext, sq_prod, sq_out, out_count, s
+    switch (group) {
+        case 2: group_launch<V, 2>(SFN_GROUP_ARGS); break;
+        case 4: group_launch<V, 4>(SFN_GROUP_ARGS); break;
+        case 8: group_launch<V, 8>(SFN_GROUP_ARGS); break;
+        default: group_launch<V, 16>(SFN_GROUP_ARGS); break;
+    }
+#undef SFN_GROUP_ARGS
 }
 template void launch_spgemm_group<double>(int, const int32_t *, int, const int32_t *,
-                                          const double *, const int32_t *, MatView<double>,
-                                          MatView<double>, MatView<double>, double, double, double,
+                                          const uint32_t *, const int32_t *, const double *,
+                                          const int32_t *, MatView<double>, MatView<double>,
+                                          MatView<double>, double, double, double,
                                           const int32_t *, const int32_t *, int64_t,
                                           const int64_t *, int32_t *, double *, int32_t *,
                                           int32_t *, int32_t *, double *, double *, int64_t *,
                                           hipStream_t);
-template void launch_spgemm_group<float>(int, const int32_t *, int, const int32_t *, const float *,
+template void launch_spgemm_group<float>(int, const int32_t *, int, const int32_t *,
+                                         const uint32_t *, const int32_t *, const float *,
                                          const int32_t *, MatView<float>, MatView<float>,
                                          MatView<float>, double, double, double, const int32_t *,
                                          const int32_t *, int64_t, const int64_t *, int32_t *,

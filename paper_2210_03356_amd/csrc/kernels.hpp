@@ -70,7 +70,7 @@ void launch_plan(MatView<V> A, MatView<V> B, MatView<V> D, int diag, int64_t r0,
 // Row classes: 0 empty, 1..3 tiles.  Writes row lists per class (bins[c] holds
 // up to r1-r0 rows), counts into counts[4] (device), and len=0 for empty rows.
 // Row classes 1..3 by column span (and work), class 4 = leaders i of aligned
-// groups of `group` consecutive wide rows (group 2 or 4; 1 disables grouping;
+// groups of `group` consecutive wide rows (group 2, 4, 8 or 16; 1 disables grouping;
 // the other rows of a group are then listed nowhere).
 // cstat (optional): per class c, cstat[8c+1] += products, [8c+2] += nnz of the
 // A rows, [8c+3] += nnz of the D rows (d_len may be null).
@@ -79,19 +79,24 @@ void launch_bin_rows(const int32_t *span, const int64_t *work, int64_t r0, int64
                      int32_t *counts, int32_t *out_len, double *sq_prod, double *sq_out,
                      const int32_t *a_len, const int32_t *d_len, int64_t *cstat,
                      hipStream_t s);
-// Groups: merged (k, a_i .. a_{i+group-1}) lists stored in the index range of the
-// group's rows of A (A must be compact), coefficients interleaved mv[pos*group + r];
-// *gathered += sum of nnz(B_k) over the merged lists.
+// Groups: merged list of the group's A rows stored in the group's index range
+// of A (A must be compact): slot columns mk, row masks mm, coefficient offsets
+// mc (into cv, relative to the group's first index), coefficients cv ordered
+// by (slot, row); *gathered += sum of nnz(B_k) over the slots.
 template <typename V>
 void launch_merge_group(int group, const int32_t *leads, int ngroups, MatView<V> A, MatView<V> B,
-                        int32_t *mk, V *mv, int32_t *mlen, int64_t *gathered, hipStream_t s);
+                        int32_t *mk, uint32_t *mm, int32_t *mc, V *cv, int32_t *mlen,
+                        int64_t *gathered, hipStream_t s);
 template <typename V>
 void launch_spgemm_group(int group, const int32_t *leads, int ngroups, const int32_t *mk,
-                         const V *mv, const int32_t *mlen, MatView<V> A, MatView<V> B,
-                         MatView<V> D, double coef, double dcoef, double diag, const int32_t *lo,
-                         const int32_t *span, int64_t base, const int64_t *off, int32_t *out_col,
-                         V *out_val, int32_t *out_len, int32_t *cursor, int32_t *cnext,
-                         double *sq_prod, double *sq_out, int64_t *out_count, hipStream_t s);
+                         const uint32_t *mm, const int32_t *mc, const V *cv, const int32_t *mlen,
+                         MatView<V> A, MatView<V> B, MatView<V> D, double coef, double dcoef,
+                         double diag, const int32_t *lo, const int32_t *span, int64_t base,
+                         const int64_t *off, int32_t *out_col, V *out_val, int32_t *out_len,
+                         int32_t *cursor, int32_t *cnext, double *sq_prod, double *sq_out,
+                         int64_t *out_count, hipStream_t s);
+// tile = LDS accumulator columns per row of the group
+BinCfg group_config(int group, int value_bytes);
 
 // Numeric product for the rows listed in `rows` (class cfg).  Row i writes
 // at out_col/out_val[off[i] - base .. ), out_len[i], sq_prod[i] (sum of squares

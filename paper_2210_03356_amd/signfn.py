@@ -53,7 +53,8 @@ class sign_stats(C.Structure):
                 ("hot_threads", C.c_int), ("hot_fp32", C.c_int), ("hot_group", C.c_int),
                 ("hot_launches", C.c_int64),
                 ("hot_ms", C.c_double),
-                ("hot_bytes", C.c_double), ("hot_products", C.c_int64)]
+                ("hot_bytes", C.c_double), ("hot_products", C.c_int64),
+                ("hot_gathered", C.c_int64)]
 
 
 class sign_iter_stats(C.Structure):

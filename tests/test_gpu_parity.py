@@ -334,10 +334,13 @@ def _wide_rows_matrix(nx=203, ny=61, radius=11, seed=21):
     return W.Csr(n=n, indptr=indptr, indices=indices, data=data)
 
 
-@pytest.mark.parametrize("group", [1, 2, 4])
+GROUPS = [1, 2, 4, 8, 16]
+
+
+@pytest.mark.parametrize("group", GROUPS)
 def test_row_groups_match_oracle(sf, monkeypatch, group):
     """Wide rows computed in groups (one gather of a B row feeding the
-    accumulators of 2 or 4 consecutive output rows) give the oracle's product,
+    accumulators of up to 16 consecutive output rows) give the oracle's product,
     including groups that mix wide and narrower rows and a ragged last group."""
     monkeypatch.setenv("SIGNFN_ROW_GROUP", str(group))
     A = _wide_rows_matrix()
@@ -349,11 +352,20 @@ def test_row_groups_match_oracle(sf, monkeypatch, group):
             assert st["products"] > 0
 
 
-@pytest.mark.parametrize("group", [1, 2, 4])
-def test_row_groups_nsf(sf, monkeypatch, group):
+@pytest.fixture(scope="module")
+def lap96_oracle():
+    """2D case whose iterates have wide rows (spans above 4096 columns)."""
+    A = W.laplacian_2d(96, jitter=0.05, seed=2, m=8.0)
+    return A, oracle.nsf(A, tol=1e-12)
+
+
+@pytest.mark.parametrize("group", GROUPS)
+def test_row_groups_nsf(sf, monkeypatch, lap96_oracle, group):
     """The whole iteration with each row-group setting matches the oracle."""
     monkeypatch.setenv("SIGNFN_ROW_GROUP", str(group))
-    A = W.laplacian_2d(48, jitter=0.05, seed=2, m=8.0)
-    X = oracle.nsf(A, tol=1e-12)
+    A, X = lap96_oracle
     r = sf.sign_ns(_dev(sf, A), sf.default_opts(tol=1e-12))
-    assert sp.linalg.norm(r.to_scipy() - X.to_scipy()) / sp.linalg.norm(X.to_scipy()) <= 1e-10
+    st = r.stats()
+    assert st["hot_group"] in (1, group)
+    S = X.to_scipy()
+    assert sp.linalg.norm(r.to_scipy() - S) / sp.linalg.norm(S) <= 1e-10
