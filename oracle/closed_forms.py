@@ -12,6 +12,9 @@
   and the Schur form sign(A) = Q sign(T) Q^* for general A, with the Schur
   form ordered so that the left-half-plane eigenvalues come first; then
   sign(T) = [[-I, Y], [0, I]] with T11 Y - Y T22 = -2 T12.
+* A matrix diagonally similar to a symmetric one, M = D S D^-1 with S
+  symmetric and D = diag(d) > 0, has sign(M) = D sign(S) D^-1, since a
+  matrix function commutes with similarity.
 """
 from __future__ import annotations
 
@@ -128,3 +131,19 @@ def local_sign_row(A, i: int, radius: int):
     S = dense_sign(sub)
     loc = int(np.searchsorted(idx, i))
     return idx, S[loc]
+
+
+def local_sign_row_similar(A, i: int, radius: int, d: np.ndarray):
+    """local_sign_row for a matrix with D^-1 A D symmetric, D = diag(d): the patch
+    sign is D_B sign(D_B^-1 A_B D_B) D_B^-1 with a symmetric eigendecomposition
+    (principal submatrices keep the similarity).  Raises if D^-1 A_B D_B is not
+    symmetric to rounding."""
+    idx = ball(A, i, radius)
+    sub = A.to_scipy()[idx][:, idx].toarray()
+    dB = np.asarray(d, dtype=np.float64)[idx]
+    S = sub * (dB[None, :] / dB[:, None])
+    if not np.allclose(S, S.T, rtol=0, atol=1e-13 * np.abs(S).max()):
+        raise ValueError("patch is not symmetric under the given scaling")
+    sS = dense_sign_sym(0.5 * (S + S.T))
+    loc = int(np.searchsorted(idx, i))
+    return idx, sS[loc] * (dB[loc] / dB)

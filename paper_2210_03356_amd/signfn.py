@@ -224,6 +224,25 @@ class Result:
             _copy_d2h(va, v.val)
         return rp, ci, va
 
+    def rows(self, idx):
+        """Host copies of the listed rows only: {i: (columns int32, values)}."""
+        v = self.view()
+        load()
+        rp = np.empty(v.n + 1, np.int64)
+        _copy_d2h(rp, v.row_ptr)
+        isz = 4
+        vsz = 4 if v.val_f32 else 8
+        out = {}
+        for i in sorted(set(int(i) for i in idx)):
+            b, e = int(rp[i]), int(rp[i + 1])
+            ci = np.empty(e - b, np.int32)
+            va = np.empty(e - b, np.float32 if v.val_f32 else np.float64)
+            if e > b:
+                _copy_d2h(ci, v.col + b * isz)
+                _copy_d2h(va, v.val + b * vsz)
+            out[i] = (ci, va)
+        return out
+
     def to_scipy(self):
         import scipy.sparse as sp
         rp, ci, va = self.to_numpy()

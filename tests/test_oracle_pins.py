@@ -370,3 +370,18 @@ def test_nsf_loop_obeys_eq_1_8(oracle_lib, make):
     n = A.n
     for k in range(len(e) - 1):
         assert e[k + 1] <= 0.75 * e[k] ** 2 + 0.25 * e[k] ** 3 + 1e-14 * math.sqrt(n) * 10, (k, e)
+
+
+def test_local_sign_row_similar_matches_schur():
+    """The diagonal-similarity route to a patch sign (symmetric eigensolver) gives
+    the Schur-method row on a nonsymmetric convection-diffusion patch."""
+    A = W.convdiff_2d(14, beta=0.5, sigma=4.0, m=8.0)
+    N = 14
+    d = np.sqrt(1.0 + A.meta["b"]) ** (np.arange(A.n) % N)
+    for i in (0, 5 * N + 6, A.n - 1):
+        idx1, r1 = cf.local_sign_row(A, i, 6)
+        idx2, r2 = cf.local_sign_row_similar(A, i, 6, d)
+        assert np.array_equal(idx1, idx2)
+        assert np.abs(r1 - r2).max() <= 1e-13
+    with pytest.raises(ValueError):
+        cf.local_sign_row_similar(A, 7, 4, np.ones(A.n))
