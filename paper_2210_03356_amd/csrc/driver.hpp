@@ -18,7 +18,7 @@ struct Workspace {
     DevBuf rs1, rs2, rs3, rs4, icnt, hist, tau, bstar, seg, red, flag, zero_b;
     DevBuf cstat, mk, mm, mc, cv, mlen, cnext;
     const uint8_t *row_skip = nullptr;  // optional row mask for products (serving)
-    int row_group = 4;                  // wide rows computed in groups of 1, 2, 4, 8 or 16
+    int row_group = 8;                  // wide rows computed in groups of 1, 2, 4, 8 or 16
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     // accumulated product statistics, in total and per row class (kernel tile)
     struct ClassStat {

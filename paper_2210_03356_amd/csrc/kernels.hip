@@ -706,30 +706,30 @@ __device__ __forceinline__ void gather_chunk(const MatView<V> &B, int64_t bb, in
 }
 
 // Adds one chunk loaded by gather_chunk at position p of a B row of length bl
-// (columns c, values bv) times the group's coefficients aq into the rows' LDS
-// windows [wlo, whi) of the rows present at the slot (bits of mq).  Entries
-// outside the window and lanes past the row end go to per-lane sink columns
-// T+lane, which keeps the accumulation free of divergent branches.  Returns the
-// number of the chunk's entries inside the window (a prefix of the chunk) and,
-// in *next, the column of the first entry after them (INT_MAX past the row end).
+// (columns c, values bv) times the group's coefficients aq into the LDS windows
+// [wlo, whi) of the rows present at the slot (bits of mq; a uniform test).
+// Lanes whose entry lies outside the window or past the row end are masked
+// off.  Returns the number of the chunk's entries inside the window (a prefix
+// of the chunk) and, in *next, the column of the first entry after them
+// (INT_MAX past the row end).
 template <typename V, int R, int T, int U>
-__device__ __forceinline__ int group_accumulate(V (*acc)[T + kWave], const int (&c)[U],
-                                                const V (&bv)[U], const V (&aq)[R], uint32_t mq,
-                                                int p, int bl, int wlo, int whi, int lane,
-                                                int *next) {
-    int got = 0, slot[U], col[U];
+__device__ __forceinline__ int group_accumulate(V (*acc)[T], const int (&c)[U], const V (&bv)[U],
+                                                const V (&aq)[R], uint32_t mq, int p, int bl,
+                                                int wlo, int whi, int lane, int *next) {
+    int got = 0, col[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         col[u] = p + u * kWave + lane < bl ? c[u] : INT_MAX;
-        const bool in = col[u] < whi;
-        slot[u] = in ? col[u] - wlo : T + lane;
-        got += __popcll(__ballot(in));
+        got += __popcll(__ballot(col[u] < whi));
     }
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        if (!((mq >> r) & 1u)) continue;  // uniform: row i+r has no entry at this slot
+    for (int u = 0; u < U; ++u) {
+        if (col[u] < whi) {
+            const int s = col[u] - wlo;
 #pragma unroll
-        for (int u = 0; u < U; ++u) atomicAdd(&acc[r][slot[u]], aq[r] * bv[u]);
+            for (int r = 0; r < R; ++r)
+                if ((mq >> r) & 1u) atomicAdd(&acc[r][s], aq[r] * bv[u]);
+        }
     }
     if (got < U * kWave) {
         int cs = INT_MAX;
@@ -760,10 +760,7 @@ __global__ __launch_bounds__(NT) void k_spgemm_group(
     constexpr int NW = NT / kWave;
     constexpr int REG = T / NW;
     static_assert(T % (NW * kWave) == 0, "tile must split evenly over the waves");
-    // columns T .. T+63 of each row are per-lane sinks: lanes whose entry lies
-    // outside the window, or whose row has no entry at the slot, add there, so
-    // the accumulation runs without branches
-    __shared__ V acc[R][T + kWave];
+    __shared__ V acc[R][T];
     __shared__ int wcnt[NW];
     __shared__ double wsum[2 * R][NW];  // per-wave partial sums of squares, per row
     __shared__ int wrt[R];              // entries written so far, per row
