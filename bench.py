@@ -37,9 +37,7 @@ def kernel_hash() -> str:
 def kernel_name(st, tile) -> str:
     """Name and template arguments of the hottest numeric product kernel."""
     v = "float" if st["hot_fp32"] else "double"
-    if st["hot_group"] > 1:
-        return f"k_spgemm_group<{v},{st['hot_group']},{tile},{st['hot_threads']}>"
-    return f"k_spgemm<{v},{tile},{st['hot_threads']}>"
+    return f"k_spgemm_rows<{v},{st['hot_group']},{tile},{st['hot_threads']}>"
 
 
 def read_traffic(st, config: str, precision: int):
@@ -115,6 +113,8 @@ def sampled_properties(res, A, rows):
 def device_trace(res):
     """trace(X) of a result, summed on the device."""
     import torch
+    import paper_2210_03356_amd as sf
+    sf.release_cached()   # the library's cached blocks back to HIP, for torch's copies
     rp, ci, va = res.to_torch()
     n = rp.numel() - 1
     r = torch.repeat_interleave(torch.arange(n, device=rp.device), rp[1:] - rp[:-1])

@@ -164,6 +164,13 @@ SIGNFN_API void sign_result_free(sign_result *r);
 /* Thread-local message of the last failing call ("" if none). */
 SIGNFN_API const char *sign_last_error(void);
 
+/* Device memory that the library keeps cached for reuse between calls (segments
+ * no live result, server or call is using) goes back to the HIP allocator, so
+ * that other allocators in the process (a framework's) can use it.  Returns the
+ * bytes released.  Has nothing to release when the caller's alloc/free hooks
+ * are in use.  Thread-safe; may be called at any time. */
+SIGNFN_API size_t sign_release_cached(void);
+
 /* ---- building blocks of the path, exposed for testing and reuse ---- */
 
 /* C = A*B (sparse x sparse, FP64 or FP32 by the inputs' val_f32, which must

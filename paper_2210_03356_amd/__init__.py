@@ -10,6 +10,7 @@ from .signfn import (  # noqa: F401
     SignError,
     default_opts,
     load,
+    release_cached,
     sign_filter,
     sign_newton,
     sign_ns,

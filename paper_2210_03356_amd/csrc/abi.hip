@@ -233,6 +233,14 @@ void sign_opts_default(sign_opts *o) {
 
 const char *sign_last_error(void) { return last_error(); }
 
+size_t sign_release_cached(void) {
+    Pool &p = Pool::instance();
+    const size_t before = p.cached_bytes();
+    p.trim();
+    const size_t after = p.cached_bytes();
+    return before > after ? before - after : 0;
+}
+
 int sign_ns(const sign_csr *A, const sign_opts *o, void *hip_stream, sign_result **out) {
     if (out) *out = nullptr;
     return guarded([&]() -> int {

@@ -21,7 +21,6 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kUnroll = 4;  // 64-entry chunks of a B row gathered per sweep step
-constexpr int kGroupUnroll = 4;  // the same for the row-group kernel
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 __device__ __forceinline__ int wave_id() { return threadIdx.x / kWave; }
@@ -521,171 +520,6 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_group(
     if (gathered && lane == 0 && g) atomicAdd(gathered, g);
 }
 
-// ---------------------------------------------------------------------------
-// numeric product
-// ---------------------------------------------------------------------------
-template <typename V, int T, int NT>
-__global__ __launch_bounds__(NT) void k_spgemm(
-    const int32_t *__restrict__ rows, MatView<V> A, MatView<V> B, MatView<V> D, V coef,
-    V dcoef, V diag, const int32_t *__restrict__ row_lo, const int32_t *__restrict__ row_span,
-    const int64_t *__restrict__ off, int64_t base, int32_t *__restrict__ out_col,
-    V *__restrict__ out_val, int32_t *__restrict__ out_len, int32_t *__restrict__ cursor, int32_t *__restrict__ cnext,
-    double *__restrict__ sq_prod, double *__restrict__ sq_out, int64_t *__restrict__ out_count) {
-    constexpr int NW = NT / kWave;
-    constexpr int REG = T / NW;  // LDS slots owned by each wave in the epilogue
-    static_assert(T % (NW * kWave) == 0, "tile must split evenly over the waves");
-    __shared__ V acc[T];
-    __shared__ int wcnt[NW];
-    __shared__ double wsum[2][NW];
-
-    const int lane = lane_id(), wave = wave_id();
-    const int i = rows[xcd_row(blockIdx.x, gridDim.x)];
-    const int lo = row_lo[i], span = row_span[i];
-    const int64_t abeg = A.beg[i];
-    const int alen = A.len[i];
-    const int64_t obase = off[i] - base;
-    const bool multi = span > T;
-    const bool has_d = D.len != nullptr;
-    const int dlen = has_d ? D.len[i] : 0;
-    const int64_t dbeg = has_d ? D.beg[i] : 0;
-
-    int written = 0;
-    double sqp = 0.0, sqo = 0.0;
-    for (int wlo = lo; wlo < lo + span; wlo += T) {
-        const int nsl = min(T, lo + span - wlo);
-        const int whi = wlo + nsl;
-        const bool first = (wlo == lo);
-        for (int s = threadIdx.x; s < nsl; s += NT) acc[s] = V(0);
-        __syncthreads();
-
-        // products: each wave takes 64 entries of row i of A at a time; lane q
-        // holds entry q's B-row descriptor, broadcast through readlane
-        for (int t0 = wave * kWave; t0 < alen; t0 += NW * kWave) {
-            const int t = t0 + lane;
-            int bl = 0, cur = 0, nc = INT_MIN;
-            int64_t bb = 0;
-            V a = V(0);
-            if (t < alen) {
-                const int64_t pa = abeg + t;
-                const int k = A.col[pa];
-                a = coef * A.val[pa];
-                bb = B.beg[k];
-                bl = B.len[k];
-                if (!first) { cur = cursor[pa]; nc = cnext[pa]; }
-            }
-            const int cnt = min(kWave, alen - t0);
-            for (int q = 0; q < cnt; ++q) {
-                const int blq = rl_i32(bl, q);
-                int p = rl_i32(cur, q);
-                // B rows with nothing left in this window are skipped without a load
-                if (p < blq && rl_i32(nc, q) < whi) {
-                    const int64_t bbq = rl_i64(bb, q);
-                    const V aq = rl_val(a, q);
-                    // kUnroll chunks of 64 entries in flight per wave; B rows
-                    // are sorted, so the in-window entries form a prefix and
-                    // the sweep stops at the first chunk that is not full
-                    while (true) {
-                        int c[kUnroll];
-                        V bv[kUnroll];
-#pragma unroll
-                        for (int u = 0; u < kUnroll; ++u) {
-                            const int pos = p + u * kWave + lane;
-                            c[u] = INT_MAX;
-                            bv[u] = V(0);
-                            if (pos < blq) {
-                                c[u] = B.col[bbq + pos];
-                                bv[u] = B.val[bbq + pos];
-                            }
-                        }
-                        int got = 0;
-#pragma unroll
-                        for (int u = 0; u < kUnroll; ++u) {
-                            const bool in = c[u] < whi;
-                            if (in) atomicAdd(&acc[c[u] - wlo], aq * bv[u]);
-                            got += __popcll(__ballot(in));
-                        }
-                        p += got;
-                        if (got < kUnroll * kWave) {
-                            // column of the first entry beyond the window, for the next one
-                            int cs = INT_MAX;
-#pragma unroll
-                            for (int u = 0; u < kUnroll; ++u)
-                                if (u == (got >> 6)) cs = c[u];
-                            const int nxt = __shfl(cs, got & (kWave - 1));
-                            if (multi && lane == q) nc = nxt;
-                            break;
-                        }
-                    }
-                }
-                if (multi && lane == q) cur = p;
-            }
-            if (multi && t < alen) { cursor[abeg + t] = cur; cnext[abeg + t] = nc; }
-        }
-        __syncthreads();
-
-        if (sq_prod) {
-            for (int s = threadIdx.x; s < nsl; s += NT) {
-                const double v = as_f64(acc[s]);
-                sqp += v * v;
-            }
-            __syncthreads();
-        }
-        if (has_d) {
-            for (int q = threadIdx.x; q < dlen; q += NT) {
-                const int c = D.col[dbeg + q];
-                if (c >= wlo && c < whi) acc[c - wlo] += dcoef * D.val[dbeg + q];
-            }
-            __syncthreads();
-        }
-        if (diag != V(0) && threadIdx.x == 0 && i >= wlo && i < whi) acc[i - wlo] += diag;
-        __syncthreads();
-
-        // write the window's nonzeros in column order
-        const int rbeg = wave * REG;
-        int cw = 0;
-        for (int s0 = rbeg; s0 < rbeg + REG && s0 < nsl; s0 += kWave) {
-            const int s = s0 + lane;
-            const V v = s < nsl ? acc[s] : V(0);
-            cw += __popcll(__ballot(v != V(0)));
-        }
-        if (lane == 0) wcnt[wave] = cw;
-        __syncthreads();
-        int o = written, tot = 0;
-        for (int w = 0; w < NW; ++w) {
-            const int c = wcnt[w];
-            if (w < wave) o += c;
-            tot += c;
-        }
-        for (int s0 = rbeg; s0 < rbeg + REG && s0 < nsl; s0 += kWave) {
-            const int s = s0 + lane;
-            const V v = s < nsl ? acc[s] : V(0);
-            const bool nz = v != V(0);
-            const uint64_t m = __ballot(nz);
-            if (nz) {
-                const int64_t pos = obase + o + lanes_below(m);
-                out_col[pos] = wlo + s;
-                out_val[pos] = v;
-                sqo += as_f64(v) * as_f64(v);
-            }
-            o += __popcll(m);
-        }
-        written += tot;
-        __syncthreads();
-    }
-    // row totals
-    sqp = wave_sum(sqp);
-    sqo = wave_sum(sqo);
-    if (lane == 0) { wsum[0][wave] = sqp; wsum[1][wave] = sqo; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double a = 0.0, b = 0.0;
-        for (int w = 0; w < NW; ++w) { a += wsum[0][w]; b += wsum[1][w]; }
-        out_len[i] = written;
-        if (sq_prod) sq_prod[i] = a;
-        if (sq_out) sq_out[i] = b;
-        if (out_count) atomicAdd((unsigned long long *)out_count, (unsigned long long)written);
-    }
-}
 
 // Entries p .. p + U*64 - 1 of a B row (base bb, length bl >= 1), one per lane
 // and step u.  The loads are unconditional (positions clamped to the row's
@@ -713,9 +547,10 @@ __device__ __forceinline__ void gather_chunk(const MatView<V> &B, int64_t bb, in
 // of the chunk) and, in *next, the column of the first entry after them
 // (INT_MAX past the row end).
 template <typename V, int R, int T, int U>
-__device__ __forceinline__ int group_accumulate(V (*acc)[T], const int (&c)[U], const V (&bv)[U],
-                                                const V (&aq)[R], uint32_t mq, int p, int bl,
-                                                int wlo, int whi, int lane, int *next) {
+__device__ __forceinline__ int group_accumulate(double (*acc)[T], const int (&c)[U],
+                                                const V (&bv)[U], const V (&aq)[R], uint32_t mq,
+                                                int p, int bl, int wlo, int whi, int lane,
+                                                int *next) {
     int got = 0, col[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -728,7 +563,7 @@ __device__ __forceinline__ int group_accumulate(V (*acc)[T], const int (&c)[U], 
             const int s = col[u] - wlo;
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                if ((mq >> r) & 1u) atomicAdd(&acc[r][s], aq[r] * bv[u]);
+                if ((mq >> r) & 1u) atomicAdd(&acc[r][s], (double)aq[r] * (double)bv[u]);
         }
     }
     if (got < U * kWave) {
@@ -741,14 +576,29 @@ __device__ __forceinline__ int group_accumulate(V (*acc)[T], const int (&c)[U], 
     return got;
 }
 
-// Group variant for wide rows: one workgroup computes R consecutive output
-// rows i .. i+R-1 from their merged A list (k_merge_group).  Each chunk of a B row is gathered
-// once and added into every row's LDS window that references it (R
-// accumulators of `tile` columns), so the gathered B bytes of the group are
-// paid once -- neighbouring rows of these matrices reference almost the same
-// rows of B.
+// ---------------------------------------------------------------------------
+// numeric product: C = diag*I + coef*A*B + dcoef*D, row-wise (Gustavson)
+// ---------------------------------------------------------------------------
+// One workgroup computes R consecutive output rows i .. i+R-1 (R = 1: a single
+// row, whose own A entries are the slots; R > 1: the merged A list of the
+// group from k_merge_group).  The rows' columns are swept in windows of T
+// consecutive columns held as dense LDS accumulators (R x T values, native
+// ds_add).  Each wave takes 64 slots at a time; lane q holds slot q's
+// B-row descriptor and coefficients, broadcast with readlane.  A slot's B row
+// is streamed in chunks of U x 64 entries (coalesced col/val loads); B rows are
+// sorted, so the entries inside the window are a prefix of what is loaded, and
+// the sweep of a B row stops at the first chunk that runs past the window.
+// The first chunk of the next slot is loaded before the current one is
+// accumulated.  A row wider than T sweeps several windows, resuming each B row
+// from its per-slot cursor and skipping B rows with nothing left in the window
+// (cnext), so each B entry is read once per group.  With R > 1 every gathered
+// chunk feeds the windows of all R rows -- neighbouring rows of these matrices
+// reference almost the same rows of B, so the group pays its B bytes once.
+// Finished windows get the D row and the diagonal added in LDS and are written
+// in column order (per-wave ballot compaction, zeros dropped); per-row sums of
+// squares of the product and of the output come out in a fixed order.
 template <typename V, int R, int T, int NT, int U>
-__global__ __launch_bounds__(NT) void k_spgemm_group(
+__global__ __launch_bounds__(NT) void k_spgemm_rows(
     const int32_t *__restrict__ rows, const int32_t *__restrict__ mk,
     const uint32_t *__restrict__ mm, const int32_t *__restrict__ mc, const V *__restrict__ cv,
     const int32_t *__restrict__ mlen, MatView<V> A, MatView<V> B, MatView<V> D, V coef,
@@ -760,7 +610,10 @@ __global__ __launch_bounds__(NT) void k_spgemm_group(
     constexpr int NW = NT / kWave;
     constexpr int REG = T / NW;
     static_assert(T % (NW * kWave) == 0, "tile must split evenly over the waves");
-    __shared__ V acc[R][T];
+    // FP64 accumulators for both value types: LDS atomic add of FP32 is far
+    // slower than of FP64 on this chip, and a product of two FP32 values is
+    // exact in FP64
+    __shared__ double acc[R][T];
     __shared__ int wcnt[NW];
     __shared__ double wsum[2 * R][NW];  // per-wave partial sums of squares, per row
     __shared__ int wrt[R];              // entries written so far, per row
@@ -774,7 +627,7 @@ __global__ __launch_bounds__(NT) void k_spgemm_group(
         hi = max(hi, row_lo[i + r] + row_span[i + r]);
     }
     const int64_t mbeg = A.beg[i];
-    const int ml = mlen[i];
+    const int ml = R == 1 ? A.len[i] : mlen[i];
     const bool multi = hi - lo > T;
     const bool has_d = D.len != nullptr;
 
@@ -786,7 +639,7 @@ __global__ __launch_bounds__(NT) void k_spgemm_group(
         const bool first = (wlo == lo);
         for (int s = threadIdx.x; s < nsl; s += NT)
 #pragma unroll
-            for (int r = 0; r < R; ++r) acc[r][s] = V(0);
+            for (int r = 0; r < R; ++r) acc[r][s] = 0.0;
         __syncthreads();
 
         for (int t0 = wave * kWave; t0 < ml; t0 += NW * kWave) {
@@ -798,14 +651,21 @@ __global__ __launch_bounds__(NT) void k_spgemm_group(
             for (int r = 0; r < R; ++r) a[r] = V(0);
             if (t < ml) {
                 const int64_t pa = mbeg + t;
-                const int k = mk[pa];
-                const uint32_t m = mm[pa];
-                const V *cp = cv + mbeg + mc[pa];
-                int j = 0;
+                int k;
+                if constexpr (R == 1) {  // a single row: its own entries are the slots
+                    k = A.col[pa];
+                    a[0] = coef * A.val[pa];
+                    msk = 1;
+                } else {
+                    k = mk[pa];
+                    const uint32_t m = mm[pa];
+                    const V *cp = cv + mbeg + mc[pa];
+                    int j = 0;
 #pragma unroll
-                for (int r = 0; r < R; ++r)
-                    if ((m >> r) & 1u) a[r] = coef * cp[j++];
-                msk = (int)m;
+                    for (int r = 0; r < R; ++r)
+                        if ((m >> r) & 1u) a[r] = coef * cp[j++];
+                    msk = (int)m;
+                }
                 bb = B.beg[k];
                 bl = B.len[k];
                 if (!first) { cur = cursor[pa]; nc = cnext[pa]; }
@@ -867,7 +727,7 @@ __global__ __launch_bounds__(NT) void k_spgemm_group(
             for (int r = 0; r < R; ++r) {
                 double x = 0.0;
                 for (int s = threadIdx.x; s < nsl; s += NT) {
-                    const double v = as_f64(acc[r][s]);
+                    const double v = acc[r][s];
                     x += v * v;
                 }
                 x = wave_sum(x);
@@ -882,14 +742,15 @@ __global__ __launch_bounds__(NT) void k_spgemm_group(
                 const int64_t db = D.beg[i + r];
                 for (int q = threadIdx.x; q < dl; q += NT) {
                     const int c = D.col[db + q];
-                    if (c >= wlo && c < whi) acc[r][c - wlo] += dcoef * D.val[db + q];
+                    if (c >= wlo && c < whi)
+                        acc[r][c - wlo] += (double)dcoef * (double)D.val[db + q];
                 }
             }
             __syncthreads();
         }
         if (diag != V(0) && threadIdx.x < R) {
             const int r = threadIdx.x, ir = i + r;
-            if (ir >= wlo && ir < whi) acc[r][ir - wlo] += diag;
+            if (ir >= wlo && ir < whi) acc[r][ir - wlo] += (double)diag;
         }
         __syncthreads();
 
@@ -899,7 +760,7 @@ __global__ __launch_bounds__(NT) void k_spgemm_group(
             int cw = 0;
             for (int s0 = rbeg; s0 < rbeg + REG && s0 < nsl; s0 += kWave) {
                 const int s = s0 + lane;
-                const V v = s < nsl ? acc[r][s] : V(0);
+                const V v = s < nsl ? (V)acc[r][s] : V(0);
                 cw += __popcll(__ballot(v != V(0)));
             }
             if (lane == 0) wcnt[wave] = cw;
@@ -913,7 +774,7 @@ __global__ __launch_bounds__(NT) void k_spgemm_group(
             }
             for (int s0 = rbeg; s0 < rbeg + REG && s0 < nsl; s0 += kWave) {
                 const int s = s0 + lane;
-                const V v = s < nsl ? acc[r][s] : V(0);
+                const V v = s < nsl ? (V)acc[r][s] : V(0);
                 const bool nz = v != V(0);
                 const uint64_t m = __ballot(nz);
                 if (nz) {
@@ -1363,10 +1224,11 @@ void launch_bin_rows(const int32_t *span, const int64_t *work, int64_t r0, int64
 }
 
 BinCfg bin_config(int cls, int value_bytes) {
+    (void)value_bytes;  // FP64 accumulators for both value types
     switch (cls) {
         case 1: return {512, 64};
         case 2: return {4096, 256};
-        default: return {value_bytes == 8 ? 8192 : 16384, 512};
+        default: return {8192, 512};
     }
 }
 
@@ -1405,8 +1267,9 @@ template void launch_merge_group<float>(int, const int32_t *, int, MatView<float
 // LDS accumulators of a group kernel: 128 KB for groups of 4 and more (64 KB for
 // pairs), split into `group` windows.
 BinCfg group_config(int group, int value_bytes) {
-    if (group == 2) return {value_bytes == 8 ? 4096 : 8192, 512};
-    return {(value_bytes == 8 ? 16384 : 32768) / group, 1024};
+    (void)value_bytes;  // FP64 accumulators for both value types
+    if (group == 2) return {4096, 512};
+    return {16384 / group, 1024};
 }
 
 template <typename V, int R>
@@ -1417,10 +1280,9 @@ static void group_launch(const int32_t *leads, int ngroups, const int32_t *mk, c
                          int32_t *out_col, V *out_val, int32_t *out_len, int32_t *cursor,
                          int32_t *cnext, double *sq_prod, double *sq_out, int64_t *out_count,
                          hipStream_t s) {
-    constexpr int T = R == 2 ? (sizeof(V) == 8 ? 4096 : 8192)
-                             : (sizeof(V) == 8 ? 16384 : 32768) / R;
+    constexpr int T = R == 2 ? 4096 : 16384 / R;
     constexpr int NT = R == 2 ? 512 : 1024;
-    k_spgemm_group<V, R, T, NT, kGroupUnroll><<<ngroups, NT, 0, s>>>(
+    k_spgemm_rows<V, R, T, NT, kUnroll><<<ngroups, NT, 0, s>>>(
         leads, mk, mm, mc, cv, mlen, A, B, D, (V)coef, (V)dcoef, (V)diag, lo, span, off, base,
         out_col, out_val, out_len, cursor, cnext, sq_prod, sq_out, out_count);
 }
@@ -1469,23 +1331,21 @@ void launch_spgemm(int cls, const int32_t *rows, int nrows, MatView<V> A, MatVie
                    double *sq_out, int64_t *out_count, hipStream_t s) {
     if (nrows <= 0) return;
     const V c = (V)coef, d = (V)diag, dc = (V)dcoef;
+#define SFN_ROW_ARGS                                                                          \
+    rows, nullptr, nullptr, nullptr, nullptr, nullptr, A, B, D, c, dc, d, lo, span, off, base, \
+        out_col, out_val, out_len, cursor, cnext, sq_prod, sq_out, out_count
     switch (cls) {
         case 1:
-            k_spgemm<V, 512, 64><<<nrows, 64, 0, s>>>(rows, A, B, D, c, dc, d, lo, span, off, base,
-                                                      out_col, out_val, out_len, cursor, cnext,
-                                                      sq_prod, sq_out, out_count);
+            k_spgemm_rows<V, 1, 512, 64, kUnroll><<<nrows, 64, 0, s>>>(SFN_ROW_ARGS);
             break;
         case 2:
-            k_spgemm<V, 4096, 256><<<nrows, 256, 0, s>>>(rows, A, B, D, c, dc, d, lo, span, off, base,
-                                                         out_col, out_val, out_len, cursor,
-                                                         cnext, sq_prod, sq_out, out_count);
+            k_spgemm_rows<V, 1, 4096, 256, kUnroll><<<nrows, 256, 0, s>>>(SFN_ROW_ARGS);
             break;
         default:
-            k_spgemm<V, (sizeof(V) == 8 ? 8192 : 16384), 512><<<nrows, 512, 0, s>>>(
-                rows, A, B, D, c, dc, d, lo, span, off, base, out_col, out_val, out_len, cursor,
-                cnext, sq_prod, sq_out, out_count);
+            k_spgemm_rows<V, 1, 8192, 512, kUnroll><<<nrows, 512, 0, s>>>(SFN_ROW_ARGS);
             break;
     }
+#undef SFN_ROW_ARGS
 }
 template void launch_spgemm<double>(int, const int32_t *, int, MatView<double>, MatView<double>,
                                     MatView<double>, double, double, double, const int32_t *,

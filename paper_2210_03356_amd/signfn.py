@@ -108,6 +108,8 @@ def load():
     lib.sign_result_free.restype = None
     lib.sign_last_error.argtypes = []
     lib.sign_last_error.restype = C.c_char_p
+    lib.sign_release_cached.argtypes = []
+    lib.sign_release_cached.restype = C.c_size_t
     lib.sign_server_create.argtypes = [P(sign_server_opts), P(C.c_void_p)]
     lib.sign_server_create.restype = C.c_int
     lib.sign_serve_submit.argtypes = [C.c_void_p, P(sign_csr), P(sign_opts), P(C.c_uint64)]
@@ -282,6 +284,11 @@ def _call(fn, *args) -> Result:
     if out.value is None:
         raise _err(st)
     return Result(out.value, st)
+
+
+def release_cached() -> int:
+    """Returns the library's cached idle device memory to HIP; bytes released."""
+    return int(load().sign_release_cached())
 
 
 def sign_ns(A: DeviceCsr, opts: Optional[sign_opts] = None, stream=None) -> Result:

@@ -82,6 +82,8 @@ def _properties(res, A, rows):
 
 def _trace(res):
     import torch
+    import paper_2210_03356_amd as pkg
+    pkg.release_cached()
     rp, ci, va = res.to_torch()
     n = rp.numel() - 1
     r = torch.repeat_interleave(torch.arange(n, device=rp.device), rp[1:] - rp[:-1])
