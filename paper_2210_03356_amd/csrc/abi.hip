@@ -129,6 +129,7 @@ LoopOut mixed_precision(Workspace &w, const sign_csr *A, double c, const sign_op
     X32.bind(w.al);
     load_scaled<float>(w, A, 1.0 / c, X32);
     LoopParams p32{o.tol, o.c_fixed, o.switch_res, 0, o.max_iter, o.filter_y, 1};
+    p32.sym = w.allow_sym && is_symmetric<float>(w, X32);
     p32.tol = std::max(o.tol, 32.0 * 5.960464477539063e-08 * std::sqrt((double)n));
     const LoopOut l32 = nsf_loop<float>(w, X32, p32, trace);
     convert<float, double>(w, X32, X);
@@ -138,6 +139,7 @@ LoopOut mixed_precision(Workspace &w, const sign_csr *A, double c, const sign_op
     // FP32 phase ends below the switch residual, and the eq. 1.18 budget there
     // (proportional to e^2) would stop filtering altogether
     LoopParams p64{o.tol, o.c_fixed, 0.0, 0, 0, o.filter_y, 0};
+    p64.sym = p32.sym;
     int iters = l32.iters;
     LoopOut lo;
     if (o.polish_steps > 0) {
@@ -169,7 +171,23 @@ LoopOut mixed_precision(Workspace &w, const sign_csr *A, double c, const sign_op
             product<double>(w, X, Cm, &X, -omega, 1.0, 0.0, Xb, nullptr, nullptr);
             filter<double, double>(w, Xb, o.c_fixed * o.tol, Xn, nullptr, nullptr);
             std::swap(X, Xn);
+            p64.sym = 0;  // X - w X [A, X] is not exactly symmetric
         }
+    }
+    if (p32.sym && !p64.sym && !o.filter_y) {
+        // refinement left X slightly unsymmetric; the sign of a symmetric A is
+        // symmetric, so continue from (X + X^T)/2 (never farther from it) and
+        // keep the remaining steps on symmetric products
+        DMat<double> Xt, I, Xs;
+        for (DMat<double> *m : {&Xt, &I, &Xs}) m->bind(w.al);
+        transpose(w, X, Xt);
+        I.ensure_rows(n);
+        I.ensure_entries(n);
+        launch_identity(n, I.begp(), I.lenp(), I.colp(), I.valp(), w.s);
+        I.nnz = n;
+        product<double>(w, I, Xt, &X, 0.5, 0.5, 0.0, Xs, nullptr, nullptr);
+        std::swap(X, Xs);
+        p64.sym = 1;
     }
     p64.max_iter = std::max(1, o.polish_steps - 1);
     const LoopOut l2 = nsf_loop<double>(w, X, p64, trace);
@@ -261,6 +279,7 @@ int sign_ns(const sign_csr *A, const sign_opts *o, void *hip_stream, sign_result
         X.bind(&al);
         if (o->precision == 0) {
             load_scaled<double>(w, A, 1.0 / c, X);
+            p.sym = w.allow_sym && is_symmetric<double>(w, X);
             lo = nsf_loop<double>(w, X, p, trace);
         } else {
             lo = mixed_precision(w, A, c, *o, X, trace, comm_rel);

@@ -15,13 +15,15 @@ constexpr int kMidTile = 4096;
 Workspace::Workspace(Allocator *a, size_t staging_bytes) : al(a), s(a->stream) {
     for (DevBuf *b : {&lo, &span, &cap, &work, &capoff, &workoff, &tmp, &bins, &counts, &cursor,
                       &stage_col, &stage_val, &rs1, &rs2, &rs3, &rs4, &icnt, &hist, &tau,
-                      &bstar, &seg, &red, &flag, &zero_b, &cstat, &mk, &mm, &mc, &cv, &mlen, &cnext})
+                      &bstar, &seg, &red, &flag, &zero_b, &cstat, &mk, &mm, &mc, &cv, &mlen, &cnext, &symcnt, &symoff, &symfill,
+                      &symtcol, &symtval})
         b->bind(a);
     // rows per workgroup for wide rows: 1 (off), 2, 4, 8 or 16
     if (const char *ge = std::getenv("SIGNFN_ROW_GROUP")) {
         const int g = std::atoi(ge);
         if (g == 1 || g == 2 || g == 4 || g == 8 || g == 16) row_group = g;
     }
+    if (const char *se = std::getenv("SIGNFN_SYMMETRIC")) allow_sym = se[0] != '0';
     if (staging_bytes == 0) {
         // a quarter of the memory that is free or idle in the caching pool,
         // capped so that one reservation stays a modest share of HBM
@@ -80,9 +82,11 @@ double Workspace::max_rows(const DevBuf &rows, int64_t n) {
     return read_scalar(red.as<double>(), s);
 }
 
+namespace {
 template <typename V>
-void product(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D, double coef,
-             double dcoef, double diag, DMat<V> &C, DevBuf *sq_prod, DevBuf *sq_out) {
+void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D,
+                  double coef, double dcoef, double diag, DMat<V> &C, DevBuf *sq_prod,
+                  DevBuf *sq_out, int lower) {
     const int64_t n = A.n;
     hipStream_t s = w.s;
     if (B.n != n || (D && D->n != n)) throw Error(SIGN_EINVAL, "product: shape mismatch");
@@ -189,7 +193,7 @@ void product(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D,
                                    w.cnext.as<int32_t>(),
                                    sq_prod ? sq_prod->as<double>() : nullptr,
                                    sq_out ? sq_out->as<double>() : nullptr,
-                                   w.cstat.as<int64_t>() + 4 * 8 + 4, s);
+                                   w.cstat.as<int64_t>() + 4 * 8 + 4, lower, s);
         } else {
             SFN_HIP(hipEventRecord(w.ev[1], s));
         }
@@ -202,7 +206,7 @@ void product(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D,
                              w.cursor.as<int32_t>(), w.cnext.as<int32_t>(),
                              sq_prod ? sq_prod->as<double>() : nullptr,
                              sq_out ? sq_out->as<double>() : nullptr,
-                             w.cstat.as<int64_t>() + cls * 8 + 4, s);
+                             w.cstat.as<int64_t>() + cls * 8 + 4, lower, s);
             SFN_HIP(hipEventRecord(w.ev[6 - cls], s));
         }
         // compact row starts of this batch, continuing from the previous batches
@@ -253,6 +257,65 @@ void product(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D,
     }
     C.nnz = running;
 }
+
+
+// C (full) from the lower triangle L of a symmetric matrix: rows of L first,
+// then each row's mirror list (the strictly-lower entries of its column),
+// ordered by column.
+template <typename V>
+void symmetrize(Workspace &w, const DMat<V> &L, DMat<V> &C) {
+    const int64_t n = L.n;
+    hipStream_t s = w.s;
+    C.ensure_rows(n);
+    w.symcnt.ensure(sizeof(int32_t) * std::max<int64_t>(n, 1));
+    w.symfill.ensure(sizeof(int32_t) * std::max<int64_t>(n, 1));
+    w.symoff.ensure(sizeof(int64_t) * (n + 1));
+    w.tmp.ensure(sizeof(int64_t) * scan_tmp_elems(n));
+    SFN_HIP(hipMemsetAsync(w.symcnt.get(), 0, sizeof(int32_t) * n, s));
+    SFN_HIP(hipMemsetAsync(w.symfill.get(), 0, sizeof(int32_t) * n, s));
+    launch_sym_count<V>(L.view(), w.symcnt.as<int32_t>(), s);
+    launch_exclusive_scan_i32(w.symcnt.as<int32_t>(), n, w.symoff.as<int64_t>(),
+                              w.tmp.as<int64_t>(), 0, s);
+    launch_add_len(L.lenp(), w.symcnt.as<int32_t>(), n, C.lenp(), s);
+    launch_exclusive_scan_i32(C.lenp(), n, C.begp(), w.tmp.as<int64_t>(), 0, s);
+    int64_t tot[2];
+    SFN_HIP(hipMemcpyAsync(&tot[0], C.begp() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SFN_HIP(hipMemcpyAsync(&tot[1], w.symoff.as<int64_t>() + n, sizeof(int64_t),
+                           hipMemcpyDeviceToHost, s));
+    SFN_HIP(hipStreamSynchronize(s));
+    C.ensure_entries(tot[0]);
+    w.symtcol.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(tot[1], 1));
+    w.symtval.ensure(sizeof(V) * (size_t)std::max<int64_t>(tot[1], 1));
+    launch_sym_place<V>(L.view(), C.begp(), C.colp(), C.valp(), w.symoff.as<int64_t>(),
+                        w.symfill.as<int32_t>(), w.symtcol.as<int32_t>(), w.symtval.as<V>(), s);
+    launch_sym_rank<V>(n, C.begp(), L.lenp(), w.symoff.as<int64_t>(), w.symcnt.as<int32_t>(),
+                       w.symtcol.as<int32_t>(), w.symtval.as<V>(), C.colp(), C.valp(), s);
+    C.nnz = tot[0];
+}
+}  // namespace
+
+template <typename V>
+void product(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D, double coef,
+             double dcoef, double diag, DMat<V> &C, DevBuf *sq_prod, DevBuf *sq_out, bool sym) {
+    if (!sym) {
+        product_rows<V>(w, A, B, D, coef, dcoef, diag, C, sq_prod, sq_out, 0);
+        return;
+    }
+    DMat<V> L;
+    L.bind(w.al);
+    product_rows<V>(w, A, B, D, coef, dcoef, diag, L, sq_prod, sq_out, 1);
+    symmetrize<V>(w, L, C);
+}
+
+template <typename V>
+bool is_symmetric(Workspace &w, const DMat<V> &X) {
+    w.flag.ensure(sizeof(int));
+    SFN_HIP(hipMemsetAsync(w.flag.get(), 0, sizeof(int), w.s));
+    launch_sym_check<V>(X.view(), w.flag.as<int>(), w.s);
+    return read_scalar(w.flag.as<int>(), w.s) == 0;
+}
+template bool is_symmetric<double>(Workspace &, const DMat<double> &);
+template bool is_symmetric<float>(Workspace &, const DMat<float> &);
 
 template <typename V, typename Vo>
 int filter(Workspace &w, const DMat<V> &In, double tau, DMat<Vo> &Out, DevBuf *sq_keep,
@@ -375,7 +438,10 @@ LoopOut nsf_loop(Workspace &w, DMat<V> &X, const LoopParams &p,
     for (int k = 1;; ++k) {
         const double t0 = now_s();
         // residual of the current iterate: R^_k = I - X^_k^2
-        product<V>(w, X, X, nullptr, -1.0, 0.0, 1.0, R, nullptr, &w.rs1);
+        // symmetric products keep X^ exactly symmetric only when R^ stays the
+        // exact polynomial I - X^2 (R^ not filtered): then X^R^ is symmetric too
+        const bool sym = p.sym && !p.filter_y;
+        product<V>(w, X, X, nullptr, -1.0, 0.0, 1.0, R, nullptr, &w.rs1, sym);
         const double e = std::sqrt(w.sum_rows(w.rs1, n));
         es.push_back(e);
         sign_iter_stats it{};
@@ -406,7 +472,7 @@ LoopOut nsf_loop(Workspace &w, DMat<V> &X, const LoopParams &p,
             std::swap(R, Xn);
         }
         // Xbar_{k+1} = X^_k + 1/2 X^_k R^_k  (= 1/2 X^_k (3I - X^_k^2))
-        product<V>(w, X, R, &X, 0.5, 1.0, 0.0, Xb, &w.rs2, nullptr);
+        product<V>(w, X, R, &X, 0.5, 1.0, 0.0, Xb, &w.rs2, nullptr, sym);
         const double d = std::sqrt(w.sum_rows(w.rs2, n));
         // X^_{k+1} = Xbar_{k+1} - F_{k+1}
         const int bstar = filter<V, V>(w, Xb, tau, Xn, &w.rs3, &w.rs4);
@@ -556,10 +622,10 @@ LoopOut nmf_loop(Workspace &w, DMat<double> &X, const LoopParams &p,
 
 template void product<double>(Workspace &, const DMat<double> &, const DMat<double> &,
                               const DMat<double> *, double, double, double, DMat<double> &,
-                              DevBuf *, DevBuf *);
+                              DevBuf *, DevBuf *, bool);
 template void product<float>(Workspace &, const DMat<float> &, const DMat<float> &,
                              const DMat<float> *, double, double, double, DMat<float> &, DevBuf *,
-                             DevBuf *);
+                             DevBuf *, bool);
 template int filter<double, double>(Workspace &, const DMat<double> &, double, DMat<double> &,
                                     DevBuf *, DevBuf *);
 template int filter<float, float>(Workspace &, const DMat<float> &, double, DMat<float> &,

@@ -17,8 +17,10 @@ struct Workspace {
     DevBuf lo, span, cap, work, capoff, workoff, tmp, bins, counts, cursor, stage_col, stage_val;
     DevBuf rs1, rs2, rs3, rs4, icnt, hist, tau, bstar, seg, red, flag, zero_b;
     DevBuf cstat, mk, mm, mc, cv, mlen, cnext;
+    DevBuf symcnt, symoff, symfill, symtcol, symtval;  // mirroring of symmetric products
     const uint8_t *row_skip = nullptr;  // optional row mask for products (serving)
     int row_group = 8;                  // wide rows computed in groups of 1, 2, 4, 8 or 16
+    bool allow_sym = true;              // symmetric products from their lower triangle
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     // accumulated product statistics, in total and per row class (kernel tile)
     struct ClassStat {
@@ -42,10 +44,18 @@ struct Workspace {
 
 // C = diag*I + coef*A*B + dcoef*D (D may be null); C becomes compact CSR.
 // sq_prod[i] receives the sum of squares of row i of coef*A*B and sq_out[i]
-// that of the stored row of C (either may be null).
+// that of the stored row of C (either may be null); only their totals are
+// meaningful when sym is set.  sym: the caller knows C is symmetric (A, B, D
+// symmetric and AB = BA); only the lower triangle is computed and the upper
+// one is its mirror.
 template <typename V>
 void product(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D, double coef,
-             double dcoef, double diag, DMat<V> &C, DevBuf *sq_prod, DevBuf *sq_out);
+             double dcoef, double diag, DMat<V> &C, DevBuf *sq_prod, DevBuf *sq_out,
+             bool sym = false);
+
+// true if X equals its transpose exactly (pattern and values)
+template <typename V>
+bool is_symmetric(Workspace &w, const DMat<V> &X);
 
 // Out = In without its largest low-magnitude part of Frobenius norm <= tau.
 // Returns the cut bucket; sq_keep/sq_drop (optional) receive per-row sums of
@@ -76,7 +86,8 @@ double nmf_budget(double e, double xfro, double zfro, double tol, double c_fixed
 struct LoopParams {
     double tol, c_fixed, switch_res;
     int stop_rule, max_iter, filter_y;
-    int fp32;  // recorded in the trace
+    int fp32;     // recorded in the trace
+    int sym = 0;  // the iterate is symmetric: symmetric products from their lower triangle
 };
 
 struct LoopOut {

@@ -576,6 +576,15 @@ __device__ __forceinline__ int group_accumulate(double (*acc)[T], const int (&c)
     return got;
 }
 
+// Weight of an entry (row, col) in a Frobenius norm taken over the stored part
+// of a matrix: 1 when the whole matrix is stored; for a symmetric matrix held
+// by its lower triangle, 2 below the diagonal (the entry stands for itself and
+// its mirror), 1 on it, 0 above (not stored).
+__device__ __forceinline__ double sym_weight(int lower, int col, int row) {
+    if (!lower) return 1.0;
+    return col < row ? 2.0 : (col == row ? 1.0 : 0.0);
+}
+
 // ---------------------------------------------------------------------------
 // numeric product: C = diag*I + coef*A*B + dcoef*D, row-wise (Gustavson)
 // ---------------------------------------------------------------------------
@@ -606,7 +615,7 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
     const int64_t *__restrict__ off, int64_t base, int32_t *__restrict__ out_col,
     V *__restrict__ out_val, int32_t *__restrict__ out_len, int32_t *__restrict__ cursor,
     int32_t *__restrict__ cnext, double *__restrict__ sq_prod, double *__restrict__ sq_out,
-    int64_t *__restrict__ out_count) {
+    int64_t *__restrict__ out_count, int lower) {
     constexpr int NW = NT / kWave;
     constexpr int REG = T / NW;
     static_assert(T % (NW * kWave) == 0, "tile must split evenly over the waves");
@@ -626,6 +635,10 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
         lo = min(lo, row_lo[i + r]);
         hi = max(hi, row_lo[i + r] + row_span[i + r]);
     }
+    // lower: only columns <= the row itself (the product is symmetric and its
+    // upper triangle is mirrored afterwards); B rows are then read only up to
+    // the diagonal, as the sweep stops at the last window
+    if (lower) hi = min(hi, i + R);
     const int64_t mbeg = A.beg[i];
     const int ml = R == 1 ? A.len[i] : mlen[i];
     const bool multi = hi - lo > T;
@@ -728,7 +741,7 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
                 double x = 0.0;
                 for (int s = threadIdx.x; s < nsl; s += NT) {
                     const double v = acc[r][s];
-                    x += v * v;
+                    x += sym_weight(lower, wlo + s, i + r) * v * v;
                 }
                 x = wave_sum(x);
                 if (lane == 0) wsum[2 * r][wave] += x;
@@ -757,10 +770,12 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
         for (int r = 0; r < R; ++r) {
             const int64_t obase = off[i + r] - base;
             const int rbeg = wave * REG;
+            // columns written for this row: all, or up to the diagonal
+            const int lim = lower ? min(nsl, i + r + 1 - wlo) : nsl;
             int cw = 0;
             for (int s0 = rbeg; s0 < rbeg + REG && s0 < nsl; s0 += kWave) {
                 const int s = s0 + lane;
-                const V v = s < nsl ? (V)acc[r][s] : V(0);
+                const V v = s < lim ? (V)acc[r][s] : V(0);
                 cw += __popcll(__ballot(v != V(0)));
             }
             if (lane == 0) wcnt[wave] = cw;
@@ -774,14 +789,14 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
             }
             for (int s0 = rbeg; s0 < rbeg + REG && s0 < nsl; s0 += kWave) {
                 const int s = s0 + lane;
-                const V v = s < nsl ? (V)acc[r][s] : V(0);
+                const V v = s < lim ? (V)acc[r][s] : V(0);
                 const bool nz = v != V(0);
                 const uint64_t m = __ballot(nz);
                 if (nz) {
                     const int64_t pos = obase + o + lanes_below(m);
                     out_col[pos] = wlo + s;
                     out_val[pos] = v;
-                    y += as_f64(v) * as_f64(v);
+                    y += sym_weight(lower, wlo + s, i + r) * as_f64(v) * as_f64(v);
                 }
                 o += __popcll(m);
             }
@@ -1043,6 +1058,141 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_rows(const int64_t *rp, i
     }
 }
 
+// ---------------------------------------------------------------------------
+// symmetric products: the full matrix from its lower triangle L
+// ---------------------------------------------------------------------------
+// cnt[c] += number of entries L(j, c) with j > c (wave per row j)
+template <typename V>
+__global__ void k_sym_count(MatView<V> L, int32_t *cnt) {
+    const int64_t j = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
+    if (j >= L.n) return;
+    const int64_t b = L.beg[j];
+    for (int p = lane_id(); p < L.len[j]; p += kWave) {
+        const int c = L.col[b + p];
+        if (c < j) atomicAdd(&cnt[c], 1);
+    }
+}
+
+// out[i] = a[i] + b[i]
+__global__ void k_add_len(const int32_t *a, const int32_t *b, int64_t n, int32_t *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = a[i] + b[i];
+}
+
+// Row j of L goes to the front of row j of C; every strictly-lower entry
+// L(j, c) is also appended, unordered, to row c's mirror list in (tcol, tval)
+// at toff[c] + (arrival order).  Wave per row j.
+template <typename V>
+__global__ void k_sym_place(MatView<V> L, const int64_t *cbeg, int32_t *ccol, V *cval,
+                            const int64_t *toff, int32_t *fill, int32_t *tcol, V *tval) {
+    const int64_t j = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
+    if (j >= L.n) return;
+    const int64_t b = L.beg[j], o = cbeg[j];
+    for (int p = lane_id(); p < L.len[j]; p += kWave) {
+        const int c = L.col[b + p];
+        const V v = L.val[b + p];
+        ccol[o + p] = c;
+        cval[o + p] = v;
+        if (c < j) {
+            const int64_t w = toff[c] + atomicAdd(&fill[c], 1);
+            tcol[w] = (int32_t)j;
+            tval[w] = v;
+        }
+    }
+}
+
+// Row c of C gets its mirror list, ordered by column, after its lower part:
+// the keys j > c are ranked with an LDS bitmap over chunks of kRankChunk
+// consecutive keys (rank = set bits below the key), so no comparison sort is
+// needed and any list length is handled.  One workgroup per row.
+constexpr int kRankChunk = 65536;
+constexpr int kRankThreads = 256;
+
+template <typename V>
+__global__ __launch_bounds__(kRankThreads) void k_sym_rank(
+    const int64_t *cbeg, const int32_t *llen, const int64_t *toff, const int32_t *tcnt,
+    const int32_t *tcol, const V *tval, int32_t *ccol, V *cval) {
+    constexpr int NWORD = kRankChunk / 32;
+    constexpr int PER = NWORD / kRankThreads;
+    __shared__ uint32_t bits[NWORD];
+    __shared__ int32_t wpre[NWORD];
+    __shared__ int red[kRankThreads / kWave];
+    __shared__ int wtot[kRankThreads / kWave];
+    const int c = blockIdx.x;
+    const int m = tcnt[c];
+    if (m == 0) return;
+    const int64_t tb = toff[c];
+    const int64_t ob = cbeg[c] + llen[c];
+    const int lane = lane_id(), wave = wave_id();
+    // largest key, to bound the chunks
+    int kmax = c;
+    for (int q = threadIdx.x; q < m; q += kRankThreads) kmax = max(kmax, tcol[tb + q]);
+    kmax = wave_max(kmax);
+    if (lane == 0) red[wave] = kmax;
+    __syncthreads();
+    for (int w = 0; w < kRankThreads / kWave; ++w) kmax = max(kmax, red[w]);
+    int done = 0;  // keys ranked in earlier chunks
+    for (int64_t k0 = (int64_t)c + 1; k0 <= kmax; k0 += kRankChunk) {
+        for (int q = threadIdx.x; q < NWORD; q += kRankThreads) bits[q] = 0u;
+        __syncthreads();
+        for (int q = threadIdx.x; q < m; q += kRankThreads) {
+            const int64_t d = (int64_t)tcol[tb + q] - k0;
+            if (d >= 0 && d < kRankChunk) atomicOr(&bits[d >> 5], 1u << (d & 31));
+        }
+        __syncthreads();
+        // exclusive prefix of popcounts over the words (PER consecutive words per thread)
+        int loc = 0;
+        for (int u = 0; u < PER; ++u) loc += __popc(bits[threadIdx.x * PER + u]);
+        const int inc = (int)wave_incl_scan((int64_t)loc);
+        if (lane == kWave - 1) wtot[wave] = inc;
+        __syncthreads();
+        int before = inc - loc, total = 0;
+        for (int w = 0; w < kRankThreads / kWave; ++w) {
+            if (w < wave) before += wtot[w];
+            total += wtot[w];
+        }
+        for (int u = 0; u < PER; ++u) {
+            wpre[threadIdx.x * PER + u] = before;
+            before += __popc(bits[threadIdx.x * PER + u]);
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < m; q += kRankThreads) {
+            const int key = tcol[tb + q];
+            const int64_t d = (int64_t)key - k0;
+            if (d >= 0 && d < kRankChunk) {
+                const int wd = (int)(d >> 5);
+                const int r = done + wpre[wd] + __popc(bits[wd] & ((1u << (d & 31)) - 1u));
+                ccol[ob + r] = key;
+                cval[ob + r] = tval[tb + q];
+            }
+        }
+        done += total;
+        __syncthreads();
+    }
+}
+
+// flag |= 1 if some entry (i, j, v) has no entry (j, i) of the same value
+// (wave per row, binary search in the sorted row j)
+template <typename V>
+__global__ void k_sym_check(MatView<V> X, int *flag) {
+    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
+    if (i >= X.n) return;
+    const int64_t b = X.beg[i];
+    int bad = 0;
+    for (int p = lane_id(); p < X.len[i]; p += kWave) {
+        const int j = X.col[b + p];
+        const int64_t bj = X.beg[j];
+        int lo = 0, hi = X.len[j];
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (X.col[bj + mid] < i) lo = mid + 1;
+            else hi = mid;
+        }
+        if (!(lo < X.len[j] && X.col[bj + lo] == i && X.val[bj + lo] == X.val[b + p])) bad = 1;
+    }
+    if (__ballot(bad) && lane_id() == 0) atomicOr(flag, 1);
+}
+
 // diag[i] = X_ii (0 if absent), wave per row, binary search in the sorted row
 template <typename V>
 __global__ void k_diag(MatView<V> X, double *diag) {
@@ -1099,6 +1249,44 @@ template void launch_transpose_fill<double>(MatView<double>, const int64_t *, in
                                             double *, hipStream_t);
 template void launch_sort_rows<double>(const int64_t *, int32_t *, double *, int64_t, int *,
                                        hipStream_t);
+template <typename V>
+void launch_sym_count(MatView<V> L, int32_t *cnt, hipStream_t s) {
+    if (L.n > 0) k_sym_count<V><<<blocks_for(L.n, 4), 256, 0, s>>>(L, cnt);
+}
+void launch_add_len(const int32_t *a, const int32_t *b, int64_t n, int32_t *out, hipStream_t s) {
+    if (n > 0) k_add_len<<<blocks_for(n, 256), 256, 0, s>>>(a, b, n, out);
+}
+template <typename V>
+void launch_sym_place(MatView<V> L, const int64_t *cbeg, int32_t *ccol, V *cval,
+                      const int64_t *toff, int32_t *fill, int32_t *tcol, V *tval, hipStream_t s) {
+    if (L.n > 0)
+        k_sym_place<V><<<blocks_for(L.n, 4), 256, 0, s>>>(L, cbeg, ccol, cval, toff, fill, tcol,
+                                                          tval);
+}
+template <typename V>
+void launch_sym_rank(int64_t n, const int64_t *cbeg, const int32_t *llen, const int64_t *toff,
+                     const int32_t *tcnt, const int32_t *tcol, const V *tval, int32_t *ccol,
+                     V *cval, hipStream_t s) {
+    if (n > 0)
+        k_sym_rank<V><<<(unsigned)n, kRankThreads, 0, s>>>(cbeg, llen, toff, tcnt, tcol, tval,
+                                                           ccol, cval);
+}
+template <typename V>
+void launch_sym_check(MatView<V> X, int *flag, hipStream_t s) {
+    if (X.n > 0) k_sym_check<V><<<blocks_for(X.n, 4), 256, 0, s>>>(X, flag);
+}
+#define SFN_SYM_INST(V)                                                                        \
+    template void launch_sym_count<V>(MatView<V>, int32_t *, hipStream_t);                     \
+    template void launch_sym_place<V>(MatView<V>, const int64_t *, int32_t *, V *,             \
+                                      const int64_t *, int32_t *, int32_t *, V *, hipStream_t); \
+    template void launch_sym_rank<V>(int64_t, const int64_t *, const int32_t *,                \
+                                     const int64_t *, const int32_t *, const int32_t *,        \
+                                     const V *, int32_t *, V *, hipStream_t);                  \
+    template void launch_sym_check<V>(MatView<V>, int *, hipStream_t);
+SFN_SYM_INST(double)
+SFN_SYM_INST(float)
+#undef SFN_SYM_INST
+
 int sort_rows_max() { return kSortMax; }
 
 // ===========================================================================
@@ -1279,12 +1467,12 @@ static void group_launch(const int32_t *leads, int ngroups, const int32_t *mk, c
                          const int32_t *lo, const int32_t *span, int64_t base, const int64_t *off,
                          int32_t *out_col, V *out_val, int32_t *out_len, int32_t *cursor,
                          int32_t *cnext, double *sq_prod, double *sq_out, int64_t *out_count,
-                         hipStream_t s) {
+                         int lower, hipStream_t s) {
     constexpr int T = R == 2 ? 4096 : 16384 / R;
     constexpr int NT = R == 2 ? 512 : 1024;
     k_spgemm_rows<V, R, T, NT, kUnroll><<<ngroups, NT, 0, s>>>(
         leads, mk, mm, mc, cv, mlen, A, B, D, (V)coef, (V)dcoef, (V)diag, lo, span, off, base,
-        out_col, out_val, out_len, cursor, cnext, sq_prod, sq_out, out_count);
+        out_col, out_val, out_len, cursor, cnext, sq_prod, sq_out, out_count, lower);
 }
 
 template <typename V>
@@ -1294,11 +1482,11 @@ void launch_spgemm_group(int group, const int32_t *leads, int ngroups, const int
                          double diag, const int32_t *lo, const int32_t *span, int64_t base,
                          const int64_t *off, int32_t *out_col, V *out_val, int32_t *out_len,
                          int32_t *cursor, int32_t *cnext, double *sq_prod, double *sq_out,
-                         int64_t *out_count, hipStream_t s) {
+                         int64_t *out_count, int lower, hipStream_t s) {
     if (ngroups <= 0) return;
 #define SFN_GROUP_ARGS                                                                        \
     leads, ngroups, mk, mm, mc, cv, mlen, A, B, D, coef, dcoef, diag, lo, span, base, off,    \
-        out_col, out_val, out_len, cursor, cnext, sq_prod, sq_out, out_count, s
+        out_col, out_val, out_len, cursor, cnext, sq_prod, sq_out, out_count, lower, s
     switch (group) {
         case 2: group_launch<V, 2>(SFN_GROUP_ARGS); break;
         case 4: group_launch<V, 4>(SFN_GROUP_ARGS); break;
@@ -1314,26 +1502,26 @@ template void launch_spgemm_group<double>(int, const int32_t *, int, const int32
                                           const int32_t *, const int32_t *, int64_t,
                                           const int64_t *, int32_t *, double *, int32_t *,
                                           int32_t *, int32_t *, double *, double *, int64_t *,
-                                          hipStream_t);
+                                          int, hipStream_t);
 template void launch_spgemm_group<float>(int, const int32_t *, int, const int32_t *,
                                          const uint32_t *, const int32_t *, const float *,
                                          const int32_t *, MatView<float>, MatView<float>,
                                          MatView<float>, double, double, double, const int32_t *,
                                          const int32_t *, int64_t, const int64_t *, int32_t *,
                                          float *, int32_t *, int32_t *, int32_t *, double *,
-                                         double *, int64_t *, hipStream_t);
+                                         double *, int64_t *, int, hipStream_t);
 
 template <typename V>
 void launch_spgemm(int cls, const int32_t *rows, int nrows, MatView<V> A, MatView<V> B,
                    MatView<V> D, double coef, double dcoef, double diag, const int32_t *lo,
                    const int32_t *span, int64_t base, const int64_t *off, int32_t *out_col,
                    V *out_val, int32_t *out_len, int32_t *cursor, int32_t *cnext, double *sq_prod,
-                   double *sq_out, int64_t *out_count, hipStream_t s) {
+                   double *sq_out, int64_t *out_count, int lower, hipStream_t s) {
     if (nrows <= 0) return;
     const V c = (V)coef, d = (V)diag, dc = (V)dcoef;
 #define SFN_ROW_ARGS                                                                          \
     rows, nullptr, nullptr, nullptr, nullptr, nullptr, A, B, D, c, dc, d, lo, span, off, base, \
-        out_col, out_val, out_len, cursor, cnext, sq_prod, sq_out, out_count
+        out_col, out_val, out_len, cursor, cnext, sq_prod, sq_out, out_count, lower
     switch (cls) {
         case 1:
             k_spgemm_rows<V, 1, 512, 64, kUnroll><<<nrows, 64, 0, s>>>(SFN_ROW_ARGS);
@@ -1351,12 +1539,12 @@ template void launch_spgemm<double>(int, const int32_t *, int, MatView<double>, 
                                     MatView<double>, double, double, double, const int32_t *,
                                     const int32_t *, int64_t, const int64_t *, int32_t *, double *,
                                     int32_t *, int32_t *, int32_t *, double *, double *, int64_t *,
-                                    hipStream_t);
+                                    int, hipStream_t);
 template void launch_spgemm<float>(int, const int32_t *, int, MatView<float>, MatView<float>,
                                    MatView<float>, double, double, double, const int32_t *,
                                    const int32_t *, int64_t, const int64_t *, int32_t *, float *,
                                    int32_t *, int32_t *, int32_t *, double *, double *, int64_t *,
-                                   hipStream_t);
+                                   int, hipStream_t);
 
 template <typename V>
 void launch_copy_rows(const int64_t *src_off, int64_t src_base, const int32_t *len,

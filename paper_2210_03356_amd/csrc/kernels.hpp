@@ -94,9 +94,28 @@ void launch_spgemm_group(int group, const int32_t *leads, int ngroups, const int
                          double diag, const int32_t *lo, const int32_t *span, int64_t base,
                          const int64_t *off, int32_t *out_col, V *out_val, int32_t *out_len,
                          int32_t *cursor, int32_t *cnext, double *sq_prod, double *sq_out,
-                         int64_t *out_count, hipStream_t s);
+                         int64_t *out_count, int lower, hipStream_t s);
 // tile = LDS accumulator columns per row of the group
 BinCfg group_config(int group, int value_bytes);
+
+// Symmetric products (the full matrix C from its lower triangle L, both compact):
+// cnt[c] += #{j > c : L(j, c) != 0}; out = a + b (row lengths);
+// place: L rows to the front of C rows, strictly-lower entries appended to
+// their column's mirror list (tcol/tval at toff[c] + arrival order; fill
+// zeroed); rank: each mirror list written ordered after the row's lower part.
+template <typename V>
+void launch_sym_count(MatView<V> L, int32_t *cnt, hipStream_t s);
+void launch_add_len(const int32_t *a, const int32_t *b, int64_t n, int32_t *out, hipStream_t s);
+template <typename V>
+void launch_sym_place(MatView<V> L, const int64_t *cbeg, int32_t *ccol, V *cval,
+                      const int64_t *toff, int32_t *fill, int32_t *tcol, V *tval, hipStream_t s);
+template <typename V>
+void launch_sym_rank(int64_t n, const int64_t *cbeg, const int32_t *llen, const int64_t *toff,
+                     const int32_t *tcnt, const int32_t *tcol, const V *tval, int32_t *ccol,
+                     V *cval, hipStream_t s);
+// *flag |= 1 unless X equals its transpose exactly (pattern and values)
+template <typename V>
+void launch_sym_check(MatView<V> X, int *flag, hipStream_t s);
 
 // Numeric product for the rows listed in `rows` (class cfg).  Row i writes
 // at out_col/out_val[off[i] - base .. ), out_len[i], sq_prod[i] (sum of squares
@@ -109,7 +128,7 @@ void launch_spgemm(int cls, const int32_t *rows, int nrows, MatView<V> A, MatVie
                    MatView<V> D, double coef, double dcoef, double diag, const int32_t *lo,
                    const int32_t *span, int64_t base, const int64_t *off, int32_t *out_col,
                    V *out_val, int32_t *out_len, int32_t *cursor, int32_t *cnext, double *sq_prod,
-                   double *sq_out, int64_t *out_count, hipStream_t s);
+                   double *sq_out, int64_t *out_count, int lower, hipStream_t s);
 BinCfg bin_config(int cls, int value_bytes);
 
 // Copy rows [r0, r1) from a gapped layout (row i at src_off[i] - src_base)

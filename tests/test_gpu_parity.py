@@ -369,3 +369,24 @@ def test_row_groups_nsf(sf, monkeypatch, lap96_oracle, group):
     assert st["hot_group"] in (1, group)
     S = X.to_scipy()
     assert sp.linalg.norm(r.to_scipy() - S) / sp.linalg.norm(S) <= 1e-10
+
+
+@pytest.mark.parametrize("name", ["c1_1024", "lap2d_48", "lap3d_9"])
+def test_symmetric_products_match_general(sf, monkeypatch, name):
+    """For a symmetric input the products are formed from their lower triangle
+    and mirrored: the result is exactly symmetric and agrees with the general
+    path and the oracle."""
+    make, kw = CASES[name]
+    A = make()
+    monkeypatch.setenv("SIGNFN_SYMMETRIC", "1")
+    Xs = sf.sign_ns(_dev(sf, A), sf.default_opts(**kw)).to_scipy()
+    assert (Xs - Xs.T).nnz == 0                      # exactly symmetric
+    monkeypatch.setenv("SIGNFN_SYMMETRIC", "0")
+    Xg = sf.sign_ns(_dev(sf, A), sf.default_opts(**kw)).to_scipy()
+    S = oracle.nsf(A, **kw).to_scipy()
+    assert sp.linalg.norm(Xs - Xg) <= 1e-10 * sp.linalg.norm(S)
+    assert sp.linalg.norm(Xs - S) <= 1e-10 * sp.linalg.norm(S)
+    # mixed precision takes the same route in its FP32 phase
+    monkeypatch.setenv("SIGNFN_SYMMETRIC", "1")
+    Xm = sf.sign_ns(_dev(sf, A), sf.default_opts(precision=1, **kw)).to_scipy()
+    assert sp.linalg.norm(Xm - S) <= 1e-8 * sp.linalg.norm(S)
