@@ -259,6 +259,8 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
 }
 
 
+}  // namespace
+
 // C (full) from the lower triangle L of a symmetric matrix: rows of L first,
 // then each row's mirror list (the strictly-lower entries of its column),
 // ordered by column.
@@ -292,13 +294,15 @@ void symmetrize(Workspace &w, const DMat<V> &L, DMat<V> &C) {
                        w.symtcol.as<int32_t>(), w.symtval.as<V>(), C.colp(), C.valp(), s);
     C.nnz = tot[0];
 }
-}  // namespace
+template void symmetrize<double>(Workspace &, const DMat<double> &, DMat<double> &);
+template void symmetrize<float>(Workspace &, const DMat<float> &, DMat<float> &);
 
 template <typename V>
 void product(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D, double coef,
-             double dcoef, double diag, DMat<V> &C, DevBuf *sq_prod, DevBuf *sq_out, bool sym) {
-    if (!sym) {
-        product_rows<V>(w, A, B, D, coef, dcoef, diag, C, sq_prod, sq_out, 0);
+             double dcoef, double diag, DMat<V> &C, DevBuf *sq_prod, DevBuf *sq_out, bool sym,
+             bool keep_lower) {
+    if (!sym || keep_lower) {
+        product_rows<V>(w, A, B, D, coef, dcoef, diag, C, sq_prod, sq_out, sym ? 1 : 0);
         return;
     }
     DMat<V> L;
@@ -319,7 +323,7 @@ template bool is_symmetric<float>(Workspace &, const DMat<float> &);
 
 template <typename V, typename Vo>
 int filter(Workspace &w, const DMat<V> &In, double tau, DMat<Vo> &Out, DevBuf *sq_keep,
-           DevBuf *sq_drop) {
+           DevBuf *sq_drop, int lower) {
     const int64_t n = In.n;
     hipStream_t s = w.s;
     Out.ensure_rows(n);
@@ -334,11 +338,11 @@ int filter(Workspace &w, const DMat<V> &In, double tau, DMat<Vo> &Out, DevBuf *s
     SFN_HIP(hipMemcpyAsync(w.seg.get(), h, sizeof(h), hipMemcpyHostToDevice, s));
     SFN_HIP(hipMemcpyAsync(w.tau.get(), &tau, sizeof(double), hipMemcpyHostToDevice, s));
     SFN_HIP(hipMemsetAsync(w.hist.get(), 0, sizeof(uint64_t) * kBuckets, s));
-    launch_histogram<V>(In.view(), w.seg.as<int64_t>(), 1, n, w.hist.as<uint64_t>(), s);
+    launch_histogram<V>(In.view(), w.seg.as<int64_t>(), 1, n, w.hist.as<uint64_t>(), lower, s);
     launch_select(w.hist.as<uint64_t>(), w.tau.as<double>(), 1, w.bstar.as<int>(), s);
     launch_count_keep<V>(In.view(), nullptr, w.bstar.as<int>(), Out.lenp(),
                          sq_keep ? sq_keep->as<double>() : nullptr,
-                         sq_drop ? sq_drop->as<double>() : nullptr, s);
+                         sq_drop ? sq_drop->as<double>() : nullptr, lower, s);
     launch_exclusive_scan_i32(Out.lenp(), n, Out.begp(),
                               w.tmp.as<int64_t>(), 0, s);
     int64_t total;
@@ -372,11 +376,11 @@ void filter_seg(Workspace &w, const DMat<double> &In, const std::vector<int64_t>
     SFN_HIP(hipMemcpyAsync(w.tau.get(), tau_h.data(), sizeof(double) * nseg,
                            hipMemcpyHostToDevice, s));
     SFN_HIP(hipMemsetAsync(w.hist.get(), 0, sizeof(uint64_t) * kBuckets * nseg, s));
-    launch_histogram<double>(In.view(), seg_d, nseg, maxrows, w.hist.as<uint64_t>(), s);
+    launch_histogram<double>(In.view(), seg_d, nseg, maxrows, w.hist.as<uint64_t>(), 0, s);
     launch_select(w.hist.as<uint64_t>(), w.tau.as<double>(), nseg, w.bstar.as<int>(), s);
     launch_count_keep<double>(In.view(), row_seg, w.bstar.as<int>(), Out.lenp(),
                               sq_keep ? sq_keep->as<double>() : nullptr,
-                              sq_drop ? sq_drop->as<double>() : nullptr, s);
+                              sq_drop ? sq_drop->as<double>() : nullptr, 0, s);
     launch_exclusive_scan_i32(Out.lenp(), n, Out.begp(), w.tmp.as<int64_t>(), 0, s);
     int64_t total;
     bstar_h.resize(nseg);
@@ -409,7 +413,7 @@ void row_sumsq(Workspace &w, const DMat<V> &X, DevBuf &rows) {
     w.zero_b.ensure(sizeof(int));
     SFN_HIP(hipMemsetAsync(w.zero_b.get(), 0, sizeof(int), w.s));
     launch_count_keep<V>(X.view(), nullptr, w.zero_b.as<int>(), w.icnt.as<int32_t>(),
-                         rows.as<double>(), nullptr, w.s);
+                         rows.as<double>(), nullptr, 0, w.s);
 }
 
 double nsf_budget(double e, double xfro, double tol, double c_fixed, double switch_res) {
@@ -427,8 +431,8 @@ template <typename V>
 LoopOut nsf_loop(Workspace &w, DMat<V> &X, const LoopParams &p,
                  std::vector<sign_iter_stats> &trace) {
     const int64_t n = X.n;
-    DMat<V> R, Xb, Xn;
-    R.bind(w.al); Xb.bind(w.al); Xn.bind(w.al);
+    DMat<V> R, Xb, Xn, Xl;
+    R.bind(w.al); Xb.bind(w.al); Xn.bind(w.al); Xl.bind(w.al);
     LoopOut out;
     row_sumsq(w, X, w.rs3);
     double xf = std::sqrt(w.sum_rows(w.rs3, n));
@@ -472,13 +476,24 @@ LoopOut nsf_loop(Workspace &w, DMat<V> &X, const LoopParams &p,
             std::swap(R, Xn);
         }
         // Xbar_{k+1} = X^_k + 1/2 X^_k R^_k  (= 1/2 X^_k (3I - X^_k^2))
-        product<V>(w, X, R, &X, 0.5, 1.0, 0.0, Xb, &w.rs2, nullptr, sym);
+        // (symmetric: the lower triangle of Xbar is filtered, with entries below
+        // the diagonal counted twice, and the survivors are mirrored)
+        product<V>(w, X, R, &X, 0.5, 1.0, 0.0, Xb, &w.rs2, nullptr, sym, sym);
         const double d = std::sqrt(w.sum_rows(w.rs2, n));
         // X^_{k+1} = Xbar_{k+1} - F_{k+1}
-        const int bstar = filter<V, V>(w, Xb, tau, Xn, &w.rs3, &w.rs4);
+        int bstar;
+        if (sym) {
+            bstar = filter<V, V>(w, Xb, tau, Xl, &w.rs3, &w.rs4, 1);
+            symmetrize<V>(w, Xl, Xn);
+        } else {
+            bstar = filter<V, V>(w, Xb, tau, Xn, &w.rs3, &w.rs4, 0);
+        }
         const double xf_new = std::sqrt(w.sum_rows(w.rs3, n));
         const double ff = std::sqrt(w.sum_rows(w.rs4, n));
-        it.d = d; it.tau = tau; it.ffro = ff; it.nnz_bar = Xb.nnz; it.bstar = bstar;
+        // (symmetric: the full Xbar holds both mirrors of the entries below the diagonal;
+        // counted with a full diagonal)
+        it.d = d; it.tau = tau; it.ffro = ff; it.bstar = bstar;
+        it.nnz_bar = sym ? 2 * Xb.nnz - n : Xb.nnz;
         it.ms = 1e3 * (now_s() - t0);
         trace.push_back(it);
         std::swap(X, Xn);
@@ -622,18 +637,18 @@ LoopOut nmf_loop(Workspace &w, DMat<double> &X, const LoopParams &p,
 
 template void product<double>(Workspace &, const DMat<double> &, const DMat<double> &,
                               const DMat<double> *, double, double, double, DMat<double> &,
-                              DevBuf *, DevBuf *, bool);
+                              DevBuf *, DevBuf *, bool, bool);
 template void product<float>(Workspace &, const DMat<float> &, const DMat<float> &,
                              const DMat<float> *, double, double, double, DMat<float> &, DevBuf *,
-                             DevBuf *, bool);
+                             DevBuf *, bool, bool);
 template int filter<double, double>(Workspace &, const DMat<double> &, double, DMat<double> &,
-                                    DevBuf *, DevBuf *);
+                                    DevBuf *, DevBuf *, int);
 template int filter<float, float>(Workspace &, const DMat<float> &, double, DMat<float> &,
-                                  DevBuf *, DevBuf *);
+                                  DevBuf *, DevBuf *, int);
 template int filter<float, double>(Workspace &, const DMat<float> &, double, DMat<double> &,
-                                   DevBuf *, DevBuf *);
+                                   DevBuf *, DevBuf *, int);
 template int filter<double, float>(Workspace &, const DMat<double> &, double, DMat<float> &,
-                                   DevBuf *, DevBuf *);
+                                   DevBuf *, DevBuf *, int);
 template void row_sumsq<double>(Workspace &, const DMat<double> &, DevBuf &);
 template void row_sumsq<float>(Workspace &, const DMat<float> &, DevBuf &);
 template LoopOut nsf_loop<double>(Workspace &, DMat<double> &, const LoopParams &,

@@ -47,11 +47,15 @@ struct Workspace {
 // that of the stored row of C (either may be null); only their totals are
 // meaningful when sym is set.  sym: the caller knows C is symmetric (A, B, D
 // symmetric and AB = BA); only the lower triangle is computed and the upper
-// one is its mirror.
+// one is its mirror.  keep_lower (with sym): C receives the lower triangle only.
 template <typename V>
 void product(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D, double coef,
              double dcoef, double diag, DMat<V> &C, DevBuf *sq_prod, DevBuf *sq_out,
-             bool sym = false);
+             bool sym = false, bool keep_lower = false);
+
+// C (full, compact) from the lower triangle L (compact) of a symmetric matrix.
+template <typename V>
+void symmetrize(Workspace &w, const DMat<V> &L, DMat<V> &C);
 
 // true if X equals its transpose exactly (pattern and values)
 template <typename V>
@@ -60,9 +64,11 @@ bool is_symmetric(Workspace &w, const DMat<V> &X);
 // Out = In without its largest low-magnitude part of Frobenius norm <= tau.
 // Returns the cut bucket; sq_keep/sq_drop (optional) receive per-row sums of
 // squares of kept / dropped entries.
+// lower: In is the lower triangle of a symmetric matrix (Out likewise); the cut
+// and the sums of squares count entries below the diagonal twice.
 template <typename V, typename Vo>
 int filter(Workspace &w, const DMat<V> &In, double tau, DMat<Vo> &Out, DevBuf *sq_keep,
-           DevBuf *sq_drop);
+           DevBuf *sq_drop, int lower = 0);
 
 // Filtering of a block-diagonal batch: segment s owns rows [seg_h[s], seg_h[s+1])
 // (seg_d: the same boundaries on the device, row_seg: segment of every row)

@@ -105,6 +105,15 @@ __device__ __forceinline__ int bucket_of(double x) {
     return 1 + 16 * (E + 127) + (int)((b >> 48) & 15u);
 }
 
+// Weight of an entry (row, col) in a Frobenius norm taken over the stored part
+// of a matrix: 1 when the whole matrix is stored; for a symmetric matrix held
+// by its lower triangle, 2 below the diagonal (the entry stands for itself and
+// its mirror), 1 on it, 0 above (not stored).
+__device__ __forceinline__ double sym_weight(int lower, int col, int row) {
+    if (!lower) return 1.0;
+    return col < row ? 2.0 : (col == row ? 1.0 : 0.0);
+}
+
 template <typename T>
 __device__ __forceinline__ double as_f64(T v) { return (double)v; }
 
@@ -576,14 +585,6 @@ __device__ __forceinline__ int group_accumulate(double (*acc)[T], const int (&c)
     return got;
 }
 
-// Weight of an entry (row, col) in a Frobenius norm taken over the stored part
-// of a matrix: 1 when the whole matrix is stored; for a symmetric matrix held
-// by its lower triangle, 2 below the diagonal (the entry stands for itself and
-// its mirror), 1 on it, 0 above (not stored).
-__device__ __forceinline__ double sym_weight(int lower, int col, int row) {
-    if (!lower) return 1.0;
-    return col < row ? 2.0 : (col == row ? 1.0 : 0.0);
-}
 
 // ---------------------------------------------------------------------------
 // numeric product: C = diag*I + coef*A*B + dcoef*D, row-wise (Gustavson)
@@ -846,7 +847,7 @@ constexpr int kHistRowsPerBlock = 128;
 
 template <typename V>
 __global__ __launch_bounds__(kHistThreads) void k_histogram(MatView<V> X, const int64_t *seg_rows,
-                                                            uint64_t *hist) {
+                                                            uint64_t *hist, int lower) {
     __shared__ uint32_t h[kBuckets];
     const int s = blockIdx.y;
     const int64_t rlo = seg_rows[s], rhi = seg_rows[s + 1];
@@ -859,7 +860,8 @@ __global__ __launch_bounds__(kHistThreads) void k_histogram(MatView<V> X, const 
         const int64_t b0 = X.beg[r];
         const int l = X.len[r];
         for (int p = lane_id(); p < l; p += kWave)
-            atomicAdd(&h[bucket_of(as_f64(X.val[b0 + p]))], 1u);
+            atomicAdd(&h[bucket_of(as_f64(X.val[b0 + p]))],
+                      (uint32_t)sym_weight(lower, X.col[b0 + p], (int)r));
     }
     __syncthreads();
     for (int b = threadIdx.x; b < kBuckets; b += kHistThreads)
@@ -895,7 +897,7 @@ __global__ void k_select(const uint64_t *hist, const double *tau, int nseg, int 
 
 template <typename V>
 __global__ void k_count_keep(MatView<V> X, const int32_t *row_seg, const int *bstar,
-                             int32_t *cnt, double *sq_keep, double *sq_drop) {
+                             int32_t *cnt, double *sq_keep, double *sq_drop, int lower) {
     const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
     if (i >= X.n) return;
     const int b = bstar[row_seg ? row_seg[i] : 0];
@@ -905,8 +907,9 @@ __global__ void k_count_keep(MatView<V> X, const int32_t *row_seg, const int *bs
     double sk = 0.0, sd = 0.0;
     for (int p = lane_id(); p < l; p += kWave) {
         const double v = as_f64(X.val[b0 + p]);
-        if (v != 0.0 && bucket_of(v) >= b) { ++k; sk += v * v; }
-        else sd += v * v;
+        const double wv = sym_weight(lower, X.col[b0 + p], (int)i) * v * v;
+        if (v != 0.0 && bucket_of(v) >= b) { ++k; sk += wv; }
+        else sd += wv;
     }
     k = wave_sum(k);
     sk = wave_sum(sk);
@@ -1563,15 +1566,15 @@ template void launch_copy_rows<float>(const int64_t *, int64_t, const int32_t *,
 
 template <typename V>
 void launch_histogram(MatView<V> X, const int64_t *seg_rows, int nseg, int64_t max_seg_rows,
-                      uint64_t *hist, hipStream_t s) {
+                      uint64_t *hist, int lower, hipStream_t s) {
     if (nseg <= 0 || max_seg_rows <= 0) return;
     dim3 grid(blocks_for(max_seg_rows, kHistRowsPerBlock), nseg);
-    k_histogram<V><<<grid, kHistThreads, 0, s>>>(X, seg_rows, hist);
+    k_histogram<V><<<grid, kHistThreads, 0, s>>>(X, seg_rows, hist, lower);
 }
 template void launch_histogram<double>(MatView<double>, const int64_t *, int, int64_t, uint64_t *,
-                                       hipStream_t);
+                                       int, hipStream_t);
 template void launch_histogram<float>(MatView<float>, const int64_t *, int, int64_t, uint64_t *,
-                                      hipStream_t);
+                                      int, hipStream_t);
 
 void launch_select(const uint64_t *hist, const double *tau, int nseg, int *bstar, hipStream_t s) {
     if (nseg > 0) k_select<<<blocks_for(nseg, 64), 64, 0, s>>>(hist, tau, nseg, bstar);
@@ -1579,14 +1582,15 @@ void launch_select(const uint64_t *hist, const double *tau, int nseg, int *bstar
 
 template <typename V>
 void launch_count_keep(MatView<V> X, const int32_t *row_seg, const int *bstar, int32_t *cnt,
-                       double *sq_keep, double *sq_drop, hipStream_t s) {
+                       double *sq_keep, double *sq_drop, int lower, hipStream_t s) {
     if (X.n <= 0) return;
-    k_count_keep<V><<<blocks_for(X.n, 4), 256, 0, s>>>(X, row_seg, bstar, cnt, sq_keep, sq_drop);
+    k_count_keep<V><<<blocks_for(X.n, 4), 256, 0, s>>>(X, row_seg, bstar, cnt, sq_keep, sq_drop,
+                                                       lower);
 }
 template void launch_count_keep<double>(MatView<double>, const int32_t *, const int *, int32_t *,
-                                        double *, double *, hipStream_t);
+                                        double *, double *, int, hipStream_t);
 template void launch_count_keep<float>(MatView<float>, const int32_t *, const int *, int32_t *,
-                                       double *, double *, hipStream_t);
+                                       double *, double *, int, hipStream_t);
 
 template <typename V, typename Vo>
 void launch_scatter_keep(MatView<V> X, const int32_t *row_seg, const int *bstar,

@@ -141,16 +141,18 @@ void launch_copy_rows(const int64_t *src_off, int64_t src_base, const int32_t *l
 // ---- filtering ---------------------------------------------------------------
 // Histogram of bucket(|x|) per segment.  seg_rows[s]..seg_rows[s+1] are the
 // rows of segment s; hist is nseg x kBuckets (uint64), zeroed by the caller.
+// lower: X is the lower triangle of a symmetric matrix; entries below the
+// diagonal count twice (here and in launch_count_keep's sums of squares).
 template <typename V>
 void launch_histogram(MatView<V> X, const int64_t *seg_rows, int nseg, int64_t max_seg_rows,
-                      uint64_t *hist, hipStream_t s);
+                      uint64_t *hist, int lower, hipStream_t s);
 // bstar[s] = cut bucket for budget tau[s] (one thread per segment, ascending
 // FP64 accumulation without contraction).
 void launch_select(const uint64_t *hist, const double *tau, int nseg, int *bstar, hipStream_t s);
 // Survivors per row (bucket >= bstar[seg], value != 0) and their/dropped sums of squares.
 template <typename V>
 void launch_count_keep(MatView<V> X, const int32_t *row_seg, const int *bstar, int32_t *cnt,
-                       double *sq_keep, double *sq_drop, hipStream_t s);
+                       double *sq_keep, double *sq_drop, int lower, hipStream_t s);
 template <typename V, typename Vo>
 void launch_scatter_keep(MatView<V> X, const int32_t *row_seg, const int *bstar,
                          const int64_t *dst_ptr, int32_t *dcol, Vo *dval, hipStream_t s);
