@@ -23,6 +23,15 @@
  * Errors: functions return a sign_status; negative values are errors, and
  * sign_last_error() gives a message for the last failing call of the calling
  * thread.  Nothing is printed.
+ *
+ * Symmetric inputs: sign_ns checks the (scaled) input for exact symmetry; when
+ * it holds and residuals are not filtered (filter_y = 0), every product of the
+ * iteration is symmetric and is formed from its lower triangle and mirrored,
+ * and the result is exactly symmetric.
+ *
+ * Tuning (environment, read when a call starts): SIGNFN_ROW_GROUP = 1, 2, 4,
+ * 8 (default) or 16 output rows per workgroup of the product kernel for rows
+ * with wide column spans; SIGNFN_SYMMETRIC=0 turns the symmetric products off.
  */
 #ifndef SIGNFN_H
 #define SIGNFN_H
