@@ -16,7 +16,7 @@ Workspace::Workspace(Allocator *a, size_t staging_bytes) : al(a), s(a->stream) {
     for (DevBuf *b : {&lo, &span, &cap, &work, &capoff, &workoff, &tmp, &bins, &counts, &cursor,
                       &stage_col, &stage_val, &rs1, &rs2, &rs3, &rs4, &icnt, &hist, &tau,
                       &bstar, &seg, &red, &flag, &zero_b, &cstat, &mk, &mm, &mc, &cv, &mlen, &cnext, &symcnt, &symoff, &symfill,
-                      &symtcol, &symtval})
+                      &symtcol, &symtval, &rs5})
         b->bind(a);
     // rows per workgroup for wide rows: 1 (off), 2, 4, 8 or 16
     if (const char *ge = std::getenv("SIGNFN_ROW_GROUP")) {
@@ -83,10 +83,27 @@ double Workspace::max_rows(const DevBuf &rows, int64_t n) {
 }
 
 namespace {
+// Largest bucket b such that every bucket below b has its upper edge at most
+// tau / sqrt(U): with at most U candidates, the entries there have a sum of
+// squares <= tau^2, so every cut the selection can take drops them.
+int safe_drop_bucket(double tau, double U) {
+    if (!(tau > 0.0) || !(U >= 1.0)) return 0;
+    const double t = tau / std::sqrt(U);
+    int b = 0;
+    while (b < kBucketTop) {
+        const double hi = b == 0 ? std::ldexp(1.0, -127)
+                                 : std::ldexp(1.0 + (double)((b - 1) % 16 + 1) / 16.0,
+                                              (b - 1) / 16 - 127);
+        if (hi > t) break;
+        ++b;
+    }
+    return b;
+}
+
 template <typename V>
 void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D,
                   double coef, double dcoef, double diag, DMat<V> &C, DevBuf *sq_prod,
-                  DevBuf *sq_out, int lower) {
+                  DevBuf *sq_out, int lower, const FusedFilter *ff) {
     const int64_t n = A.n;
     hipStream_t s = w.s;
     if (B.n != n || (D && D->n != n)) throw Error(SIGN_EINVAL, "product: shape mismatch");
@@ -118,6 +135,16 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
     SFN_HIP(hipStreamSynchronize(s));
     const int64_t total_cap = tot[0];
     w.products += tot[1];
+    ProductEpi epi;
+    epi.lower = lower;
+    if (ff) {
+        // the filter's histogram comes out of the product, and entries that no
+        // cut can keep are not stored (the candidates number at most total_cap,
+        // counted twice below the diagonal of a symmetric product)
+        epi.hist = ff->hist;
+        epi.sq_pre = ff->sq_pre;
+        epi.keep_from = safe_drop_bucket(ff->tau, (lower ? 2.0 : 1.0) * (double)total_cap);
+    }
 
     // batches of rows whose reserved output fits the staging budget
     const size_t entry = sizeof(int32_t) + sizeof(V);
@@ -193,7 +220,7 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
                                    w.cnext.as<int32_t>(),
                                    sq_prod ? sq_prod->as<double>() : nullptr,
                                    sq_out ? sq_out->as<double>() : nullptr,
-                                   w.cstat.as<int64_t>() + 4 * 8 + 4, lower, s);
+                                   w.cstat.as<int64_t>() + 4 * 8 + 4, epi, s);
         } else {
             SFN_HIP(hipEventRecord(w.ev[1], s));
         }
@@ -206,7 +233,7 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
                              w.cursor.as<int32_t>(), w.cnext.as<int32_t>(),
                              sq_prod ? sq_prod->as<double>() : nullptr,
                              sq_out ? sq_out->as<double>() : nullptr,
-                             w.cstat.as<int64_t>() + cls * 8 + 4, lower, s);
+                             w.cstat.as<int64_t>() + cls * 8 + 4, epi, s);
             SFN_HIP(hipEventRecord(w.ev[6 - cls], s));
         }
         // compact row starts of this batch, continuing from the previous batches
@@ -300,14 +327,14 @@ template void symmetrize<float>(Workspace &, const DMat<float> &, DMat<float> &)
 template <typename V>
 void product(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D, double coef,
              double dcoef, double diag, DMat<V> &C, DevBuf *sq_prod, DevBuf *sq_out, bool sym,
-             bool keep_lower) {
+             bool keep_lower, const FusedFilter *ff) {
     if (!sym || keep_lower) {
-        product_rows<V>(w, A, B, D, coef, dcoef, diag, C, sq_prod, sq_out, sym ? 1 : 0);
+        product_rows<V>(w, A, B, D, coef, dcoef, diag, C, sq_prod, sq_out, sym ? 1 : 0, ff);
         return;
     }
     DMat<V> L;
     L.bind(w.al);
-    product_rows<V>(w, A, B, D, coef, dcoef, diag, L, sq_prod, sq_out, 1);
+    product_rows<V>(w, A, B, D, coef, dcoef, diag, L, sq_prod, sq_out, 1, ff);
     symmetrize<V>(w, L, C);
 }
 
@@ -323,7 +350,7 @@ template bool is_symmetric<float>(Workspace &, const DMat<float> &);
 
 template <typename V, typename Vo>
 int filter(Workspace &w, const DMat<V> &In, double tau, DMat<Vo> &Out, DevBuf *sq_keep,
-           DevBuf *sq_drop, int lower) {
+           DevBuf *sq_drop, int lower, bool hist_ready) {
     const int64_t n = In.n;
     hipStream_t s = w.s;
     Out.ensure_rows(n);
@@ -337,8 +364,11 @@ int filter(Workspace &w, const DMat<V> &In, double tau, DMat<Vo> &Out, DevBuf *s
     const int64_t h[2] = {0, n};
     SFN_HIP(hipMemcpyAsync(w.seg.get(), h, sizeof(h), hipMemcpyHostToDevice, s));
     SFN_HIP(hipMemcpyAsync(w.tau.get(), &tau, sizeof(double), hipMemcpyHostToDevice, s));
-    SFN_HIP(hipMemsetAsync(w.hist.get(), 0, sizeof(uint64_t) * kBuckets, s));
-    launch_histogram<V>(In.view(), w.seg.as<int64_t>(), 1, n, w.hist.as<uint64_t>(), lower, s);
+    if (!hist_ready) {
+        SFN_HIP(hipMemsetAsync(w.hist.get(), 0, sizeof(uint64_t) * kBuckets, s));
+        launch_histogram<V>(In.view(), w.seg.as<int64_t>(), 1, n, w.hist.as<uint64_t>(), lower,
+                            s);
+    }
     launch_select(w.hist.as<uint64_t>(), w.tau.as<double>(), 1, w.bstar.as<int>(), s);
     launch_count_keep<V>(In.view(), nullptr, w.bstar.as<int>(), Out.lenp(),
                          sq_keep ? sq_keep->as<double>() : nullptr,
@@ -478,22 +508,33 @@ LoopOut nsf_loop(Workspace &w, DMat<V> &X, const LoopParams &p,
         // Xbar_{k+1} = X^_k + 1/2 X^_k R^_k  (= 1/2 X^_k (3I - X^_k^2))
         // (symmetric: the lower triangle of Xbar is filtered, with entries below
         // the diagonal counted twice, and the survivors are mirrored)
-        product<V>(w, X, R, &X, 0.5, 1.0, 0.0, Xb, &w.rs2, nullptr, sym, sym);
+        // (fused: the filter's histogram comes out of the product, and entries no
+        // cut can keep are never stored)
+        w.hist.ensure(sizeof(uint64_t) * kBuckets);
+        w.rs5.ensure(sizeof(double) * n);
+        SFN_HIP(hipMemsetAsync(w.hist.get(), 0, sizeof(uint64_t) * kBuckets, w.s));
+        SFN_HIP(hipMemsetAsync(w.rs5.get(), 0, sizeof(double) * n, w.s));  // rows with no output
+        const FusedFilter fuse{tau, w.hist.as<uint64_t>(), w.rs5.as<double>()};
+        product<V>(w, X, R, &X, 0.5, 1.0, 0.0, Xb, &w.rs2, nullptr, sym, sym, &fuse);
         const double d = std::sqrt(w.sum_rows(w.rs2, n));
+        const double pre = w.sum_rows(w.rs5, n);
         // X^_{k+1} = Xbar_{k+1} - F_{k+1}
         int bstar;
         if (sym) {
-            bstar = filter<V, V>(w, Xb, tau, Xl, &w.rs3, &w.rs4, 1);
+            bstar = filter<V, V>(w, Xb, tau, Xl, &w.rs3, &w.rs4, 1, true);
             symmetrize<V>(w, Xl, Xn);
         } else {
-            bstar = filter<V, V>(w, Xb, tau, Xn, &w.rs3, &w.rs4, 0);
+            bstar = filter<V, V>(w, Xb, tau, Xn, &w.rs3, &w.rs4, 0, true);
         }
         const double xf_new = std::sqrt(w.sum_rows(w.rs3, n));
-        const double ff = std::sqrt(w.sum_rows(w.rs4, n));
-        // (symmetric: the full Xbar holds both mirrors of the entries below the diagonal;
-        // counted with a full diagonal)
-        it.d = d; it.tau = tau; it.ffro = ff; it.bstar = bstar;
-        it.nnz_bar = sym ? 2 * Xb.nnz - n : Xb.nnz;
+        const double ff = std::sqrt(w.sum_rows(w.rs4, n) + pre);
+        // entries of the full Xbar: the histogram counts every candidate (twice
+        // below the diagonal of a symmetric product)
+        uint64_t hist_h[kBuckets];
+        SFN_HIP(hipMemcpy(hist_h, w.hist.get(), sizeof(hist_h), hipMemcpyDeviceToHost));
+        int64_t nbar = 0;
+        for (int b = 0; b < kBuckets; ++b) nbar += (int64_t)hist_h[b];
+        it.d = d; it.tau = tau; it.ffro = ff; it.bstar = bstar; it.nnz_bar = nbar;
         it.ms = 1e3 * (now_s() - t0);
         trace.push_back(it);
         std::swap(X, Xn);
@@ -637,18 +678,18 @@ LoopOut nmf_loop(Workspace &w, DMat<double> &X, const LoopParams &p,
 
 template void product<double>(Workspace &, const DMat<double> &, const DMat<double> &,
                               const DMat<double> *, double, double, double, DMat<double> &,
-                              DevBuf *, DevBuf *, bool, bool);
+                              DevBuf *, DevBuf *, bool, bool, const FusedFilter *);
 template void product<float>(Workspace &, const DMat<float> &, const DMat<float> &,
                              const DMat<float> *, double, double, double, DMat<float> &, DevBuf *,
-                             DevBuf *, bool, bool);
+                             DevBuf *, bool, bool, const FusedFilter *);
 template int filter<double, double>(Workspace &, const DMat<double> &, double, DMat<double> &,
-                                    DevBuf *, DevBuf *, int);
+                                    DevBuf *, DevBuf *, int, bool);
 template int filter<float, float>(Workspace &, const DMat<float> &, double, DMat<float> &,
-                                  DevBuf *, DevBuf *, int);
+                                  DevBuf *, DevBuf *, int, bool);
 template int filter<float, double>(Workspace &, const DMat<float> &, double, DMat<double> &,
-                                   DevBuf *, DevBuf *, int);
+                                   DevBuf *, DevBuf *, int, bool);
 template int filter<double, float>(Workspace &, const DMat<double> &, double, DMat<float> &,
-                                   DevBuf *, DevBuf *, int);
+                                   DevBuf *, DevBuf *, int, bool);
 template void row_sumsq<double>(Workspace &, const DMat<double> &, DevBuf &);
 template void row_sumsq<float>(Workspace &, const DMat<float> &, DevBuf &);
 template LoopOut nsf_loop<double>(Workspace &, DMat<double> &, const LoopParams &,

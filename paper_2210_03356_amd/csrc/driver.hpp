@@ -18,6 +18,7 @@ struct Workspace {
     DevBuf rs1, rs2, rs3, rs4, icnt, hist, tau, bstar, seg, red, flag, zero_b;
     DevBuf cstat, mk, mm, mc, cv, mlen, cnext;
     DevBuf symcnt, symoff, symfill, symtcol, symtval;  // mirroring of symmetric products
+    DevBuf rs5;                                        // per-row sums not stored by a product
     const uint8_t *row_skip = nullptr;  // optional row mask for products (serving)
     int row_group = 8;                  // wide rows computed in groups of 1, 2, 4, 8 or 16
     bool allow_sym = true;              // symmetric products from their lower triangle
@@ -48,10 +49,19 @@ struct Workspace {
 // meaningful when sym is set.  sym: the caller knows C is symmetric (A, B, D
 // symmetric and AB = BA); only the lower triangle is computed and the upper
 // one is its mirror.  keep_lower (with sym): C receives the lower triangle only.
+// A product whose output is filtered next with budget tau: the product adds the
+// filter's bucket histogram of all its entries to hist (kBuckets, zeroed by the
+// caller) and stores only entries that some cut could keep; the sums of squares
+// of the others go to sq_pre[row].
+struct FusedFilter {
+    double tau;
+    uint64_t *hist;
+    double *sq_pre;
+};
 template <typename V>
 void product(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D, double coef,
              double dcoef, double diag, DMat<V> &C, DevBuf *sq_prod, DevBuf *sq_out,
-             bool sym = false, bool keep_lower = false);
+             bool sym = false, bool keep_lower = false, const FusedFilter *ff = nullptr);
 
 // C (full, compact) from the lower triangle L (compact) of a symmetric matrix.
 template <typename V>
@@ -66,9 +76,10 @@ bool is_symmetric(Workspace &w, const DMat<V> &X);
 // squares of kept / dropped entries.
 // lower: In is the lower triangle of a symmetric matrix (Out likewise); the cut
 // and the sums of squares count entries below the diagonal twice.
+// hist_ready: the histogram of In is already in w.hist (a fused product).
 template <typename V, typename Vo>
 int filter(Workspace &w, const DMat<V> &In, double tau, DMat<Vo> &Out, DevBuf *sq_keep,
-           DevBuf *sq_drop, int lower = 0);
+           DevBuf *sq_drop, int lower = 0, bool hist_ready = false);
 
 // Filtering of a block-diagonal batch: segment s owns rows [seg_h[s], seg_h[s+1])
 // (seg_d: the same boundaries on the device, row_seg: segment of every row)

@@ -616,7 +616,7 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
     const int64_t *__restrict__ off, int64_t base, int32_t *__restrict__ out_col,
     V *__restrict__ out_val, int32_t *__restrict__ out_len, int32_t *__restrict__ cursor,
     int32_t *__restrict__ cnext, double *__restrict__ sq_prod, double *__restrict__ sq_out,
-    int64_t *__restrict__ out_count, int lower) {
+    int64_t *__restrict__ out_count, ProductEpi epi) {
     constexpr int NW = NT / kWave;
     constexpr int REG = T / NW;
     static_assert(T % (NW * kWave) == 0, "tile must split evenly over the waves");
@@ -627,6 +627,9 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
     __shared__ int wcnt[NW];
     __shared__ double wsum[2 * R][NW];  // per-wave partial sums of squares, per row
     __shared__ int wrt[R];              // entries written so far, per row
+    __shared__ uint32_t hst[kBuckets];  // bucket histogram of the candidates
+    __shared__ double wpre[R][NW];      // per-wave sums of squares not stored, per row
+    const int lower = epi.lower;
 
     const int lane = lane_id(), wave = wave_id();
     const int i = rows[xcd_row(blockIdx.x, gridDim.x)];
@@ -647,6 +650,9 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
 
     for (int q = threadIdx.x; q < 2 * R * NW; q += NT) (&wsum[0][0])[q] = 0.0;
     if (threadIdx.x < R) wrt[threadIdx.x] = 0;
+    if (epi.hist)
+        for (int q = threadIdx.x; q < kBuckets; q += NT) hst[q] = 0u;
+    for (int q = threadIdx.x; q < R * NW; q += NT) (&wpre[0][0])[q] = 0.0;
     for (int wlo = lo; wlo < hi; wlo += T) {
         const int nsl = min(T, hi - wlo);
         const int whi = wlo + nsl;
@@ -774,10 +780,27 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
             // columns written for this row: all, or up to the diagonal
             const int lim = lower ? min(nsl, i + r + 1 - wlo) : nsl;
             int cw = 0;
+            double pr = 0.0;
             for (int s0 = rbeg; s0 < rbeg + REG && s0 < nsl; s0 += kWave) {
                 const int s = s0 + lane;
                 const V v = s < lim ? (V)acc[r][s] : V(0);
-                cw += __popcll(__ballot(v != V(0)));
+                bool keep = v != V(0);
+                if (keep && (epi.hist || epi.keep_from > 0)) {
+                    // the filter's histogram counts every candidate; entries in
+                    // buckets below keep_from are dropped by any cut it can choose
+                    const int bk = bucket_of(as_f64(v));
+                    const double wgt = sym_weight(lower, wlo + s, i + r);
+                    if (epi.hist) atomicAdd(&hst[bk], (uint32_t)wgt);
+                    if (bk < epi.keep_from) {
+                        keep = false;
+                        pr += wgt * as_f64(v) * as_f64(v);
+                    }
+                }
+                cw += __popcll(__ballot(keep));
+            }
+            if (epi.sq_pre) {
+                pr = wave_sum(pr);
+                if (lane == 0) wpre[r][wave] += pr;
             }
             if (lane == 0) wcnt[wave] = cw;
             __syncthreads();
@@ -791,7 +814,8 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
             for (int s0 = rbeg; s0 < rbeg + REG && s0 < nsl; s0 += kWave) {
                 const int s = s0 + lane;
                 const V v = s < lim ? (V)acc[r][s] : V(0);
-                const bool nz = v != V(0);
+                const bool nz = v != V(0) && (epi.keep_from == 0 ||
+                                              bucket_of(as_f64(v)) >= epi.keep_from);
                 const uint64_t m = __ballot(nz);
                 if (nz) {
                     const int64_t pos = obase + o + lanes_below(m);
@@ -808,6 +832,14 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
         }
     }
     __syncthreads();
+    if (epi.hist)
+        for (int q = threadIdx.x; q < kBuckets; q += NT)
+            if (hst[q]) atomicAdd((unsigned long long *)&epi.hist[q], (unsigned long long)hst[q]);
+    if (epi.sq_pre && threadIdx.x < R) {
+        double x = 0.0;
+        for (int w = 0; w < NW; ++w) x += wpre[threadIdx.x][w];
+        epi.sq_pre[i + threadIdx.x] = x;
+    }
     if (threadIdx.x == 0) {
         unsigned long long tw = 0;
         for (int r = 0; r < R; ++r) {
@@ -1470,12 +1502,12 @@ static void group_launch(const int32_t *leads, int ngroups, const int32_t *mk, c
                          const int32_t *lo, const int32_t *span, int64_t base, const int64_t *off,
                          int32_t *out_col, V *out_val, int32_t *out_len, int32_t *cursor,
                          int32_t *cnext, double *sq_prod, double *sq_out, int64_t *out_count,
-                         int lower, hipStream_t s) {
+                         ProductEpi epi, hipStream_t s) {
     constexpr int T = R == 2 ? 4096 : 16384 / R;
     constexpr int NT = R == 2 ? 512 : 1024;
     k_spgemm_rows<V, R, T, NT, kUnroll><<<ngroups, NT, 0, s>>>(
         leads, mk, mm, mc, cv, mlen, A, B, D, (V)coef, (V)dcoef, (V)diag, lo, span, off, base,
-        out_col, out_val, out_len, cursor, cnext, sq_prod, sq_out, out_count, lower);
+        out_col, out_val, out_len, cursor, cnext, sq_prod, sq_out, out_count, epi);
 }
 
 template <typename V>
@@ -1485,11 +1517,11 @@ void launch_spgemm_group(int group, const int32_t *leads, int ngroups, const int
                          double diag, const int32_t *lo, const int32_t *span, int64_t base,
                          const int64_t *off, int32_t *out_col, V *out_val, int32_t *out_len,
                          int32_t *cursor, int32_t *cnext, double *sq_prod, double *sq_out,
-                         int64_t *out_count, int lower, hipStream_t s) {
+                         int64_t *out_count, ProductEpi epi, hipStream_t s) {
     if (ngroups <= 0) return;
 #define SFN_GROUP_ARGS                                                                        \
     leads, ngroups, mk, mm, mc, cv, mlen, A, B, D, coef, dcoef, diag, lo, span, base, off,    \
-        out_col, out_val, out_len, cursor, cnext, sq_prod, sq_out, out_count, lower, s
+        out_col, out_val, out_len, cursor, cnext, sq_prod, sq_out, out_count, epi, s
     switch (group) {
         case 2: group_launch<V, 2>(SFN_GROUP_ARGS); break;
         case 4: group_launch<V, 4>(SFN_GROUP_ARGS); break;
@@ -1505,26 +1537,26 @@ template void launch_spgemm_group<double>(int, const int32_t *, int, const int32
                                           const int32_t *, const int32_t *, int64_t,
                                           const int64_t *, int32_t *, double *, int32_t *,
                                           int32_t *, int32_t *, double *, double *, int64_t *,
-                                          int, hipStream_t);
+                                          ProductEpi, hipStream_t);
 template void launch_spgemm_group<float>(int, const int32_t *, int, const int32_t *,
                                          const uint32_t *, const int32_t *, const float *,
                                          const int32_t *, MatView<float>, MatView<float>,
                                          MatView<float>, double, double, double, const int32_t *,
                                          const int32_t *, int64_t, const int64_t *, int32_t *,
                                          float *, int32_t *, int32_t *, int32_t *, double *,
-                                         double *, int64_t *, int, hipStream_t);
+                                         double *, int64_t *, ProductEpi, hipStream_t);
 
 template <typename V>
 void launch_spgemm(int cls, const int32_t *rows, int nrows, MatView<V> A, MatView<V> B,
                    MatView<V> D, double coef, double dcoef, double diag, const int32_t *lo,
                    const int32_t *span, int64_t base, const int64_t *off, int32_t *out_col,
                    V *out_val, int32_t *out_len, int32_t *cursor, int32_t *cnext, double *sq_prod,
-                   double *sq_out, int64_t *out_count, int lower, hipStream_t s) {
+                   double *sq_out, int64_t *out_count, ProductEpi epi, hipStream_t s) {
     if (nrows <= 0) return;
     const V c = (V)coef, d = (V)diag, dc = (V)dcoef;
 #define SFN_ROW_ARGS                                                                          \
     rows, nullptr, nullptr, nullptr, nullptr, nullptr, A, B, D, c, dc, d, lo, span, off, base, \
-        out_col, out_val, out_len, cursor, cnext, sq_prod, sq_out, out_count, lower
+        out_col, out_val, out_len, cursor, cnext, sq_prod, sq_out, out_count, epi
     switch (cls) {
         case 1:
             k_spgemm_rows<V, 1, 512, 64, kUnroll><<<nrows, 64, 0, s>>>(SFN_ROW_ARGS);
@@ -1542,12 +1574,12 @@ template void launch_spgemm<double>(int, const int32_t *, int, MatView<double>, 
                                     MatView<double>, double, double, double, const int32_t *,
                                     const int32_t *, int64_t, const int64_t *, int32_t *, double *,
                                     int32_t *, int32_t *, int32_t *, double *, double *, int64_t *,
-                                    int, hipStream_t);
+                                    ProductEpi, hipStream_t);
 template void launch_spgemm<float>(int, const int32_t *, int, MatView<float>, MatView<float>,
                                    MatView<float>, double, double, double, const int32_t *,
                                    const int32_t *, int64_t, const int64_t *, int32_t *, float *,
                                    int32_t *, int32_t *, int32_t *, double *, double *, int64_t *,
-                                   int, hipStream_t);
+                                   ProductEpi, hipStream_t);
 
 template <typename V>
 void launch_copy_rows(const int64_t *src_off, int64_t src_base, const int32_t *len,

@@ -26,6 +26,16 @@ struct MatView {
 };
 
 // Launch geometry of the numeric product for one row class.
+// Output options of the numeric product.
+struct ProductEpi {
+    int lower = 0;             // store only columns <= the row (symmetric product)
+    int keep_from = 0;         // store only entries whose bucket >= keep_from
+    uint64_t *hist = nullptr;  // += bucket histogram of all nonzero entries (weighted
+                               //    as launch_histogram with `lower`), kBuckets long
+    double *sq_pre = nullptr;  // [row] sum of squares of the entries not stored
+                               //    because of keep_from (weighted likewise)
+};
+
 struct BinCfg {
     int tile;     // LDS accumulator slots (columns per window)
     int threads;  // workgroup size
@@ -94,7 +104,7 @@ void launch_spgemm_group(int group, const int32_t *leads, int ngroups, const int
                          double diag, const int32_t *lo, const int32_t *span, int64_t base,
                          const int64_t *off, int32_t *out_col, V *out_val, int32_t *out_len,
                          int32_t *cursor, int32_t *cnext, double *sq_prod, double *sq_out,
-                         int64_t *out_count, int lower, hipStream_t s);
+                         int64_t *out_count, ProductEpi epi, hipStream_t s);
 // tile = LDS accumulator columns per row of the group
 BinCfg group_config(int group, int value_bytes);
 
@@ -128,7 +138,7 @@ void launch_spgemm(int cls, const int32_t *rows, int nrows, MatView<V> A, MatVie
                    MatView<V> D, double coef, double dcoef, double diag, const int32_t *lo,
                    const int32_t *span, int64_t base, const int64_t *off, int32_t *out_col,
                    V *out_val, int32_t *out_len, int32_t *cursor, int32_t *cnext, double *sq_prod,
-                   double *sq_out, int64_t *out_count, int lower, hipStream_t s);
+                   double *sq_out, int64_t *out_count, ProductEpi epi, hipStream_t s);
 BinCfg bin_config(int cls, int value_bytes);
 
 // Copy rows [r0, r1) from a gapped layout (row i at src_off[i] - src_base)
