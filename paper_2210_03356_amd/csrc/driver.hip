@@ -16,7 +16,7 @@ Workspace::Workspace(Allocator *a, size_t staging_bytes) : al(a), s(a->stream) {
     for (DevBuf *b : {&lo, &span, &cap, &work, &capoff, &workoff, &tmp, &bins, &counts, &cursor,
                       &stage_col, &stage_val, &rs1, &rs2, &rs3, &rs4, &icnt, &hist, &tau,
                       &bstar, &seg, &red, &flag, &zero_b, &cstat, &mk, &mm, &mc, &cv, &mlen, &cnext, &symcnt, &symoff, &symfill,
-                      &symtcol, &symtval, &rs5})
+                      &symtcol, &symtval, &rs5, &whole, &sums})
         b->bind(a);
     // rows per workgroup for wide rows: 1 (off), 2, 4, 8 or 16
     if (const char *ge = std::getenv("SIGNFN_ROW_GROUP")) {
@@ -65,12 +65,27 @@ void Workspace::hot_stats(sign_stats &st) const {
 }
 
 double Workspace::sum_rows(const DevBuf &rows, int64_t n) {
-    seg.ensure(2 * sizeof(int64_t));
-    red.ensure(sizeof(double));
-    const int64_t h[2] = {0, n};
-    SFN_HIP(hipMemcpyAsync(seg.get(), h, sizeof(h), hipMemcpyHostToDevice, s));
-    launch_seg_sum(rows.as<double>(), seg.as<int64_t>(), 1, red.as<double>(), s);
-    return read_scalar(red.as<double>(), s);
+    return sum_rows_many({&rows}, n)[0];
+}
+
+std::vector<double> Workspace::sum_rows_many(std::initializer_list<const DevBuf *> rows,
+                                             int64_t n) {
+    const int k = (int)rows.size();
+    whole.ensure(2 * sizeof(int64_t));
+    if (whole_n != n) {
+        const int64_t h[2] = {0, n};
+        SFN_HIP(hipMemcpyAsync(whole.get(), h, sizeof(h), hipMemcpyHostToDevice, s));
+        whole_n = n;
+    }
+    sums.ensure(sizeof(double) * (size_t)k);
+    int j = 0;
+    for (const DevBuf *r : rows)
+        launch_seg_sum(r->as<double>(), whole.as<int64_t>(), 1, sums.as<double>() + j++, s);
+    std::vector<double> out((size_t)k);
+    SFN_HIP(hipMemcpyAsync(out.data(), sums.get(), sizeof(double) * (size_t)k,
+                           hipMemcpyDeviceToHost, s));
+    SFN_HIP(hipStreamSynchronize(s));
+    return out;
 }
 
 double Workspace::max_rows(const DevBuf &rows, int64_t n) {
@@ -350,7 +365,7 @@ template bool is_symmetric<float>(Workspace &, const DMat<float> &);
 
 template <typename V, typename Vo>
 int filter(Workspace &w, const DMat<V> &In, double tau, DMat<Vo> &Out, DevBuf *sq_keep,
-           DevBuf *sq_drop, int lower, bool hist_ready) {
+           DevBuf *sq_drop, int lower, bool hist_ready, int64_t *candidates) {
     const int64_t n = In.n;
     hipStream_t s = w.s;
     Out.ensure_rows(n);
@@ -380,7 +395,14 @@ int filter(Workspace &w, const DMat<V> &In, double tau, DMat<Vo> &Out, DevBuf *s
     SFN_HIP(hipMemcpyAsync(&total, Out.begp() + n, sizeof(int64_t),
                            hipMemcpyDeviceToHost, s));
     SFN_HIP(hipMemcpyAsync(&bstar, w.bstar.get(), sizeof(int), hipMemcpyDeviceToHost, s));
+    uint64_t hist_h[kBuckets];
+    if (candidates)
+        SFN_HIP(hipMemcpyAsync(hist_h, w.hist.get(), sizeof(hist_h), hipMemcpyDeviceToHost, s));
     SFN_HIP(hipStreamSynchronize(s));
+    if (candidates) {
+        *candidates = 0;
+        for (int b = 0; b < kBuckets; ++b) *candidates += (int64_t)hist_h[b];
+    }
     Out.ensure_entries(total);
     launch_scatter_keep<V, Vo>(In.view(), nullptr, w.bstar.as<int>(), Out.begp(),
                                Out.colp(), Out.valp(), s);
@@ -516,24 +538,21 @@ LoopOut nsf_loop(Workspace &w, DMat<V> &X, const LoopParams &p,
         SFN_HIP(hipMemsetAsync(w.rs5.get(), 0, sizeof(double) * n, w.s));  // rows with no output
         const FusedFilter fuse{tau, w.hist.as<uint64_t>(), w.rs5.as<double>()};
         product<V>(w, X, R, &X, 0.5, 1.0, 0.0, Xb, &w.rs2, nullptr, sym, sym, &fuse);
-        const double d = std::sqrt(w.sum_rows(w.rs2, n));
-        const double pre = w.sum_rows(w.rs5, n);
         // X^_{k+1} = Xbar_{k+1} - F_{k+1}
+        // (nbar: entries of the full Xbar -- the histogram counts every candidate,
+        // twice below the diagonal of a symmetric product)
         int bstar;
+        int64_t nbar = 0;
         if (sym) {
-            bstar = filter<V, V>(w, Xb, tau, Xl, &w.rs3, &w.rs4, 1, true);
+            bstar = filter<V, V>(w, Xb, tau, Xl, &w.rs3, &w.rs4, 1, true, &nbar);
             symmetrize<V>(w, Xl, Xn);
         } else {
-            bstar = filter<V, V>(w, Xb, tau, Xn, &w.rs3, &w.rs4, 0, true);
+            bstar = filter<V, V>(w, Xb, tau, Xn, &w.rs3, &w.rs4, 0, true, &nbar);
         }
-        const double xf_new = std::sqrt(w.sum_rows(w.rs3, n));
-        const double ff = std::sqrt(w.sum_rows(w.rs4, n) + pre);
-        // entries of the full Xbar: the histogram counts every candidate (twice
-        // below the diagonal of a symmetric product)
-        uint64_t hist_h[kBuckets];
-        SFN_HIP(hipMemcpy(hist_h, w.hist.get(), sizeof(hist_h), hipMemcpyDeviceToHost));
-        int64_t nbar = 0;
-        for (int b = 0; b < kBuckets; ++b) nbar += (int64_t)hist_h[b];
+        const std::vector<double> sums = w.sum_rows_many({&w.rs2, &w.rs5, &w.rs3, &w.rs4}, n);
+        const double d = std::sqrt(sums[0]);
+        const double xf_new = std::sqrt(sums[2]);
+        const double ff = std::sqrt(sums[3] + sums[1]);
         it.d = d; it.tau = tau; it.ffro = ff; it.bstar = bstar; it.nnz_bar = nbar;
         it.ms = 1e3 * (now_s() - t0);
         trace.push_back(it);
@@ -683,13 +702,13 @@ template void product<float>(Workspace &, const DMat<float> &, const DMat<float>
                              const DMat<float> *, double, double, double, DMat<float> &, DevBuf *,
                              DevBuf *, bool, bool, const FusedFilter *);
 template int filter<double, double>(Workspace &, const DMat<double> &, double, DMat<double> &,
-                                    DevBuf *, DevBuf *, int, bool);
+                                    DevBuf *, DevBuf *, int, bool, int64_t *);
 template int filter<float, float>(Workspace &, const DMat<float> &, double, DMat<float> &,
-                                  DevBuf *, DevBuf *, int, bool);
+                                  DevBuf *, DevBuf *, int, bool, int64_t *);
 template int filter<float, double>(Workspace &, const DMat<float> &, double, DMat<double> &,
-                                   DevBuf *, DevBuf *, int, bool);
+                                   DevBuf *, DevBuf *, int, bool, int64_t *);
 template int filter<double, float>(Workspace &, const DMat<double> &, double, DMat<float> &,
-                                   DevBuf *, DevBuf *, int, bool);
+                                   DevBuf *, DevBuf *, int, bool, int64_t *);
 template void row_sumsq<double>(Workspace &, const DMat<double> &, DevBuf &);
 template void row_sumsq<float>(Workspace &, const DMat<float> &, DevBuf &);
 template LoopOut nsf_loop<double>(Workspace &, DMat<double> &, const LoopParams &,

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <chrono>
+#include <initializer_list>
 #include <vector>
 
 #include "runtime.hpp"
@@ -40,6 +41,10 @@ struct Workspace {
     ~Workspace();
     // ||rows||: deterministic sum of a per-row double array over [0, n)
     double sum_rows(const DevBuf &rows, int64_t n);
+    // several row-sum totals with one synchronisation
+    std::vector<double> sum_rows_many(std::initializer_list<const DevBuf *> rows, int64_t n);
+    DevBuf whole, sums;   // {0, n} segment for whole-matrix sums, their results
+    int64_t whole_n = -1;
     double max_rows(const DevBuf &rows, int64_t n);
 };
 
@@ -76,10 +81,12 @@ bool is_symmetric(Workspace &w, const DMat<V> &X);
 // squares of kept / dropped entries.
 // lower: In is the lower triangle of a symmetric matrix (Out likewise); the cut
 // and the sums of squares count entries below the diagonal twice.
-// hist_ready: the histogram of In is already in w.hist (a fused product).
+// hist_ready: the histogram of In is already in w.hist (a fused product);
+// candidates (optional): the histogram's total count.
 template <typename V, typename Vo>
 int filter(Workspace &w, const DMat<V> &In, double tau, DMat<Vo> &Out, DevBuf *sq_keep,
-           DevBuf *sq_drop, int lower = 0, bool hist_ready = false);
+           DevBuf *sq_drop, int lower = 0, bool hist_ready = false,
+           int64_t *candidates = nullptr);
 
 // Filtering of a block-diagonal batch: segment s owns rows [seg_h[s], seg_h[s+1])
 // (seg_d: the same boundaries on the device, row_seg: segment of every row)
