@@ -118,7 +118,7 @@ int safe_drop_bucket(double tau, double U) {
 template <typename V>
 void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D,
                   double coef, double dcoef, double diag, DMat<V> &C, DevBuf *sq_prod,
-                  DevBuf *sq_out, int lower, const FusedFilter *ff) {
+                  DevBuf *sq_out, LowerRows lower, const FusedFilter *ff) {
     const int64_t n = A.n;
     hipStream_t s = w.s;
     if (B.n != n || (D && D->n != n)) throw Error(SIGN_EINVAL, "product: shape mismatch");
@@ -158,7 +158,7 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
         // counted twice below the diagonal of a symmetric product)
         epi.hist = ff->hist;
         epi.sq_pre = ff->sq_pre;
-        epi.keep_from = safe_drop_bucket(ff->tau, (lower ? 2.0 : 1.0) * (double)total_cap);
+        epi.keep_from = safe_drop_bucket(ff->tau, (lower.any() ? 2.0 : 1.0) * (double)total_cap);
     }
 
     // batches of rows whose reserved output fits the staging budget
@@ -307,7 +307,7 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
 // then each row's mirror list (the strictly-lower entries of its column),
 // ordered by column.
 template <typename V>
-void symmetrize(Workspace &w, const DMat<V> &L, DMat<V> &C) {
+void symmetrize(Workspace &w, const DMat<V> &L, DMat<V> &C, LowerRows lower) {
     const int64_t n = L.n;
     hipStream_t s = w.s;
     C.ensure_rows(n);
@@ -317,7 +317,7 @@ void symmetrize(Workspace &w, const DMat<V> &L, DMat<V> &C) {
     w.tmp.ensure(sizeof(int64_t) * scan_tmp_elems(n));
     SFN_HIP(hipMemsetAsync(w.symcnt.get(), 0, sizeof(int32_t) * n, s));
     SFN_HIP(hipMemsetAsync(w.symfill.get(), 0, sizeof(int32_t) * n, s));
-    launch_sym_count<V>(L.view(), w.symcnt.as<int32_t>(), s);
+    launch_sym_count<V>(L.view(), lower, w.symcnt.as<int32_t>(), s);
     launch_exclusive_scan_i32(w.symcnt.as<int32_t>(), n, w.symoff.as<int64_t>(),
                               w.tmp.as<int64_t>(), 0, s);
     launch_add_len(L.lenp(), w.symcnt.as<int32_t>(), n, C.lenp(), s);
@@ -330,27 +330,30 @@ void symmetrize(Workspace &w, const DMat<V> &L, DMat<V> &C) {
     C.ensure_entries(tot[0]);
     w.symtcol.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(tot[1], 1));
     w.symtval.ensure(sizeof(V) * (size_t)std::max<int64_t>(tot[1], 1));
-    launch_sym_place<V>(L.view(), C.begp(), C.colp(), C.valp(), w.symoff.as<int64_t>(),
+    launch_sym_place<V>(L.view(), lower, C.begp(), C.colp(), C.valp(), w.symoff.as<int64_t>(),
                         w.symfill.as<int32_t>(), w.symtcol.as<int32_t>(), w.symtval.as<V>(), s);
     launch_sym_rank<V>(n, C.begp(), L.lenp(), w.symoff.as<int64_t>(), w.symcnt.as<int32_t>(),
                        w.symtcol.as<int32_t>(), w.symtval.as<V>(), C.colp(), C.valp(), s);
     C.nnz = tot[0];
 }
-template void symmetrize<double>(Workspace &, const DMat<double> &, DMat<double> &);
-template void symmetrize<float>(Workspace &, const DMat<float> &, DMat<float> &);
+template void symmetrize<double>(Workspace &, const DMat<double> &, DMat<double> &, LowerRows);
+template void symmetrize<float>(Workspace &, const DMat<float> &, DMat<float> &, LowerRows);
 
 template <typename V>
 void product(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D, double coef,
              double dcoef, double diag, DMat<V> &C, DevBuf *sq_prod, DevBuf *sq_out, bool sym,
-             bool keep_lower, const FusedFilter *ff) {
-    if (!sym || keep_lower) {
-        product_rows<V>(w, A, B, D, coef, dcoef, diag, C, sq_prod, sq_out, sym ? 1 : 0, ff);
+             bool keep_lower, const FusedFilter *ff, const uint8_t *row_sym) {
+    LowerRows lower;
+    lower.all = sym ? 1 : 0;
+    lower.rows = row_sym;
+    if (!lower.any() || keep_lower) {
+        product_rows<V>(w, A, B, D, coef, dcoef, diag, C, sq_prod, sq_out, lower, ff);
         return;
     }
     DMat<V> L;
     L.bind(w.al);
-    product_rows<V>(w, A, B, D, coef, dcoef, diag, L, sq_prod, sq_out, 1, ff);
-    symmetrize<V>(w, L, C);
+    product_rows<V>(w, A, B, D, coef, dcoef, diag, L, sq_prod, sq_out, lower, ff);
+    symmetrize<V>(w, L, C, lower);
 }
 
 template <typename V>
@@ -381,13 +384,16 @@ int filter(Workspace &w, const DMat<V> &In, double tau, DMat<Vo> &Out, DevBuf *s
     SFN_HIP(hipMemcpyAsync(w.tau.get(), &tau, sizeof(double), hipMemcpyHostToDevice, s));
     if (!hist_ready) {
         SFN_HIP(hipMemsetAsync(w.hist.get(), 0, sizeof(uint64_t) * kBuckets, s));
-        launch_histogram<V>(In.view(), w.seg.as<int64_t>(), 1, n, w.hist.as<uint64_t>(), lower,
-                            s);
+            LowerRows lr;
+        lr.all = lower;
+        launch_histogram<V>(In.view(), w.seg.as<int64_t>(), 1, n, w.hist.as<uint64_t>(), lr, s);
     }
     launch_select(w.hist.as<uint64_t>(), w.tau.as<double>(), 1, w.bstar.as<int>(), s);
+    LowerRows lrk;
+    lrk.all = lower;
     launch_count_keep<V>(In.view(), nullptr, w.bstar.as<int>(), Out.lenp(),
                          sq_keep ? sq_keep->as<double>() : nullptr,
-                         sq_drop ? sq_drop->as<double>() : nullptr, lower, s);
+                         sq_drop ? sq_drop->as<double>() : nullptr, lrk, s);
     launch_exclusive_scan_i32(Out.lenp(), n, Out.begp(),
                               w.tmp.as<int64_t>(), 0, s);
     int64_t total;
@@ -412,7 +418,8 @@ int filter(Workspace &w, const DMat<V> &In, double tau, DMat<Vo> &Out, DevBuf *s
 
 void filter_seg(Workspace &w, const DMat<double> &In, const std::vector<int64_t> &seg_h,
                 const int64_t *seg_d, const int32_t *row_seg, const std::vector<double> &tau_h,
-                DMat<double> &Out, DevBuf *sq_keep, DevBuf *sq_drop, std::vector<int> &bstar_h) {
+                DMat<double> &Out, DevBuf *sq_keep, DevBuf *sq_drop, std::vector<int> &bstar_h,
+                LowerRows lower) {
     const int64_t n = In.n;
     const int nseg = (int)tau_h.size();
     hipStream_t s = w.s;
@@ -428,11 +435,11 @@ void filter_seg(Workspace &w, const DMat<double> &In, const std::vector<int64_t>
     SFN_HIP(hipMemcpyAsync(w.tau.get(), tau_h.data(), sizeof(double) * nseg,
                            hipMemcpyHostToDevice, s));
     SFN_HIP(hipMemsetAsync(w.hist.get(), 0, sizeof(uint64_t) * kBuckets * nseg, s));
-    launch_histogram<double>(In.view(), seg_d, nseg, maxrows, w.hist.as<uint64_t>(), 0, s);
+    launch_histogram<double>(In.view(), seg_d, nseg, maxrows, w.hist.as<uint64_t>(), lower, s);
     launch_select(w.hist.as<uint64_t>(), w.tau.as<double>(), nseg, w.bstar.as<int>(), s);
     launch_count_keep<double>(In.view(), row_seg, w.bstar.as<int>(), Out.lenp(),
                               sq_keep ? sq_keep->as<double>() : nullptr,
-                              sq_drop ? sq_drop->as<double>() : nullptr, 0, s);
+                              sq_drop ? sq_drop->as<double>() : nullptr, lower, s);
     launch_exclusive_scan_i32(Out.lenp(), n, Out.begp(), w.tmp.as<int64_t>(), 0, s);
     int64_t total;
     bstar_h.resize(nseg);
@@ -465,7 +472,7 @@ void row_sumsq(Workspace &w, const DMat<V> &X, DevBuf &rows) {
     w.zero_b.ensure(sizeof(int));
     SFN_HIP(hipMemsetAsync(w.zero_b.get(), 0, sizeof(int), w.s));
     launch_count_keep<V>(X.view(), nullptr, w.zero_b.as<int>(), w.icnt.as<int32_t>(),
-                         rows.as<double>(), nullptr, 0, w.s);
+                         rows.as<double>(), nullptr, LowerRows(), w.s);
 }
 
 double nsf_budget(double e, double xfro, double tol, double c_fixed, double switch_res) {
@@ -697,10 +704,11 @@ LoopOut nmf_loop(Workspace &w, DMat<double> &X, const LoopParams &p,
 
 template void product<double>(Workspace &, const DMat<double> &, const DMat<double> &,
                               const DMat<double> *, double, double, double, DMat<double> &,
-                              DevBuf *, DevBuf *, bool, bool, const FusedFilter *);
+                              DevBuf *, DevBuf *, bool, bool, const FusedFilter *,
+                              const uint8_t *);
 template void product<float>(Workspace &, const DMat<float> &, const DMat<float> &,
                              const DMat<float> *, double, double, double, DMat<float> &, DevBuf *,
-                             DevBuf *, bool, bool, const FusedFilter *);
+                             DevBuf *, bool, bool, const FusedFilter *, const uint8_t *);
 template int filter<double, double>(Workspace &, const DMat<double> &, double, DMat<double> &,
                                     DevBuf *, DevBuf *, int, bool, int64_t *);
 template int filter<float, float>(Workspace &, const DMat<float> &, double, DMat<float> &,

@@ -66,11 +66,15 @@ struct FusedFilter {
 template <typename V>
 void product(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D, double coef,
              double dcoef, double diag, DMat<V> &C, DevBuf *sq_prod, DevBuf *sq_out,
-             bool sym = false, bool keep_lower = false, const FusedFilter *ff = nullptr);
+             bool sym = false, bool keep_lower = false, const FusedFilter *ff = nullptr,
+             const uint8_t *row_sym = nullptr);
+// (row_sym: per-row flags instead of sym, for block-diagonal batches whose
+// symmetric blocks -- and only those -- take the symmetric route)
 
-// C (full, compact) from the lower triangle L (compact) of a symmetric matrix.
+// C (full, compact) from the lower triangle L (compact) of a symmetric matrix
+// (or of the rows of its symmetric diagonal blocks flagged in lower.rows).
 template <typename V>
-void symmetrize(Workspace &w, const DMat<V> &L, DMat<V> &C);
+void symmetrize(Workspace &w, const DMat<V> &L, DMat<V> &C, LowerRows lower = LowerRows{1, nullptr});
 
 // true if X equals its transpose exactly (pattern and values)
 template <typename V>
@@ -93,7 +97,8 @@ int filter(Workspace &w, const DMat<V> &In, double tau, DMat<Vo> &Out, DevBuf *s
 // and is cut with its own budget tau_h[s].  bstar_h receives the cuts.
 void filter_seg(Workspace &w, const DMat<double> &In, const std::vector<int64_t> &seg_h,
                 const int64_t *seg_d, const int32_t *row_seg, const std::vector<double> &tau_h,
-                DMat<double> &Out, DevBuf *sq_keep, DevBuf *sq_drop, std::vector<int> &bstar_h);
+                DMat<double> &Out, DevBuf *sq_keep, DevBuf *sq_drop, std::vector<int> &bstar_h,
+                LowerRows lower = LowerRows());
 
 // Per-segment sums of a per-row FP64 array (deterministic).
 std::vector<double> seg_sums(Workspace &w, const DevBuf &rows, const int64_t *seg_d, int nseg);

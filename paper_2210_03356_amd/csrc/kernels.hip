@@ -109,7 +109,7 @@ __device__ __forceinline__ int bucket_of(double x) {
 // of a matrix: 1 when the whole matrix is stored; for a symmetric matrix held
 // by its lower triangle, 2 below the diagonal (the entry stands for itself and
 // its mirror), 1 on it, 0 above (not stored).
-__device__ __forceinline__ double sym_weight(int lower, int col, int row) {
+__device__ __forceinline__ double sym_weight(bool lower, int col, int row) {
     if (!lower) return 1.0;
     return col < row ? 2.0 : (col == row ? 1.0 : 0.0);
 }
@@ -629,7 +629,6 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
     __shared__ int wrt[R];              // entries written so far, per row
     __shared__ uint32_t hst[kBuckets];  // bucket histogram of the candidates
     __shared__ double wpre[R][NW];      // per-wave sums of squares not stored, per row
-    const int lower = epi.lower;
 
     const int lane = lane_id(), wave = wave_id();
     const int i = rows[xcd_row(blockIdx.x, gridDim.x)];
@@ -642,7 +641,10 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
     // lower: only columns <= the row itself (the product is symmetric and its
     // upper triangle is mirrored afterwards); B rows are then read only up to
     // the diagonal, as the sweep stops at the last window
-    if (lower) hi = min(hi, i + R);
+    bool all_lower = true;
+#pragma unroll
+    for (int r = 0; r < R; ++r) all_lower = all_lower && epi.lower.of(i + r);
+    if (all_lower) hi = min(hi, i + R);
     const int64_t mbeg = A.beg[i];
     const int ml = R == 1 ? A.len[i] : mlen[i];
     const bool multi = hi - lo > T;
@@ -748,7 +750,7 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
                 double x = 0.0;
                 for (int s = threadIdx.x; s < nsl; s += NT) {
                     const double v = acc[r][s];
-                    x += sym_weight(lower, wlo + s, i + r) * v * v;
+                    x += sym_weight(epi.lower.of(i + r), wlo + s, i + r) * v * v;
                 }
                 x = wave_sum(x);
                 if (lane == 0) wsum[2 * r][wave] += x;
@@ -778,7 +780,8 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
             const int64_t obase = off[i + r] - base;
             const int rbeg = wave * REG;
             // columns written for this row: all, or up to the diagonal
-            const int lim = lower ? min(nsl, i + r + 1 - wlo) : nsl;
+            const bool low = epi.lower.of(i + r);
+            const int lim = low ? min(nsl, i + r + 1 - wlo) : nsl;
             int cw = 0;
             double pr = 0.0;
             for (int s0 = rbeg; s0 < rbeg + REG && s0 < nsl; s0 += kWave) {
@@ -789,7 +792,7 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
                     // the filter's histogram counts every candidate; entries in
                     // buckets below keep_from are dropped by any cut it can choose
                     const int bk = bucket_of(as_f64(v));
-                    const double wgt = sym_weight(lower, wlo + s, i + r);
+                    const double wgt = sym_weight(low, wlo + s, i + r);
                     if (epi.hist) atomicAdd(&hst[bk], (uint32_t)wgt);
                     if (bk < epi.keep_from) {
                         keep = false;
@@ -821,7 +824,7 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
                     const int64_t pos = obase + o + lanes_below(m);
                     out_col[pos] = wlo + s;
                     out_val[pos] = v;
-                    y += sym_weight(lower, wlo + s, i + r) * as_f64(v) * as_f64(v);
+                    y += sym_weight(low, wlo + s, i + r) * as_f64(v) * as_f64(v);
                 }
                 o += __popcll(m);
             }
@@ -879,7 +882,7 @@ constexpr int kHistRowsPerBlock = 128;
 
 template <typename V>
 __global__ __launch_bounds__(kHistThreads) void k_histogram(MatView<V> X, const int64_t *seg_rows,
-                                                            uint64_t *hist, int lower) {
+                                                            uint64_t *hist, LowerRows lower) {
     __shared__ uint32_t h[kBuckets];
     const int s = blockIdx.y;
     const int64_t rlo = seg_rows[s], rhi = seg_rows[s + 1];
@@ -893,7 +896,7 @@ __global__ __launch_bounds__(kHistThreads) void k_histogram(MatView<V> X, const 
         const int l = X.len[r];
         for (int p = lane_id(); p < l; p += kWave)
             atomicAdd(&h[bucket_of(as_f64(X.val[b0 + p]))],
-                      (uint32_t)sym_weight(lower, X.col[b0 + p], (int)r));
+                      (uint32_t)sym_weight(lower.of(r), X.col[b0 + p], (int)r));
     }
     __syncthreads();
     for (int b = threadIdx.x; b < kBuckets; b += kHistThreads)
@@ -929,7 +932,7 @@ __global__ void k_select(const uint64_t *hist, const double *tau, int nseg, int 
 
 template <typename V>
 __global__ void k_count_keep(MatView<V> X, const int32_t *row_seg, const int *bstar,
-                             int32_t *cnt, double *sq_keep, double *sq_drop, int lower) {
+                             int32_t *cnt, double *sq_keep, double *sq_drop, LowerRows lower) {
     const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
     if (i >= X.n) return;
     const int b = bstar[row_seg ? row_seg[i] : 0];
@@ -939,7 +942,7 @@ __global__ void k_count_keep(MatView<V> X, const int32_t *row_seg, const int *bs
     double sk = 0.0, sd = 0.0;
     for (int p = lane_id(); p < l; p += kWave) {
         const double v = as_f64(X.val[b0 + p]);
-        const double wv = sym_weight(lower, X.col[b0 + p], (int)i) * v * v;
+        const double wv = sym_weight(lower.of(i), X.col[b0 + p], (int)i) * v * v;
         if (v != 0.0 && bucket_of(v) >= b) { ++k; sk += wv; }
         else sd += wv;
     }
@@ -1096,11 +1099,11 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_rows(const int64_t *rp, i
 // ---------------------------------------------------------------------------
 // symmetric products: the full matrix from its lower triangle L
 // ---------------------------------------------------------------------------
-// cnt[c] += number of entries L(j, c) with j > c (wave per row j)
+// cnt[c] += number of entries L(j, c) with j > c over the lower rows j (wave per row j)
 template <typename V>
-__global__ void k_sym_count(MatView<V> L, int32_t *cnt) {
+__global__ void k_sym_count(MatView<V> L, LowerRows lower, int32_t *cnt) {
     const int64_t j = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
-    if (j >= L.n) return;
+    if (j >= L.n || !lower.of(j)) return;
     const int64_t b = L.beg[j];
     for (int p = lane_id(); p < L.len[j]; p += kWave) {
         const int c = L.col[b + p];
@@ -1114,21 +1117,22 @@ __global__ void k_add_len(const int32_t *a, const int32_t *b, int64_t n, int32_t
     if (i < n) out[i] = a[i] + b[i];
 }
 
-// Row j of L goes to the front of row j of C; every strictly-lower entry
-// L(j, c) is also appended, unordered, to row c's mirror list in (tcol, tval)
-// at toff[c] + (arrival order).  Wave per row j.
+// Row j of L goes to the front of row j of C; for a lower row j, every
+// strictly-lower entry L(j, c) is also appended, unordered, to row c's mirror
+// list in (tcol, tval) at toff[c] + (arrival order).  Wave per row j.
 template <typename V>
-__global__ void k_sym_place(MatView<V> L, const int64_t *cbeg, int32_t *ccol, V *cval,
-                            const int64_t *toff, int32_t *fill, int32_t *tcol, V *tval) {
+__global__ void k_sym_place(MatView<V> L, LowerRows lower, const int64_t *cbeg, int32_t *ccol,
+                            V *cval, const int64_t *toff, int32_t *fill, int32_t *tcol, V *tval) {
     const int64_t j = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
     if (j >= L.n) return;
+    const bool low = lower.of(j);
     const int64_t b = L.beg[j], o = cbeg[j];
     for (int p = lane_id(); p < L.len[j]; p += kWave) {
         const int c = L.col[b + p];
         const V v = L.val[b + p];
         ccol[o + p] = c;
         cval[o + p] = v;
-        if (c < j) {
+        if (low && c < j) {
             const int64_t w = toff[c] + atomicAdd(&fill[c], 1);
             tcol[w] = (int32_t)j;
             tval[w] = v;
@@ -1285,18 +1289,18 @@ template void launch_transpose_fill<double>(MatView<double>, const int64_t *, in
 template void launch_sort_rows<double>(const int64_t *, int32_t *, double *, int64_t, int *,
                                        hipStream_t);
 template <typename V>
-void launch_sym_count(MatView<V> L, int32_t *cnt, hipStream_t s) {
-    if (L.n > 0) k_sym_count<V><<<blocks_for(L.n, 4), 256, 0, s>>>(L, cnt);
+void launch_sym_count(MatView<V> L, LowerRows lower, int32_t *cnt, hipStream_t s) {
+    if (L.n > 0) k_sym_count<V><<<blocks_for(L.n, 4), 256, 0, s>>>(L, lower, cnt);
 }
 void launch_add_len(const int32_t *a, const int32_t *b, int64_t n, int32_t *out, hipStream_t s) {
     if (n > 0) k_add_len<<<blocks_for(n, 256), 256, 0, s>>>(a, b, n, out);
 }
 template <typename V>
-void launch_sym_place(MatView<V> L, const int64_t *cbeg, int32_t *ccol, V *cval,
+void launch_sym_place(MatView<V> L, LowerRows lower, const int64_t *cbeg, int32_t *ccol, V *cval,
                       const int64_t *toff, int32_t *fill, int32_t *tcol, V *tval, hipStream_t s) {
     if (L.n > 0)
-        k_sym_place<V><<<blocks_for(L.n, 4), 256, 0, s>>>(L, cbeg, ccol, cval, toff, fill, tcol,
-                                                          tval);
+        k_sym_place<V><<<blocks_for(L.n, 4), 256, 0, s>>>(L, lower, cbeg, ccol, cval, toff, fill,
+                                                          tcol, tval);
 }
 template <typename V>
 void launch_sym_rank(int64_t n, const int64_t *cbeg, const int32_t *llen, const int64_t *toff,
@@ -1311,8 +1315,8 @@ void launch_sym_check(MatView<V> X, int *flag, hipStream_t s) {
     if (X.n > 0) k_sym_check<V><<<blocks_for(X.n, 4), 256, 0, s>>>(X, flag);
 }
 #define SFN_SYM_INST(V)                                                                        \
-    template void launch_sym_count<V>(MatView<V>, int32_t *, hipStream_t);                     \
-    template void launch_sym_place<V>(MatView<V>, const int64_t *, int32_t *, V *,             \
+    template void launch_sym_count<V>(MatView<V>, LowerRows, int32_t *, hipStream_t);          \
+    template void launch_sym_place<V>(MatView<V>, LowerRows, const int64_t *, int32_t *, V *,  \
                                       const int64_t *, int32_t *, int32_t *, V *, hipStream_t); \
     template void launch_sym_rank<V>(int64_t, const int64_t *, const int32_t *,                \
                                      const int64_t *, const int32_t *, const int32_t *,        \
@@ -1598,15 +1602,15 @@ template void launch_copy_rows<float>(const int64_t *, int64_t, const int32_t *,
 
 template <typename V>
 void launch_histogram(MatView<V> X, const int64_t *seg_rows, int nseg, int64_t max_seg_rows,
-                      uint64_t *hist, int lower, hipStream_t s) {
+                      uint64_t *hist, LowerRows lower, hipStream_t s) {
     if (nseg <= 0 || max_seg_rows <= 0) return;
     dim3 grid(blocks_for(max_seg_rows, kHistRowsPerBlock), nseg);
     k_histogram<V><<<grid, kHistThreads, 0, s>>>(X, seg_rows, hist, lower);
 }
 template void launch_histogram<double>(MatView<double>, const int64_t *, int, int64_t, uint64_t *,
-                                       int, hipStream_t);
+                                       LowerRows, hipStream_t);
 template void launch_histogram<float>(MatView<float>, const int64_t *, int, int64_t, uint64_t *,
-                                      int, hipStream_t);
+                                      LowerRows, hipStream_t);
 
 void launch_select(const uint64_t *hist, const double *tau, int nseg, int *bstar, hipStream_t s) {
     if (nseg > 0) k_select<<<blocks_for(nseg, 64), 64, 0, s>>>(hist, tau, nseg, bstar);
@@ -1614,15 +1618,15 @@ void launch_select(const uint64_t *hist, const double *tau, int nseg, int *bstar
 
 template <typename V>
 void launch_count_keep(MatView<V> X, const int32_t *row_seg, const int *bstar, int32_t *cnt,
-                       double *sq_keep, double *sq_drop, int lower, hipStream_t s) {
+                       double *sq_keep, double *sq_drop, LowerRows lower, hipStream_t s) {
     if (X.n <= 0) return;
     k_count_keep<V><<<blocks_for(X.n, 4), 256, 0, s>>>(X, row_seg, bstar, cnt, sq_keep, sq_drop,
                                                        lower);
 }
 template void launch_count_keep<double>(MatView<double>, const int32_t *, const int *, int32_t *,
-                                        double *, double *, int, hipStream_t);
+                                        double *, double *, LowerRows, hipStream_t);
 template void launch_count_keep<float>(MatView<float>, const int32_t *, const int *, int32_t *,
-                                       double *, double *, int, hipStream_t);
+                                       double *, double *, LowerRows, hipStream_t);
 
 template <typename V, typename Vo>
 void launch_scatter_keep(MatView<V> X, const int32_t *row_seg, const int *bstar,

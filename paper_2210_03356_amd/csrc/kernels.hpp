@@ -26,9 +26,20 @@ struct MatView {
 };
 
 // Launch geometry of the numeric product for one row class.
+// Rows stored as the lower triangle of a symmetric matrix: all rows (all != 0),
+// the rows flagged in `rows` (when non-null), or none.
+struct LowerRows {
+    int all = 0;
+    const uint8_t *rows = nullptr;
+#ifdef __HIPCC__
+    __host__ __device__ bool of(int64_t i) const { return rows ? rows[i] != 0 : all != 0; }
+#endif
+    bool any() const { return all != 0 || rows != nullptr; }
+};
+
 // Output options of the numeric product.
 struct ProductEpi {
-    int lower = 0;             // store only columns <= the row (symmetric product)
+    LowerRows lower;           // rows that store only columns <= the row (symmetric product)
     int keep_from = 0;         // store only entries whose bucket >= keep_from
     uint64_t *hist = nullptr;  // += bucket histogram of all nonzero entries (weighted
                                //    as launch_histogram with `lower`), kBuckets long
@@ -114,10 +125,10 @@ BinCfg group_config(int group, int value_bytes);
 // their column's mirror list (tcol/tval at toff[c] + arrival order; fill
 // zeroed); rank: each mirror list written ordered after the row's lower part.
 template <typename V>
-void launch_sym_count(MatView<V> L, int32_t *cnt, hipStream_t s);
+void launch_sym_count(MatView<V> L, LowerRows lower, int32_t *cnt, hipStream_t s);
 void launch_add_len(const int32_t *a, const int32_t *b, int64_t n, int32_t *out, hipStream_t s);
 template <typename V>
-void launch_sym_place(MatView<V> L, const int64_t *cbeg, int32_t *ccol, V *cval,
+void launch_sym_place(MatView<V> L, LowerRows lower, const int64_t *cbeg, int32_t *ccol, V *cval,
                       const int64_t *toff, int32_t *fill, int32_t *tcol, V *tval, hipStream_t s);
 template <typename V>
 void launch_sym_rank(int64_t n, const int64_t *cbeg, const int32_t *llen, const int64_t *toff,
@@ -155,14 +166,14 @@ void launch_copy_rows(const int64_t *src_off, int64_t src_base, const int32_t *l
 // diagonal count twice (here and in launch_count_keep's sums of squares).
 template <typename V>
 void launch_histogram(MatView<V> X, const int64_t *seg_rows, int nseg, int64_t max_seg_rows,
-                      uint64_t *hist, int lower, hipStream_t s);
+                      uint64_t *hist, LowerRows lower, hipStream_t s);
 // bstar[s] = cut bucket for budget tau[s] (one thread per segment, ascending
 // FP64 accumulation without contraction).
 void launch_select(const uint64_t *hist, const double *tau, int nseg, int *bstar, hipStream_t s);
 // Survivors per row (bucket >= bstar[seg], value != 0) and their/dropped sums of squares.
 template <typename V>
 void launch_count_keep(MatView<V> X, const int32_t *row_seg, const int *bstar, int32_t *cnt,
-                       double *sq_keep, double *sq_drop, int lower, hipStream_t s);
+                       double *sq_keep, double *sq_drop, LowerRows lower, hipStream_t s);
 template <typename V, typename Vo>
 void launch_scatter_keep(MatView<V> X, const int32_t *row_seg, const int *bstar,
                          const int64_t *dst_ptr, int32_t *dcol, Vo *dval, hipStream_t s);

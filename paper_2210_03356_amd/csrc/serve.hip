@@ -53,6 +53,7 @@ struct Req {
     // a request is deleted once it has left the batch and its ticket was
     // collected (both under the server mutex)
     bool in_batch = false, collected = false;
+    bool sym = false;  // A equals its transpose exactly
 };
 
 double wall() {
@@ -81,8 +82,10 @@ struct sign_server {
     double busy = 0.0;
     // batch (worker thread only)
     std::vector<Req *> active;
-    DMat<double> X, R, Xb, Xn;
+    DMat<double> X, R, Xb, Xn, Xl;
     DevBuf seg_d, row_seg, skip, moves;
+    DevBuf rowsym;         // rows of requests that take the symmetric products
+    bool any_sym = false;
 
     void run();
     void relayout(std::vector<Req *> &admit, Workspace &w);
@@ -119,6 +122,20 @@ void host_validate(const sign_csr *A) {
             if (!std::isfinite(v[p])) throw Error(SIGN_EINVAL, "malformed CSR: non-finite value");
         }
     }
+}
+
+// A equals its transpose exactly (pattern and values); A is a validated CSR
+bool host_is_symmetric(const sign_csr *A) {
+    const int64_t *rp = A->row_ptr;
+    const double *v = (const double *)A->val;
+    for (int64_t i = 0; i < A->n; ++i)
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+            const int32_t j = A->col[p];
+            const int32_t *b = A->col + rp[j], *e = A->col + rp[j + 1];
+            const int32_t *f = std::lower_bound(b, e, (int32_t)i);
+            if (f == e || *f != i || v[rp[j] + (f - b)] != v[p]) return false;
+        }
+    return true;
 }
 
 sign_result *result_from(const Allocator &al, DMat<double> &X) {
@@ -287,6 +304,14 @@ void sign_server::relayout(std::vector<Req *> &admit, Workspace &w) {
     for (Req *r : active) maxr = std::max(maxr, r->n);
     launch_row_segments(seg_d.as<int64_t>(), S, maxr, row_seg.as<int32_t>(), stream);
     launch_fill_u8(skip.as<uint8_t>(), 0, rows, 0, stream);
+    // symmetric requests with unfiltered residuals take the symmetric products
+    rowsym.ensure(std::max<int64_t>(rows, 1));
+    any_sym = false;
+    for (Req *r : active) {
+        const bool sy = r->sym && !r->o.filter_y;
+        launch_fill_u8(rowsym.as<uint8_t>(), r->base, r->base + r->n, sy ? 1 : 0, stream);
+        any_sym = any_sym || sy;
+    }
     // ||X^_1||_F of the new requests
     if (!admit.empty()) {
         row_sumsq(w, X, w.rs3);
@@ -302,7 +327,9 @@ void sign_server::tick(Workspace &w) {
     w.row_skip = skip.as<uint8_t>();
     ++ticks;
     // residuals of all requests: R^ = I - X^ X^
-    product<double>(w, X, X, nullptr, -1.0, 0.0, 1.0, R, nullptr, &w.rs1);
+    const uint8_t *rs = any_sym ? rowsym.as<uint8_t>() : nullptr;
+    product<double>(w, X, X, nullptr, -1.0, 0.0, 1.0, R, nullptr, &w.rs1, false, false, nullptr,
+                    rs);
     const std::vector<double> e2 = seg_sums(w, w.rs1, segd, S);
     std::vector<double> tau(S, 0.0), tau_r(S, 0.0);
     bool any_live = false, any_fy = false;
@@ -347,9 +374,20 @@ void sign_server::tick(Workspace &w) {
         std::swap(R, Xn);
     }
     // updates of all requests: Xbar = X^ + 1/2 X^ R^
-    product<double>(w, X, R, &X, 0.5, 1.0, 0.0, Xb, &w.rs2, nullptr);
+    // (rows of symmetric requests: lower triangles, filtered with the entries
+    // below the diagonal counted twice, then mirrored)
+    product<double>(w, X, R, &X, 0.5, 1.0, 0.0, Xb, &w.rs2, nullptr, false, rs != nullptr,
+                    nullptr, rs);
     const std::vector<double> d2 = seg_sums(w, w.rs2, segd, S);
-    filter_seg(w, Xb, seg_h, segd, row_seg.as<int32_t>(), tau, Xn, &w.rs3, &w.rs4, bstar);
+    LowerRows lower;
+    lower.rows = rs;
+    if (rs) {
+        filter_seg(w, Xb, seg_h, segd, row_seg.as<int32_t>(), tau, Xl, &w.rs3, &w.rs4, bstar,
+                   lower);
+        symmetrize<double>(w, Xl, Xn, lower);
+    } else {
+        filter_seg(w, Xb, seg_h, segd, row_seg.as<int32_t>(), tau, Xn, &w.rs3, &w.rs4, bstar);
+    }
     const std::vector<double> k2 = seg_sums(w, w.rs3, segd, S);
     const std::vector<double> f2 = seg_sums(w, w.rs4, segd, S);
     for (int q = 0; q < S; ++q) {
@@ -439,8 +477,9 @@ int sign_server_create(const sign_server_opts *o, sign_server **s) {
             throw Error(SIGN_EDEVICE, "hipStreamCreate failed");
         }
         sv->al.stream = sv->stream;
-        for (DevBuf *b : {&sv->seg_d, &sv->row_seg, &sv->skip, &sv->moves}) b->bind(&sv->al);
-        for (DMat<double> *m : {&sv->X, &sv->R, &sv->Xb, &sv->Xn}) m->bind(&sv->al);
+        for (DevBuf *b : {&sv->seg_d, &sv->row_seg, &sv->skip, &sv->moves, &sv->rowsym})
+            b->bind(&sv->al);
+        for (DMat<double> *m : {&sv->X, &sv->R, &sv->Xb, &sv->Xn, &sv->Xl}) m->bind(&sv->al);
         sv->worker = std::thread([sv] { sv->run(); });
         *s = sv;
         return SIGN_OK;
@@ -462,6 +501,7 @@ int sign_serve_submit(sign_server *s, const sign_csr *A, const sign_opts *o, uin
         if (o->alloc || o->free) throw Error(SIGN_EINVAL, "serving does not take allocator hooks");
         host_validate(A);
         auto *r = new Req();
+        r->sym = host_is_symmetric(A);
         r->n = A->n;
         r->rp.assign(A->row_ptr, A->row_ptr + A->n + 1);
         r->ci.assign(A->col, A->col + A->nnz);
