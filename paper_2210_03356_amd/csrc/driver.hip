@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <limits>
 
@@ -24,6 +25,7 @@ Workspace::Workspace(Allocator *a, size_t staging_bytes) : al(a), s(a->stream) {
         if (g == 1 || g == 2 || g == 4 || g == 8 || g == 16) row_group = g;
     }
     if (const char *se = std::getenv("SIGNFN_SYMMETRIC")) allow_sym = se[0] != '0';
+    if (const char *pe = std::getenv("SIGNFN_PROGRESS")) progress = pe[0] == '1';
     if (staging_bytes == 0) {
         // a quarter of the memory that is free or idle in the caching pool,
         // capped so that one reservation stays a modest share of HBM
@@ -95,6 +97,14 @@ double Workspace::max_rows(const DevBuf &rows, int64_t n) {
     SFN_HIP(hipMemcpyAsync(seg.get(), h, sizeof(h), hipMemcpyHostToDevice, s));
     launch_seg_max(rows.as<double>(), seg.as<int64_t>(), 1, red.as<double>(), s);
     return read_scalar(red.as<double>(), s);
+}
+
+void Workspace::report(const char *loop, int k, const sign_iter_stats &it) const {
+    if (!progress) return;
+    std::fprintf(stderr, "[signfn] %s k=%d%s e=%.3e nnz_x=%lld nnz_r=%lld nnz_bar=%lld ms=%.1f\n",
+                 loop, k, it.fp32 ? " fp32" : "", it.e, (long long)it.nnz_x, (long long)it.nnz_r,
+                 (long long)it.nnz_bar, it.ms);
+    std::fflush(stderr);
 }
 
 namespace {
@@ -527,6 +537,7 @@ LoopOut nsf_loop(Workspace &w, DMat<V> &X, const LoopParams &p,
         if (stop) {
             it.ms = 1e3 * (now_s() - t0);
             trace.push_back(it);
+            w.report("ns", k, it);
             break;
         }
         const double tau = nsf_budget(e, xf, p.tol, p.c_fixed, p.switch_res);
@@ -563,6 +574,7 @@ LoopOut nsf_loop(Workspace &w, DMat<V> &X, const LoopParams &p,
         it.d = d; it.tau = tau; it.ffro = ff; it.bstar = bstar; it.nnz_bar = nbar;
         it.ms = 1e3 * (now_s() - t0);
         trace.push_back(it);
+        w.report("ns", k, it);
         std::swap(X, Xn);
         xf = xf_new;
         d_prev = d;
@@ -651,6 +663,7 @@ LoopOut nmf_loop(Workspace &w, DMat<double> &X, const LoopParams &p,
         if (stop) {
             it.ms = 1e3 * (now_s() - t0);
             trace.push_back(it);
+            w.report("newton", k, it);
             break;
         }
         // Z ~ X^_k^{-1} by filtered Newton-Schulz inversion Z <- Z + Z (I - X^_k Z)
@@ -695,6 +708,7 @@ LoopOut nmf_loop(Workspace &w, DMat<double> &X, const LoopParams &p,
         it.d = d; it.tau = tau; it.ffro = ff; it.nnz_bar = Xb.nnz; it.bstar = bstar;
         it.ms = 1e3 * (now_s() - t0);
         trace.push_back(it);
+        w.report("newton", k, it);
         std::swap(X, Xn);
         xf = xf_new;
         out.d = d;

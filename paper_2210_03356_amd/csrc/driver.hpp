@@ -23,6 +23,7 @@ struct Workspace {
     const uint8_t *row_skip = nullptr;  // optional row mask for products (serving)
     int row_group = 8;                  // wide rows computed in groups of 1, 2, 4, 8 or 16
     bool allow_sym = true;              // symmetric products from their lower triangle
+    bool progress = false;              // one stderr line per finished iteration
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     // accumulated product statistics, in total and per row class (kernel tile)
     struct ClassStat {
@@ -46,6 +47,8 @@ struct Workspace {
     DevBuf whole, sums;   // {0, n} segment for whole-matrix sums, their results
     int64_t whole_n = -1;
     double max_rows(const DevBuf &rows, int64_t n);
+    // the progress line of an iteration that just ended (when progress is set)
+    void report(const char *loop, int k, const sign_iter_stats &it) const;
 };
 
 // C = diag*I + coef*A*B + dcoef*D (D may be null); C becomes compact CSR.
