@@ -106,7 +106,8 @@ typedef struct {
     int iters;           /* updates performed */
     int stagnated;       /* 1 if stopped because e_k stopped halving below 1e-8 */
     double scale;        /* c with X_1 = A/c */
-    double res_fro;      /* e of the returned iterate, ||I - X^2||_F */
+    double res_fro;      /* e of the returned iterate, ||I - X^2||_F (or the certified
+                            upper bound of it, see sign_iter_stats.e_bound) */
     double step_fro;     /* last ||Xbar_{k+1} - X^_k||_F */
     int64_t nnz;         /* nonzeros of the result */
     double seconds;      /* wall time of the call */
@@ -141,6 +142,11 @@ typedef struct {
     int64_t nnz_bar;     /* nnz(Xbar_{k+1}) */
     int bstar;           /* threshold bucket of X^_{k+1} */
     int fp32;            /* 1 if this step ran in FP32 */
+    int e_bound;         /* 1: e is a certified upper bound of ||I - X^_k^2||_F,
+                            ||I - Xt^2||_F + 2 ||Xt||_2 delta + delta^2 from a copy Xt
+                            of X^_k thinned by delta <= tol/16 in Frobenius norm
+                            (tried on the last step only, where Lemma 2.1.1 predicts
+                            convergence; nnz_r is then that of I - Xt^2) */
     double ms;           /* wall time of the step */
 } sign_iter_stats;
 

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <limits>
@@ -101,9 +102,21 @@ double Workspace::max_rows(const DevBuf &rows, int64_t n) {
 
 void Workspace::report(const char *loop, int k, const sign_iter_stats &it) const {
     if (!progress) return;
-    std::fprintf(stderr, "[signfn] %s k=%d%s e=%.3e nnz_x=%lld nnz_r=%lld nnz_bar=%lld ms=%.1f\n",
-                 loop, k, it.fp32 ? " fp32" : "", it.e, (long long)it.nnz_x, (long long)it.nnz_r,
+    std::fprintf(stderr, "[signfn] %s k=%d%s e%s%.3e nnz_x=%lld nnz_r=%lld nnz_bar=%lld ms=%.1f\n",
+                 loop, k, it.fp32 ? " fp32" : "", it.e_bound ? "<=" : "=", it.e,
+                 (long long)it.nnz_x, (long long)it.nnz_r,
                  (long long)it.nnz_bar, it.ms);
+    std::fflush(stderr);
+}
+
+void Workspace::note(const char *fmt, ...) const {
+    if (!progress) return;
+    std::fputs("[signfn] ", stderr);
+    va_list ap;
+    va_start(ap, fmt);
+    std::vfprintf(stderr, fmt, ap);
+    va_end(ap);
+    std::fputc('\n', stderr);
     std::fflush(stderr);
 }
 
@@ -496,6 +509,41 @@ double nmf_budget(double e, double xfro, double zfro, double tol, double c_fixed
     return e * e / (xfro + zfro);
 }
 
+namespace {
+// ||X||_1 * ||X||_inf of a compact FP64 matrix
+double norm_one_inf(Workspace &w, const DMat<double> &X) {
+    const int64_t n = X.n;
+    w.rs4.ensure(sizeof(double) * n);
+    SFN_HIP(hipMemsetAsync(w.rs4.get(), 0, sizeof(double) * n, w.s));
+    launch_col_abs_sum<double>(X.view(), w.rs4.as<double>(), w.s);
+    const double one = w.max_rows(w.rs4, n);
+    launch_row_abs_sum(X.begp(), X.valp(), 0, n, w.rs4.as<double>(), w.s);
+    const double inf = w.max_rows(w.rs4, n);
+    return one * inf;
+}
+
+// Upper bound of ||I - X^2||_F from a thinned copy Xt = X - D (||D||_F = delta,
+// D the entries of a filter cut with budget tau_c):
+//   I - X^2 = (I - Xt^2) - (Xt D + D Xt) - D^2,
+//   ||I - X^2||_F <= ||I - Xt^2||_F + 2 ||Xt||_2 delta + delta^2,
+// with ||Xt||_2 <= sqrt(||X||_1 ||X||_inf) (dropping entries lowers both), and
+// for an exactly symmetric Xt also ||Xt||_2^2 = ||Xt^2||_2 <= 1 + ||I - Xt^2||_F.
+// R receives I - Xt^2.
+double thinned_residual_bound(Workspace &w, const DMat<double> &X, bool sym, double tol,
+                              DMat<double> &Xt, DMat<double> &R) {
+    const int64_t n = X.n;
+    const double s_one_inf = sym ? 1.0 : std::sqrt(norm_one_inf(w, X));
+    const double tau_c = tol / (16.0 * s_one_inf);
+    filter<double, double>(w, X, tau_c, Xt, nullptr, &w.rs4);
+    product<double>(w, Xt, Xt, nullptr, -1.0, 0.0, 1.0, R, nullptr, &w.rs1, sym);
+    const std::vector<double> sums = w.sum_rows_many({&w.rs1, &w.rs4}, n);
+    const double et = std::sqrt(sums[0]);
+    const double delta = std::sqrt(sums[1]);
+    const double s2 = sym ? std::sqrt(1.0 + et) : s_one_inf;
+    return et + 2.0 * s2 * delta + delta * delta;
+}
+}  // namespace
+
 template <typename V>
 LoopOut nsf_loop(Workspace &w, DMat<V> &X, const LoopParams &p,
                  std::vector<sign_iter_stats> &trace) {
@@ -506,19 +554,48 @@ LoopOut nsf_loop(Workspace &w, DMat<V> &X, const LoopParams &p,
     row_sumsq(w, X, w.rs3);
     double xf = std::sqrt(w.sum_rows(w.rs3, n));
     double d_prev = std::numeric_limits<double>::infinity();
+    double ff_prev = std::numeric_limits<double>::infinity();
     int n_up = 0, n_flat = 0;
     std::vector<double> es;
     for (int k = 1;; ++k) {
         const double t0 = now_s();
+        if (!p.check_last && k - 1 >= p.max_iter) {
+            // the caller continues from X^_k and does not use its residual
+            out.status = SIGN_ENOCONV;
+            out.iters = k - 1;
+            out.xfro = xf;
+            break;
+        }
         // residual of the current iterate: R^_k = I - X^_k^2
         // symmetric products keep X^ exactly symmetric only when R^ stays the
         // exact polynomial I - X^2 (R^ not filtered): then X^R^ is symmetric too
         const bool sym = p.sym && !p.filter_y;
-        product<V>(w, X, X, nullptr, -1.0, 0.0, 1.0, R, nullptr, &w.rs1, sym);
-        const double e = std::sqrt(w.sum_rows(w.rs1, n));
+        // Where Lemma 2.1.1 (R_{k+1} = 3/4 R_k^2 + 1/4 R_k^3) and the last cut
+        // predict e_k far below tol, e_k <= tol is first certified from a thinned
+        // copy of X^_k, whose square costs a fraction of X^_k^2; the full residual
+        // is formed only if that bound does not reach tol.
+        double e = -1.0;
+        int e_bound = 0;
+        if constexpr (sizeof(V) == 8) {
+            if (p.stop_rule == 0 && k >= 2) {
+                const double ep = es.back();
+                const double pred = 0.75 * ep * ep * (1.0 + ep / 3.0) + 2.5 * ff_prev;
+                if (pred <= 0.25 * p.tol) {
+                    DMat<double> Xt;
+                    Xt.bind(w.al);
+                    const double b = thinned_residual_bound(w, X, sym, p.tol, Xt, R);
+                    if (b <= p.tol) { e = b; e_bound = 1; }
+                }
+            }
+        }
+        if (!e_bound) {
+            product<V>(w, X, X, nullptr, -1.0, 0.0, 1.0, R, nullptr, &w.rs1, sym);
+            e = std::sqrt(w.sum_rows(w.rs1, n));
+        }
         es.push_back(e);
         sign_iter_stats it{};
         it.e = e; it.xfro = xf; it.nnz_x = X.nnz; it.nnz_r = R.nnz; it.fp32 = p.fp32;
+        it.e_bound = e_bound;
         out.iters = k - 1; out.e = e; out.xfro = xf;
         const bool conv = (p.stop_rule == 1) ? (d_prev < p.tol) : (e <= p.tol);
         bool stop = conv;
@@ -578,6 +655,7 @@ LoopOut nsf_loop(Workspace &w, DMat<V> &X, const LoopParams &p,
         std::swap(X, Xn);
         xf = xf_new;
         d_prev = d;
+        ff_prev = ff;
         out.d = d;
     }
     return out;
@@ -607,19 +685,6 @@ void transpose(Workspace &w, const DMat<double> &X, DMat<double> &Out) {
     Out.nnz = X.nnz;
 }
 
-namespace {
-// ||X||_1 * ||X||_inf of a compact FP64 matrix
-double norm_one_inf(Workspace &w, const DMat<double> &X) {
-    const int64_t n = X.n;
-    w.rs4.ensure(sizeof(double) * n);
-    SFN_HIP(hipMemsetAsync(w.rs4.get(), 0, sizeof(double) * n, w.s));
-    launch_col_abs_sum<double>(X.view(), w.rs4.as<double>(), w.s);
-    const double one = w.max_rows(w.rs4, n);
-    launch_row_abs_sum(X.begp(), X.valp(), 0, n, w.rs4.as<double>(), w.s);
-    const double inf = w.max_rows(w.rs4, n);
-    return one * inf;
-}
-}  // namespace
 
 LoopOut nmf_loop(Workspace &w, DMat<double> &X, const LoopParams &p,
                  std::vector<sign_iter_stats> &trace, int &inner_steps) {

@@ -49,6 +49,8 @@ struct Workspace {
     double max_rows(const DevBuf &rows, int64_t n);
     // the progress line of an iteration that just ended (when progress is set)
     void report(const char *loop, int k, const sign_iter_stats &it) const;
+    // a free-form progress line (when progress is set)
+    void note(const char *fmt, ...) const __attribute__((format(printf, 2, 3)));
 };
 
 // C = diag*I + coef*A*B + dcoef*D (D may be null); C becomes compact CSR.
@@ -120,6 +122,9 @@ struct LoopParams {
     int stop_rule, max_iter, filter_y;
     int fp32;     // recorded in the trace
     int sym = 0;  // the iterate is symmetric: symmetric products from their lower triangle
+    // 0: after max_iter updates, return without forming the last iterate's
+    // residual (a caller that continues from it)
+    int check_last = 1;
 };
 
 struct LoopOut {

@@ -61,7 +61,7 @@ class sign_iter_stats(C.Structure):
     _fields_ = [("e", C.c_double), ("d", C.c_double), ("tau", C.c_double),
                 ("xfro", C.c_double), ("ffro", C.c_double), ("nnz_x", C.c_int64),
                 ("nnz_r", C.c_int64), ("nnz_bar", C.c_int64), ("bstar", C.c_int),
-                ("fp32", C.c_int), ("ms", C.c_double)]
+                ("fp32", C.c_int), ("e_bound", C.c_int), ("ms", C.c_double)]
 
 
 class sign_server_opts(C.Structure):

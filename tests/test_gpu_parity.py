@@ -247,6 +247,26 @@ def test_trace_records_budget_and_filter(sf):
     assert np.allclose(e_gpu[big], e_ref[big], rtol=1e-9)
 
 
+
+@pytest.mark.parametrize("name", ["lap2d_48", "convdiff_30", "lap3d_9", "lap2d_32_filter_y"])
+def test_certified_last_residual(sf, name):
+    """The last residual certified from a thinned copy of the iterate is a true
+    bound: the residual of the returned matrix, formed here with scipy in FP64, lies
+    below it, and the bound itself is at most tol."""
+    make, kw = CASES[name]
+    A = make()
+    r = sf.sign_ns(_dev(sf, A), sf.default_opts(**kw))
+    assert r.status == "OK"
+    tr = r.trace()
+    assert not any(t["e_bound"] for t in tr[:-1])
+    last = tr[-1]
+    if name in ("lap2d_48", "convdiff_30"):
+        assert last["e_bound"] == 1
+    X = r.to_scipy()
+    e_full = sp.linalg.norm(sp.identity(A.n, format="csr") - X @ X)
+    assert e_full <= last["e"] <= kw["tol"], (e_full, last["e"])
+    assert r.stats()["res_fro"] == last["e"]
+
 NMF_CASES = {
     "lap2d_10": (lambda: W.laplacian_2d(10, jitter=0.05, seed=2, m=8.0), {}),
     "lap2d_24": (lambda: W.laplacian_2d(24, jitter=0.05, seed=2, m=8.0), {}),

@@ -385,3 +385,42 @@ def test_local_sign_row_similar_matches_schur():
         assert np.abs(r1 - r2).max() <= 1e-13
     with pytest.raises(ValueError):
         cf.local_sign_row_similar(A, 7, 4, np.ones(A.n))
+
+
+# ---------------------------------------------------------------------------
+# the certified last residual: with Xt = X - D thinned by a filter cut,
+# ||I - X^2||_F <= ||I - Xt^2||_F + 2 ||Xt||_2 ||D||_F + ||D||_F^2,
+# ||Xt||_2 <= sqrt(||X||_1 ||X||_inf), and sqrt(1 + ||I - Xt^2||_F) when Xt is
+# symmetric -- checked on oracle iterates against dense norms
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("make,sym", [
+    (lambda: W.laplacian_2d(20, jitter=0.05, seed=2, m=8.0), True),
+    (lambda: W.convdiff_2d(14, beta=0.5, sigma=4.0, m=8.0), False),
+])
+def test_thinned_residual_bound(oracle_lib, make, sym):
+    from oracle import core
+    A = make()
+    for iters in (3, 4, 100):
+        r = core.nsf(A, tol=1e-12, max_iter=iters)
+        X = _dense(r)
+        if sym:
+            X = 0.5 * (X + X.T)  # exactly symmetric, as the GPU's symmetric iterates
+        I = np.eye(A.n)
+        e = np.linalg.norm(I - X @ X)
+        one_inf = math.sqrt(np.abs(X).sum(0).max() * np.abs(X).sum(1).max())
+        for tau in (1e-3, 1e-8, 1e-13):
+            _, keep, dsq = core.filter_values(X.ravel(), tau)
+            Xt = np.where(keep.reshape(X.shape), X, 0.0)
+            delta = math.sqrt(dsq)
+            assert delta <= tau
+            assert abs(np.linalg.norm(X - Xt) - delta) <= 1e-12 * max(delta, 1e-300) + 1e-300
+            et = np.linalg.norm(I - Xt @ Xt)
+            s2 = np.linalg.norm(Xt, 2)
+            assert s2 <= one_inf * (1 + 1e-12)
+            if sym:
+                assert np.array_equal(Xt, Xt.T)
+                assert s2 <= math.sqrt(1.0 + et) * (1 + 1e-12)
+                s = math.sqrt(1.0 + et)
+            else:
+                s = one_inf
+            assert e <= (et + 2.0 * s * delta + delta * delta) * (1 + 1e-9) + 1e-14
