@@ -81,9 +81,10 @@ typedef struct {
     double switch_res;   /* [1e-6] residual below which the adaptive budget applies
                             (eq. 1.18 for NSF, eq. 1.13 for NMF; Section 4) */
     int max_iter;        /* [100] at most this many updates */
-    int precision;       /* [0] 0: FP64 throughout.  1: FP32 values and FP32 accumulation in
-                            the products, FP64 norms/scaling/thresholds, then FP64 refinement
-                            and polishing (sign_ns only) */
+    int precision;       /* [0] 0: FP64 throughout.  1: FP32 values in the bulk products
+                            (FP32 x FP32 is exact in FP64, and the sums are accumulated in
+                            FP64 before the FP32 store), FP64 norms/scaling/thresholds, then
+                            FP64 refinement and polishing (sign_ns only) */
     int polish_steps;    /* [2] FP64 Newton-Schulz steps after an FP32 phase (precision 1) */
     int refine_steps;    /* [6] commutator-refinement sweeps between the polish steps
                             (precision 1; 0 disables) */
@@ -145,8 +146,9 @@ typedef struct {
     int e_bound;         /* 1: e is a certified upper bound of ||I - X^_k^2||_F,
                             ||I - Xt^2||_F + 2 ||Xt||_2 delta + delta^2 from a copy Xt
                             of X^_k thinned by delta <= tol/16 in Frobenius norm
-                            (tried on the last step only, where Lemma 2.1.1 predicts
-                            convergence; nnz_r is then that of I - Xt^2) */
+                            (tried where Lemma 2.1.1 predicts convergence, and on the
+                            first residual after the mixed mode's refinement; nnz_r is
+                            then that of I - Xt^2) */
     double ms;           /* wall time of the step */
 } sign_iter_stats;
 

@@ -143,8 +143,12 @@ LoopOut mixed_precision(Workspace &w, const sign_csr *A, double c, const sign_op
     int iters = l32.iters;
     LoopOut lo;
     if (o.polish_steps > 0) {
+        // one update; the refinement below starts from its result, and the
+        // remaining polish forms that residual again, so it is not formed here
         p64.max_iter = 1;
+        p64.check_last = 0;
         lo = nsf_loop<double>(w, X, p64, trace);
+        p64.check_last = 1;
         iters += lo.iters;
     }
     if (o.refine_steps > 0) {
@@ -154,6 +158,7 @@ LoopOut mixed_precision(Workspace &w, const sign_csr *A, double c, const sign_op
         row_sumsq(w, As, w.rs3);
         const double af = std::sqrt(w.sum_rows(w.rs3, n));
         for (int sweep = 0; sweep < o.refine_steps; ++sweep) {
+            const double t0 = now_s();
             product<double>(w, As, X, nullptr, 1.0, 0.0, 0.0, P, nullptr, nullptr);
             // C = A X - X A
             product<double>(w, X, As, &P, -1.0, 1.0, 0.0, Cm, nullptr, &w.rs1);
@@ -166,10 +171,20 @@ LoopOut mixed_precision(Workspace &w, const sign_csr *A, double c, const sign_op
             if (sweep == 0) comm_rel = cn / (xf * af);
             if (!(mean_abs > 0.0)) break;
             // estimated relative error of X: ||E|| ~ ||C|| / (2 mean|lambda|)
-            if (cn / (2.0 * mean_abs * xf) < 1e-11) break;
+            const double est = cn / (2.0 * mean_abs * xf);
+            // (an order below the 1e-8 accuracy the mixed mode is held to; the
+            // estimate is within the condition of the spectrum's two halves,
+            // max|lambda| / min|lambda|, of the error that NS cannot see)
+            if (est < 1e-9) {
+                w.note("refine sweep %d: estimated error %.3e, done (%.1f ms)", sweep, est,
+                       1e3 * (now_s() - t0));
+                break;
+            }
             const double omega = 1.0 / (2.0 * mean_abs);
             product<double>(w, X, Cm, &X, -omega, 1.0, 0.0, Xb, nullptr, nullptr);
             filter<double, double>(w, Xb, o.c_fixed * o.tol, Xn, nullptr, nullptr);
+            w.note("refine sweep %d: estimated error %.3e, nnz C %lld, X %lld (%.1f ms)", sweep,
+                   est, (long long)Cm.nnz, (long long)Xn.nnz, 1e3 * (now_s() - t0));
             std::swap(X, Xn);
             p64.sym = 0;  // X - w X [A, X] is not exactly symmetric
         }
@@ -178,6 +193,7 @@ LoopOut mixed_precision(Workspace &w, const sign_csr *A, double c, const sign_op
         // refinement left X slightly unsymmetric; the sign of a symmetric A is
         // symmetric, so continue from (X + X^T)/2 (never farther from it) and
         // keep the remaining steps on symmetric products
+        const double t0 = now_s();
         DMat<double> Xt, I, Xs;
         for (DMat<double> *m : {&Xt, &I, &Xs}) m->bind(w.al);
         transpose(w, X, Xt);
@@ -188,8 +204,12 @@ LoopOut mixed_precision(Workspace &w, const sign_csr *A, double c, const sign_op
         product<double>(w, I, Xt, &X, 0.5, 0.5, 0.0, Xs, nullptr, nullptr);
         std::swap(X, Xs);
         p64.sym = 1;
+        w.note("symmetric projection: nnz %lld (%.1f ms)", (long long)X.nnz, 1e3 * (now_s() - t0));
     }
     p64.max_iter = std::max(1, o.polish_steps - 1);
+    // after refinement the iterate is usually converged already: its residual
+    // is certified from a thinned copy first
+    p64.cert_first = o.refine_steps > 0;
     const LoopOut l2 = nsf_loop<double>(w, X, p64, trace);
     LoopOut out = l2;
     out.iters = iters + l2.iters;

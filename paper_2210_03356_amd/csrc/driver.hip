@@ -175,6 +175,8 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
     w.products += tot[1];
     ProductEpi epi;
     epi.lower = lower;
+    // B with a few entries per row (e.g. B = A): lane-per-slot accumulation
+    epi.short_b = B.nnz <= 16 * std::max<int64_t>(B.n, 1);
     if (ff) {
         // the filter's histogram comes out of the product, and entries that no
         // cut can keep are not stored (the candidates number at most total_cap,
@@ -573,19 +575,22 @@ LoopOut nsf_loop(Workspace &w, DMat<V> &X, const LoopParams &p,
         // Where Lemma 2.1.1 (R_{k+1} = 3/4 R_k^2 + 1/4 R_k^3) and the last cut
         // predict e_k far below tol, e_k <= tol is first certified from a thinned
         // copy of X^_k, whose square costs a fraction of X^_k^2; the full residual
-        // is formed only if that bound does not reach tol.
+        // is formed only if that bound does not reach tol.  (cert_first: the
+        // caller expects the first iterate to be converged already.)
         double e = -1.0;
         int e_bound = 0;
         if constexpr (sizeof(V) == 8) {
+            bool try_cert = p.stop_rule == 0 && k == 1 && p.cert_first;
             if (p.stop_rule == 0 && k >= 2) {
                 const double ep = es.back();
                 const double pred = 0.75 * ep * ep * (1.0 + ep / 3.0) + 2.5 * ff_prev;
-                if (pred <= 0.25 * p.tol) {
-                    DMat<double> Xt;
-                    Xt.bind(w.al);
-                    const double b = thinned_residual_bound(w, X, sym, p.tol, Xt, R);
-                    if (b <= p.tol) { e = b; e_bound = 1; }
-                }
+                try_cert = pred <= 0.25 * p.tol;
+            }
+            if (try_cert) {
+                DMat<double> Xt;
+                Xt.bind(w.al);
+                const double b = thinned_residual_bound(w, X, sym, p.tol, Xt, R);
+                if (b <= p.tol) { e = b; e_bound = 1; }
             }
         }
         if (!e_bound) {

@@ -125,6 +125,8 @@ struct LoopParams {
     // 0: after max_iter updates, return without forming the last iterate's
     // residual (a caller that continues from it)
     int check_last = 1;
+    // 1: certify the first residual from a thinned copy too (FP64; see nsf_loop)
+    int cert_first = 0;
 };
 
 struct LoopOut {

@@ -593,8 +593,9 @@ __device__ __forceinline__ int group_accumulate(double (*acc)[T], const int (&c)
 // row, whose own A entries are the slots; R > 1: the merged A list of the
 // group from k_merge_group).  The rows' columns are swept in windows of T
 // consecutive columns held as dense LDS accumulators (R x T values, native
-// ds_add).  Each wave takes 64 slots at a time; lane q holds slot q's
-// B-row descriptor and coefficients, broadcast with readlane.  A slot's B row
+// ds_add).  Each wave takes 64 slots at a time (fewer when the list is short,
+// so that every wave gets some); lane q holds slot q's B-row descriptor and
+// coefficients, broadcast with readlane.  A slot's B row
 // is streamed in chunks of U x 64 entries (coalesced col/val loads); B rows are
 // sorted, so the entries inside the window are a prefix of what is loaded, and
 // the sweep of a B row stops at the first chunk that runs past the window.
@@ -604,6 +605,8 @@ __device__ __forceinline__ int group_accumulate(double (*acc)[T], const int (&c)
 // (cnext), so each B entry is read once per group.  With R > 1 every gathered
 // chunk feeds the windows of all R rows -- neighbouring rows of these matrices
 // reference almost the same rows of B, so the group pays its B bytes once.
+// When B's rows are short (a few entries, e.g. B = A), each lane instead walks
+// its own slot's row, a wave adding 64 slots at once.
 // Finished windows get the D row and the diagonal added in LDS and are written
 // in column order (per-wave ballot compaction, zeros dropped); per-row sums of
 // squares of the product and of the output come out in a fixed order.
@@ -649,6 +652,9 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
     const int ml = R == 1 ? A.len[i] : mlen[i];
     const bool multi = hi - lo > T;
     const bool has_d = D.len != nullptr;
+    // slots per wave and batch: 64, or fewer so that a short slot list still
+    // spreads over every wave
+    const int step = ml >= NW * kWave ? kWave : max(1, (ml + NW - 1) / NW);
 
     for (int q = threadIdx.x; q < 2 * R * NW; q += NT) (&wsum[0][0])[q] = 0.0;
     if (threadIdx.x < R) wrt[threadIdx.x] = 0;
@@ -664,14 +670,15 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
             for (int r = 0; r < R; ++r) acc[r][s] = 0.0;
         __syncthreads();
 
-        for (int t0 = wave * kWave; t0 < ml; t0 += NW * kWave) {
+        for (int t0 = wave * step; t0 < ml; t0 += NW * step) {
             const int t = t0 + lane;
+            const bool own = lane < step && t < ml;
             int bl = 0, cur = 0, nc = INT_MIN, msk = 0;
             int64_t bb = 0;
             V a[R];  // this lane's slot: coefficient of each row of the group (0 if absent)
 #pragma unroll
             for (int r = 0; r < R; ++r) a[r] = V(0);
-            if (t < ml) {
+            if (own) {
                 const int64_t pa = mbeg + t;
                 int k;
                 if constexpr (R == 1) {  // a single row: its own entries are the slots
@@ -692,8 +699,27 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
                 bl = B.len[k];
                 if (!first) { cur = cursor[pa]; nc = cnext[pa]; }
             }
+            if (epi.short_b) {
+                // short B rows: every lane walks the in-window part of its own
+                // slot's row, so a wave adds up to 64 slots at once
+                if (own && cur < bl && nc < whi) {
+                    int p = cur, nx = INT_MAX;
+                    for (; p < bl; ++p) {
+                        const int col = B.col[bb + p];
+                        if (col >= whi) { nx = col; break; }
+                        const double bvv = (double)B.val[bb + p];
+#pragma unroll
+                        for (int r = 0; r < R; ++r)
+                            if ((msk >> r) & 1) atomicAdd(&acc[r][col - wlo], (double)a[r] * bvv);
+                    }
+                    cur = p;
+                    nc = nx;
+                }
+                if (multi && own) { cursor[mbeg + t] = cur; cnext[mbeg + t] = nc; }
+                continue;
+            }
             // slots with B entries left in this window; the others cost nothing
-            uint64_t act = __ballot(t < ml && cur < bl && nc < whi);
+            uint64_t act = __ballot(own && cur < bl && nc < whi);
             if (act) {
                 int c[U], cn[U];
                 V bv[U], bn[U];
@@ -741,7 +767,7 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
                     for (int u = 0; u < U; ++u) { c[u] = cn[u]; bv[u] = bn[u]; }
                 }
             }
-            if (multi && t < ml) { cursor[mbeg + t] = cur; cnext[mbeg + t] = nc; }
+            if (multi && own) { cursor[mbeg + t] = cur; cnext[mbeg + t] = nc; }
         }
         __syncthreads();
 

@@ -45,6 +45,7 @@ struct ProductEpi {
                                //    as launch_histogram with `lower`), kBuckets long
     double *sq_pre = nullptr;  // [row] sum of squares of the entries not stored
                                //    because of keep_from (weighted likewise)
+    int short_b = 0;           // B's rows are short: each lane walks its own slot's row
 };
 
 struct BinCfg {

@@ -365,7 +365,9 @@ def test_row_groups_match_oracle(sf, monkeypatch, group):
     monkeypatch.setenv("SIGNFN_ROW_GROUP", str(group))
     A = _wide_rows_matrix()
     R = W.random_sparse(A.n, mean_row=6, seed=9, powerlaw=False)
-    for left, right in ((A, A), (A, R)):
+    # (A, R): B rows short (lane-per-slot accumulation); (R, A): a handful of
+    # slots per row, spread over the waves one or a few each
+    for left, right in ((A, A), (A, R), (R, A)):
         r = _check_product(sf, left, right)
         if left is A:
             st = r.stats()
