@@ -489,6 +489,30 @@ std::vector<double> seg_sums(Workspace &w, const DevBuf &rows, const int64_t *se
     return h;
 }
 
+std::vector<double> seg_maxs(Workspace &w, const DevBuf &rows, const int64_t *seg_d, int nseg) {
+    std::vector<double> h(nseg);
+    if (nseg == 0) return h;
+    w.red.ensure(sizeof(double) * nseg);
+    launch_seg_max(rows.as<double>(), seg_d, nseg, w.red.as<double>(), w.s);
+    SFN_HIP(hipMemcpyAsync(h.data(), w.red.get(), sizeof(double) * nseg, hipMemcpyDeviceToHost,
+                           w.s));
+    SFN_HIP(hipStreamSynchronize(w.s));
+    return h;
+}
+
+std::vector<double> seg_norm_one_inf(Workspace &w, const DMat<double> &X, const int64_t *seg_d,
+                                     int nseg) {
+    const int64_t n = X.n;
+    w.rs4.ensure(sizeof(double) * std::max<int64_t>(n, 1));
+    SFN_HIP(hipMemsetAsync(w.rs4.get(), 0, sizeof(double) * n, w.s));
+    launch_col_abs_sum<double>(X.view(), w.rs4.as<double>(), w.s);
+    const std::vector<double> one = seg_maxs(w, w.rs4, seg_d, nseg);
+    launch_row_abs_sum(X.begp(), X.valp(), 0, n, w.rs4.as<double>(), w.s);
+    std::vector<double> inf = seg_maxs(w, w.rs4, seg_d, nseg);
+    for (int q = 0; q < nseg; ++q) inf[q] *= one[q];
+    return inf;
+}
+
 template <typename V>
 void row_sumsq(Workspace &w, const DMat<V> &X, DevBuf &rows) {
     const int64_t n = X.n;

@@ -107,6 +107,11 @@ void filter_seg(Workspace &w, const DMat<double> &In, const std::vector<int64_t>
 
 // Per-segment sums of a per-row FP64 array (deterministic).
 std::vector<double> seg_sums(Workspace &w, const DevBuf &rows, const int64_t *seg_d, int nseg);
+// Per-segment maxima of a per-row FP64 array.
+std::vector<double> seg_maxs(Workspace &w, const DevBuf &rows, const int64_t *seg_d, int nseg);
+// ||X_s||_1 * ||X_s||_inf of every diagonal block s of a block-diagonal FP64 matrix.
+std::vector<double> seg_norm_one_inf(Workspace &w, const DMat<double> &X, const int64_t *seg_d,
+                                     int nseg);
 
 // ||X||_F^2 per row into rows (via the survivor pass with an all-keeping cut).
 template <typename V>

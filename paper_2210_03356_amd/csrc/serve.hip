@@ -45,6 +45,8 @@ struct Req {
     double c = 1.0;
     std::vector<double> es;
     double xf = 0.0, d_prev = std::numeric_limits<double>::infinity();
+    double ff_prev = std::numeric_limits<double>::infinity();  // ||F|| of the last cut
+    bool no_cert = false;  // a certification of its residual failed: form it in full
     int n_up = 0, n_flat = 0, stagnated = 0, updates = 0;
     int status = SIGN_PENDING;
     std::string err;
@@ -82,7 +84,7 @@ struct sign_server {
     double busy = 0.0;
     // batch (worker thread only)
     std::vector<Req *> active;
-    DMat<double> X, R, Xb, Xn, Xl;
+    DMat<double> X, R, Xb, Xn, Xl, Xt;
     DevBuf seg_d, row_seg, skip, moves;
     DevBuf rowsym;         // rows of requests that take the symmetric products
     bool any_sym = false;
@@ -326,11 +328,69 @@ void sign_server::tick(Workspace &w) {
     const int64_t *segd = seg_d.as<int64_t>();
     w.row_skip = skip.as<uint8_t>();
     ++ticks;
-    // residuals of all requests: R^ = I - X^ X^
+    std::vector<int64_t> seg_h(S + 1, 0);
+    for (int q = 0; q < S; ++q) seg_h[q + 1] = seg_h[q] + active[q]->n;
+    // Requests whose residual Lemma 2.1.1 and their last cut predict far below
+    // tol have it certified from a copy thinned by delta (as sign_ns does):
+    // e <= ||I - Xt^2|| + 2 ||Xt||_2 delta + delta^2.  The other requests get a
+    // zero budget, which keeps their rows whole, so one product serves both.
+    std::vector<char> pred(S, 0);
+    std::vector<double> s_one_inf(S, 1.0), delta2(S, 0.0);
+    bool any_pred = false, any_pred_nonsym = false;
+    for (int q = 0; q < S; ++q) {
+        Req *r = active[q];
+        if (!r->live || r->no_cert || r->o.stop_rule != 0 || r->es.empty()) continue;
+        const double ep = r->es.back();
+        if (0.75 * ep * ep * (1.0 + ep / 3.0) + 2.5 * r->ff_prev <= 0.25 * r->o.tol) {
+            pred[q] = 1;
+            any_pred = true;
+            if (!(r->sym && !r->o.filter_y)) any_pred_nonsym = true;
+        }
+    }
     const uint8_t *rs = any_sym ? rowsym.as<uint8_t>() : nullptr;
-    product<double>(w, X, X, nullptr, -1.0, 0.0, 1.0, R, nullptr, &w.rs1, false, false, nullptr,
-                    rs);
-    const std::vector<double> e2 = seg_sums(w, w.rs1, segd, S);
+    if (any_pred) {
+        if (any_pred_nonsym) {
+            const std::vector<double> p = seg_norm_one_inf(w, X, segd, S);
+            for (int q = 0; q < S; ++q) s_one_inf[q] = std::sqrt(p[q]);
+        }
+        std::vector<double> tc(S, 0.0);
+        for (int q = 0; q < S; ++q) {
+            if (!pred[q]) continue;
+            const bool sy = active[q]->sym && !active[q]->o.filter_y;
+            tc[q] = active[q]->o.tol / (16.0 * (sy ? 1.0 : s_one_inf[q]));
+        }
+        std::vector<int> bs;
+        filter_seg(w, X, seg_h, segd, row_seg.as<int32_t>(), tc, Xt, nullptr, &w.rs4, bs);
+        delta2 = seg_sums(w, w.rs4, segd, S);
+    }
+    // residuals of all requests: R^ = I - X^ X^ (thinned rows for the predicted)
+    product<double>(w, any_pred ? Xt : X, any_pred ? Xt : X, nullptr, -1.0, 0.0, 1.0, R, nullptr,
+                    &w.rs1, false, false, nullptr, rs);
+    std::vector<double> e2 = seg_sums(w, w.rs1, segd, S);
+    std::vector<char> bound(S, 0);
+    if (any_pred) {
+        bool failed = false;
+        for (int q = 0; q < S; ++q) {
+            if (!pred[q]) continue;
+            const bool sy = active[q]->sym && !active[q]->o.filter_y;
+            const double et = std::sqrt(e2[q]), dl = std::sqrt(delta2[q]);
+            const double b = et + 2.0 * (sy ? std::sqrt(1.0 + et) : s_one_inf[q]) * dl + dl * dl;
+            if (b <= active[q]->o.tol) {
+                e2[q] = b * b;
+                bound[q] = 1;
+            } else {
+                active[q]->no_cert = true;
+                failed = true;
+            }
+        }
+        if (failed) {
+            // a request that goes on needs its true residual for the update
+            product<double>(w, X, X, nullptr, -1.0, 0.0, 1.0, R, nullptr, &w.rs1, false, false,
+                            nullptr, rs);
+            e2 = seg_sums(w, w.rs1, segd, S);
+            std::fill(bound.begin(), bound.end(), 0);
+        }
+    }
     std::vector<double> tau(S, 0.0), tau_r(S, 0.0);
     bool any_live = false, any_fy = false;
     for (int q = 0; q < S; ++q) {
@@ -341,6 +401,7 @@ void sign_server::tick(Workspace &w) {
         const int k = (int)r->es.size();
         sign_iter_stats it{};
         it.e = e;
+        it.e_bound = bound[q];
         it.xfro = r->xf;
         const bool conv = r->o.stop_rule == 1 ? (r->d_prev < r->o.tol) : (e <= r->o.tol);
         int st = SIGN_PENDING;
@@ -367,8 +428,6 @@ void sign_server::tick(Workspace &w) {
     }
     if (!any_live) return;
     std::vector<int> bstar;
-    std::vector<int64_t> seg_h(S + 1, 0);
-    for (int q = 0; q < S; ++q) seg_h[q + 1] = seg_h[q] + active[q]->n;
     if (any_fy) {
         filter_seg(w, R, seg_h, segd, row_seg.as<int32_t>(), tau_r, Xn, nullptr, nullptr, bstar);
         std::swap(R, Xn);
@@ -398,6 +457,7 @@ void sign_server::tick(Workspace &w) {
         it.tau = tau[q];
         it.ffro = std::sqrt(f2[q]);
         it.bstar = bstar[q];
+        r->ff_prev = it.ffro;
         r->xf = std::sqrt(k2[q]);
         r->d_prev = it.d;
         r->updates += 1;
@@ -479,7 +539,8 @@ int sign_server_create(const sign_server_opts *o, sign_server **s) {
         sv->al.stream = sv->stream;
         for (DevBuf *b : {&sv->seg_d, &sv->row_seg, &sv->skip, &sv->moves, &sv->rowsym})
             b->bind(&sv->al);
-        for (DMat<double> *m : {&sv->X, &sv->R, &sv->Xb, &sv->Xn, &sv->Xl}) m->bind(&sv->al);
+        for (DMat<double> *m : {&sv->X, &sv->R, &sv->Xb, &sv->Xn, &sv->Xl, &sv->Xt})
+            m->bind(&sv->al);
         sv->worker = std::thread([sv] { sv->run(); });
         *s = sv;
         return SIGN_OK;

@@ -63,16 +63,27 @@ def test_served_results_equal_solo_results(sf):
     finally:
         srv.close()
     assert st["completed"] == len(reqs) and st["max_active"] >= 2
+    certified = 0
     for (A, tol), t in zip(reqs, tickets):
         r = res[t]
         assert r.status == "OK"
         X = r.to_scipy()
-        solo = sf.sign_ns(sf.DeviceCsr.from_host(A), sf.default_opts(tol=tol)).to_scipy()
+        solo_r = sf.sign_ns(sf.DeviceCsr.from_host(A), sf.default_opts(tol=tol))
+        solo = solo_r.to_scipy()
         # same arithmetic alone and in the mix, up to the order of LDS additions
         assert _rel(X, solo) <= 1e-12
+        assert r.stats()["iters"] == solo_r.stats()["iters"]
         ref = oracle.nsf(A, tol=tol).to_scipy()
         assert _rel(X, ref) <= max(1e-10, 10 * tol)
         assert r.stats()["res_fro"] <= tol
+        # a residual certified from a thinned copy bounds the true one
+        last = r.trace()[-1]
+        assert last["e_bound"] == solo_r.trace()[-1]["e_bound"]
+        if last["e_bound"]:
+            certified += 1
+            e_full = sp.linalg.norm(sp.identity(A.n, format="csr") - X @ X)
+            assert e_full <= last["e"] <= tol
+    assert certified >= 1
 
 
 def test_late_arrivals_join_the_running_batch(sf):
