@@ -30,8 +30,9 @@
  * and the result is exactly symmetric.
  *
  * Tuning (environment, read when a call starts): SIGNFN_ROW_GROUP = 1, 2, 4,
- * 8 (default) or 16 output rows per workgroup of the product kernel for rows
- * with wide column spans; SIGNFN_SYMMETRIC=0 turns the symmetric products off;
+ * 8 or 16 output rows per workgroup of the product kernel for rows with wide
+ * column spans (default: 4 or 8 per product, from the density of B's rows
+ * within their column ranges); SIGNFN_SYMMETRIC=0 turns the symmetric products off;
  * SIGNFN_PROGRESS=1 prints one line per finished iteration to stderr.
  */
 #ifndef SIGNFN_H

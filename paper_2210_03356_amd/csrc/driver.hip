@@ -18,12 +18,15 @@ Workspace::Workspace(Allocator *a, size_t staging_bytes) : al(a), s(a->stream) {
     for (DevBuf *b : {&lo, &span, &cap, &work, &capoff, &workoff, &tmp, &bins, &counts, &cursor,
                       &stage_col, &stage_val, &rs1, &rs2, &rs3, &rs4, &icnt, &hist, &tau,
                       &bstar, &seg, &red, &flag, &zero_b, &cstat, &mk, &mm, &mc, &cv, &mlen, &cnext, &symcnt, &symoff, &symfill,
-                      &symtcol, &symtval, &rs5, &whole, &sums})
+                      &symtcol, &symtval, &rs5, &whole, &sums, &pst})
         b->bind(a);
     // rows per workgroup for wide rows: 1 (off), 2, 4, 8 or 16
     if (const char *ge = std::getenv("SIGNFN_ROW_GROUP")) {
         const int g = std::atoi(ge);
-        if (g == 1 || g == 2 || g == 4 || g == 8 || g == 16) row_group = g;
+        if (g == 1 || g == 2 || g == 4 || g == 8 || g == 16) {
+            row_group = g;
+            auto_group = false;
+        }
     }
     if (const char *se = std::getenv("SIGNFN_SYMMETRIC")) allow_sym = se[0] != '0';
     if (const char *pe = std::getenv("SIGNFN_PROGRESS")) progress = pe[0] == '1';
@@ -50,16 +53,23 @@ Workspace::~Workspace() {
 }
 
 void Workspace::hot_stats(sign_stats &st) const {
-    int hv = 0, h = 1;
-    for (int v = 0; v < 2; ++v)
-        for (int c = 1; c < kClasses; ++c)
-            if (cls[v][c].ms > cls[hv][h].ms) { hv = v; h = c; }
-    const ClassStat &c = cls[hv][h];
-    const BinCfg cfg = h == 4 ? group_config(row_group, hv ? 4 : 8) : bin_config(h, hv ? 4 : 8);
+    // the launch configuration with the most device time: a row class 1..3,
+    // or row groups of 2^g rows
+    int hv = 0, h = 1, hg = -1;
+    const ClassStat *best = &cls[0][1];
+    for (int v = 0; v < 2; ++v) {
+        for (int c = 1; c < 4; ++c)
+            if (cls[v][c].ms > best->ms) { best = &cls[v][c]; hv = v; h = c; hg = -1; }
+        for (int g = 0; g < 5; ++g)
+            if (grp[v][g].ms > best->ms) { best = &grp[v][g]; hv = v; h = 4; hg = g; }
+    }
+    const ClassStat &c = *best;
+    const int group = hg >= 0 ? 1 << hg : 1;
+    const BinCfg cfg = h == 4 ? group_config(group, hv ? 4 : 8) : bin_config(h, hv ? 4 : 8);
     st.hot_tile = cfg.tile;
     st.hot_threads = cfg.threads;
     st.hot_fp32 = hv;
-    st.hot_group = h == 4 ? row_group : 1;
+    st.hot_group = group;
     st.hot_launches = c.launches;
     st.hot_ms = c.ms;
     st.hot_bytes = c.bytes;
@@ -170,6 +180,13 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
                            hipMemcpyDeviceToHost, s));
     SFN_HIP(hipMemcpyAsync(&tot[1], w.workoff.as<int64_t>() + n, sizeof(int64_t),
                            hipMemcpyDeviceToHost, s));
+    unsigned long long pst[2] = {0, 0};
+    if (w.auto_group) {
+        w.pst.ensure(2 * sizeof(unsigned long long));
+        SFN_HIP(hipMemsetAsync(w.pst.get(), 0, 2 * sizeof(unsigned long long), s));
+        launch_row_density<V>(B.view(), w.pst.as<unsigned long long>(), s);
+        SFN_HIP(hipMemcpyAsync(pst, w.pst.get(), sizeof(pst), hipMemcpyDeviceToHost, s));
+    }
     SFN_HIP(hipStreamSynchronize(s));
     const int64_t total_cap = tot[0];
     w.products += tot[1];
@@ -217,7 +234,14 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
     w.cstat.ensure(sizeof(int64_t) * 8 * kClasses);
     // row groups need A compact (rows i .. i+g-1 adjacent in storage) -- every
     // matrix built here is; the merged lists reuse A's index range
-    const int group = w.row_group;
+    // Groups of 8 rows (2048-column windows) halve the B traffic of groups of 4
+    // (4096), but every window costs a pass over the group's slots.  Where a B
+    // row holds few entries per window -- density within its column range
+    // times 2048 below ~200 -- that pass dominates and groups of 4 are faster
+    // (measured on the 2D workloads: 256^2 FP64 products favour 8, 512^2 and
+    // FP32 products and products with B = A favour 4).
+    int group = w.row_group;
+    if (w.auto_group && pst[1] > 0) group = 2048ull * pst[0] < 200ull * pst[1] ? 4 : 8;
     if (group > 1) {
         const size_t ext = (size_t)std::max<int64_t>(a_extent, 1);
         w.mk.ensure(sizeof(int32_t) * ext);
@@ -295,7 +319,9 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
             SFN_HIP(hipEventElapsedTime(&ms, w.ev[evb[cls]], w.ev[evb[cls] + 1]));
             w.spgemm_ms += ms;
             if (cnt[cls] <= 0) continue;
-            Workspace::ClassStat &c = w.cls[sizeof(V) == 4 ? 1 : 0][cls];
+            const int lg = group >= 16 ? 4 : group >= 8 ? 3 : group >= 4 ? 2 : group >= 2 ? 1 : 0;
+            Workspace::ClassStat &c = cls == 4 ? w.grp[sizeof(V) == 4 ? 1 : 0][lg]
+                                               : w.cls[sizeof(V) == 4 ? 1 : 0][cls];
             const int64_t *q = cs + cls * 8;
             c.launches += 1;
             c.rows += cls == 4 ? (int64_t)group * cnt[cls] : cnt[cls];

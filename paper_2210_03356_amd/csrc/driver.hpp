@@ -20,8 +20,10 @@ struct Workspace {
     DevBuf cstat, mk, mm, mc, cv, mlen, cnext;
     DevBuf symcnt, symoff, symfill, symtcol, symtval;  // mirroring of symmetric products
     DevBuf rs5;                                        // per-row sums not stored by a product
+    DevBuf pst;                                        // column-range statistics of a plan
     const uint8_t *row_skip = nullptr;  // optional row mask for products (serving)
     int row_group = 8;                  // wide rows computed in groups of 1, 2, 4, 8 or 16
+    bool auto_group = true;             // choose 4 or 8 per product from its column ranges
     bool allow_sym = true;              // symmetric products from their lower triangle
     bool progress = false;              // one stderr line per finished iteration
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -31,7 +33,8 @@ struct Workspace {
         int64_t gathered = 0;  // B entries loaded (once per slot of a row group)
         double ms = 0.0, bytes = 0.0;
     };
-    ClassStat cls[2][kClasses];  // [FP64, FP32][row class]
+    ClassStat cls[2][kClasses];  // [FP64, FP32][row class 1..3]
+    ClassStat grp[2][5];         // [FP64, FP32][log2 of the row group] (class 4)
     double merge_ms = 0.0;
     int64_t products = 0;
     double spgemm_ms = 0.0;

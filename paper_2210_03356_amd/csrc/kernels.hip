@@ -323,6 +323,37 @@ __global__ void k_plan(MatView<V> A, MatView<V> B, MatView<V> D, int diag, int64
     }
 }
 
+// Entries and column ranges (last - first + 1) of the nonempty rows of B,
+// summed: their ratio is the density of a B row within its range.
+constexpr int kSpanThreads = 256;
+template <typename V>
+__global__ __launch_bounds__(kSpanThreads) void k_row_density(MatView<V> B,
+                                                              unsigned long long *out) {
+    __shared__ int64_t ws[kSpanThreads / kWave], wc[kSpanThreads / kWave];
+    const int64_t i = (int64_t)blockIdx.x * kSpanThreads + threadIdx.x;
+    int64_t len = 0, rng = 0;
+    if (i < B.n) {
+        const int l = B.len[i];
+        if (l > 0) {
+            const int64_t b = B.beg[i];
+            len = l;
+            rng = (int64_t)B.col[b + l - 1] - B.col[b] + 1;
+        }
+    }
+    len = wave_sum(len);
+    rng = wave_sum(rng);
+    if (lane_id() == 0) { ws[wave_id()] = len; wc[wave_id()] = rng; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t a = 0, b = 0;
+        for (int w = 0; w < kSpanThreads / kWave; ++w) { a += ws[w]; b += wc[w]; }
+        if (a) {
+            atomicAdd(&out[0], (unsigned long long)a);
+            atomicAdd(&out[1], (unsigned long long)b);
+        }
+    }
+}
+
 constexpr int kBinThreads = 256;
 
 // Row classes: 0 empty, 1 small window, 2 mid window, 3 wide rows swept in
@@ -1410,6 +1441,15 @@ void launch_exclusive_scan_i32(const int32_t *in, int64_t n, int64_t *out, int64
                                int64_t init, hipStream_t s) {
     scan_impl<int32_t>(in, n, out, tmp, init, s);
 }
+
+template <typename V>
+void launch_row_density(MatView<V> B, unsigned long long *out, hipStream_t s) {
+    if (B.n <= 0) return;
+    const int64_t nb = (B.n + kSpanThreads - 1) / kSpanThreads;
+    k_row_density<V><<<(unsigned)nb, kSpanThreads, 0, s>>>(B, out);
+}
+template void launch_row_density<double>(MatView<double>, unsigned long long *, hipStream_t);
+template void launch_row_density<float>(MatView<float>, unsigned long long *, hipStream_t);
 
 template <typename V>
 void launch_plan(MatView<V> A, MatView<V> B, MatView<V> D, int diag, int64_t r0, int64_t r1,

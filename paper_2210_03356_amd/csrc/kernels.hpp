@@ -84,6 +84,9 @@ void launch_exclusive_scan_i32(const int32_t *in, int64_t n, int64_t *out, int64
 // Plan: per row i of A (rows [r0, r1)): column window [lo[i], lo[i]+span[i]),
 // reserved output capacity cap[i], product count work[i].
 // Rows with skip[i] != 0 (skip may be null) get an empty output and no work.
+// out[0] += entries, out[1] += column ranges (last - first + 1) of B's nonempty rows
+template <typename V>
+void launch_row_density(MatView<V> B, unsigned long long *out, hipStream_t s);
 template <typename V>
 void launch_plan(MatView<V> A, MatView<V> B, MatView<V> D, int diag, int64_t r0, int64_t r1,
                  int32_t *lo, int32_t *span, int64_t *cap, int64_t *work, const uint8_t *skip,
