@@ -40,11 +40,12 @@ def kernel_name(st, tile) -> str:
     return f"k_spgemm_rows<{v},{st['hot_group']},{tile},{st['hot_threads']}>"
 
 
-def read_traffic(st, config: str, precision: int):
+def read_traffic(st, config: str, precision: int, grid=None, method="ns"):
     """Per-launch HBM bytes (FETCH + WRITE, copy-calibrated) of the hot kernel from the
     committed counter summary; None for other workloads or once the kernel source
     differs from the one the counters were taken on."""
-    if config != "c2" or precision != 0 or not os.path.exists(TRAFFIC_FILE):
+    if (config != "c2" or grid or precision != 0 or method != "ns"
+            or not os.path.exists(TRAFFIC_FILE)):
         return None
     vals = {}
     for line in open(TRAFFIC_FILE):
@@ -358,7 +359,7 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.config, args.grid, A.n)
 
-    traffic = read_traffic(st, args.config, args.precision)
+    traffic = read_traffic(st, args.config, args.precision, args.grid, args.method)
     line = {
         "metric": METRIC,
         "value": round(ms_per_step / 1e3, 4),
