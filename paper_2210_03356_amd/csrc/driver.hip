@@ -723,20 +723,20 @@ void transpose(Workspace &w, const DMat<double> &X, DMat<double> &Out) {
     Out.ensure_entries(X.nnz);
     w.icnt.ensure(sizeof(int32_t) * std::max<int64_t>(n, 1));
     w.tmp.ensure(sizeof(int64_t) * scan_tmp_elems(n));
-    w.flag.ensure(sizeof(int));
+    w.symtcol.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(X.nnz, 1));
+    w.symtval.ensure(sizeof(double) * (size_t)std::max<int64_t>(X.nnz, 1));
     SFN_HIP(hipMemsetAsync(w.icnt.get(), 0, sizeof(int32_t) * n, s));
-    SFN_HIP(hipMemsetAsync(w.flag.get(), 0, sizeof(int), s));
     launch_transpose_count<double>(X.view(), w.icnt.as<int32_t>(), s);
     launch_exclusive_scan_i32(w.icnt.as<int32_t>(), n, Out.begp(), w.tmp.as<int64_t>(), 0, s);
     SFN_HIP(hipMemcpyAsync(Out.lenp(), w.icnt.get(), sizeof(int32_t) * n, hipMemcpyDeviceToDevice,
                            s));
     SFN_HIP(hipMemsetAsync(w.icnt.get(), 0, sizeof(int32_t) * n, s));
-    launch_transpose_fill<double>(X.view(), Out.begp(), w.icnt.as<int32_t>(), Out.colp(),
-                                  Out.valp(), s);
-    launch_sort_rows<double>(Out.begp(), Out.colp(), Out.valp(), n, w.flag.as<int>(), s);
-    if (read_scalar(w.flag.as<int>(), s))
-        throw Error(SIGN_EINVAL, "transpose: a row is longer than " +
-                                     std::to_string(sort_rows_max()) + " entries");
+    // entries of column j of X, unordered, then ranked by row into row j of Out
+    launch_transpose_fill<double>(X.view(), Out.begp(), w.icnt.as<int32_t>(),
+                                  w.symtcol.as<int32_t>(), w.symtval.as<double>(), s);
+    launch_sym_rank<double>(n, Out.begp(), nullptr, Out.begp(), Out.lenp(),
+                            w.symtcol.as<int32_t>(), w.symtval.as<double>(), Out.colp(),
+                            Out.valp(), s);
     Out.nnz = X.nnz;
 }
 

@@ -1105,54 +1105,6 @@ __global__ void k_transpose_fill(MatView<V> X, const int64_t *tp, int32_t *fill,
     }
 }
 
-// Sort each row of a compact CSR by column: bitonic sort of (col, val) pairs
-// in LDS, one workgroup per row; rows longer than kSortMax are flagged.
-constexpr int kSortMax = 8192;
-constexpr int kSortThreads = 512;
-
-template <typename V>
-__global__ __launch_bounds__(kSortThreads) void k_sort_rows(const int64_t *rp, int32_t *col,
-                                                            V *val, int64_t n, int *flag) {
-    __shared__ int32_t kc[kSortMax];
-    __shared__ V kv[kSortMax];
-    const int64_t i = blockIdx.x;
-    if (i >= n) return;
-    const int64_t b = rp[i];
-    const int l = (int)(rp[i + 1] - b);
-    if (l <= 1) return;
-    if (l > kSortMax) {
-        if (threadIdx.x == 0) atomicOr(flag, 1);
-        return;
-    }
-    int m = 1;
-    while (m < l) m <<= 1;
-    for (int t = threadIdx.x; t < m; t += kSortThreads) {
-        kc[t] = t < l ? col[b + t] : INT_MAX;
-        kv[t] = t < l ? val[b + t] : V(0);
-    }
-    __syncthreads();
-    for (int k = 2; k <= m; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int t = threadIdx.x; t < m; t += kSortThreads) {
-                const int u = t ^ j;
-                if (u > t) {
-                    const bool up = (t & k) == 0;
-                    const int32_t a = kc[t], c = kc[u];
-                    if ((a > c) == up) {
-                        kc[t] = c; kc[u] = a;
-                        const V va = kv[t]; kv[t] = kv[u]; kv[u] = va;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-    for (int t = threadIdx.x; t < l; t += kSortThreads) {
-        col[b + t] = kc[t];
-        val[b + t] = kv[t];
-    }
-}
-
 // ---------------------------------------------------------------------------
 // symmetric products: the full matrix from its lower triangle L
 // ---------------------------------------------------------------------------
@@ -1197,10 +1149,12 @@ __global__ void k_sym_place(MatView<V> L, LowerRows lower, const int64_t *cbeg, 
     }
 }
 
-// Row c of C gets its mirror list, ordered by column, after its lower part:
-// the keys j > c are ranked with an LDS bitmap over chunks of kRankChunk
-// consecutive keys (rank = set bits below the key), so no comparison sort is
-// needed and any list length is handled.  One workgroup per row.
+// Row c of C gets its list of tcnt[c] unordered (key, value) pairs, ordered by
+// key, after its first llen[c] entries (none when llen is null): the keys are
+// ranked with an LDS bitmap over chunks of kRankChunk consecutive keys from the
+// smallest (rank = set bits below the key), so no comparison sort is needed
+// and any list length is handled.  Keys of a row are distinct.  One workgroup
+// per row.  (The mirror of a lower triangle: keys j > c; a transpose: any.)
 constexpr int kRankChunk = 65536;
 constexpr int kRankThreads = 256;
 
@@ -1218,17 +1172,26 @@ __global__ __launch_bounds__(kRankThreads) void k_sym_rank(
     const int m = tcnt[c];
     if (m == 0) return;
     const int64_t tb = toff[c];
-    const int64_t ob = cbeg[c] + llen[c];
+    const int64_t ob = cbeg[c] + (llen ? llen[c] : 0);
     const int lane = lane_id(), wave = wave_id();
-    // largest key, to bound the chunks
-    int kmax = c;
-    for (int q = threadIdx.x; q < m; q += kRankThreads) kmax = max(kmax, tcol[tb + q]);
+    // smallest and largest key, to bound the chunks
+    int kmin = INT_MAX, kmax = INT_MIN;
+    for (int q = threadIdx.x; q < m; q += kRankThreads) {
+        const int key = tcol[tb + q];
+        kmin = min(kmin, key);
+        kmax = max(kmax, key);
+    }
+    kmin = wave_min(kmin);
     kmax = wave_max(kmax);
-    if (lane == 0) red[wave] = kmax;
+    if (lane == 0) { red[wave] = kmin; wtot[wave] = kmax; }
     __syncthreads();
-    for (int w = 0; w < kRankThreads / kWave; ++w) kmax = max(kmax, red[w]);
+    for (int w = 0; w < kRankThreads / kWave; ++w) {
+        kmin = min(kmin, red[w]);
+        kmax = max(kmax, wtot[w]);
+    }
+    __syncthreads();  // red and wtot are reused below
     int done = 0;  // keys ranked in earlier chunks
-    for (int64_t k0 = (int64_t)c + 1; k0 <= kmax; k0 += kRankChunk) {
+    for (int64_t k0 = kmin; k0 <= kmax; k0 += kRankChunk) {
         for (int q = threadIdx.x; q < NWORD; q += kRankThreads) bits[q] = 0u;
         __syncthreads();
         for (int q = threadIdx.x; q < m; q += kRankThreads) {
@@ -1335,16 +1298,9 @@ void launch_transpose_fill(MatView<V> X, const int64_t *tp, int32_t *fill, int32
                            hipStream_t s) {
     if (X.n > 0) k_transpose_fill<V><<<blocks_for(X.n, 4), 256, 0, s>>>(X, tp, fill, tcol, tval);
 }
-template <typename V>
-void launch_sort_rows(const int64_t *rp, int32_t *col, V *val, int64_t n, int *flag,
-                      hipStream_t s) {
-    if (n > 0) k_sort_rows<V><<<(unsigned)n, kSortThreads, 0, s>>>(rp, col, val, n, flag);
-}
 template void launch_transpose_count<double>(MatView<double>, int32_t *, hipStream_t);
 template void launch_transpose_fill<double>(MatView<double>, const int64_t *, int32_t *, int32_t *,
                                             double *, hipStream_t);
-template void launch_sort_rows<double>(const int64_t *, int32_t *, double *, int64_t, int *,
-                                       hipStream_t);
 template <typename V>
 void launch_sym_count(MatView<V> L, LowerRows lower, int32_t *cnt, hipStream_t s) {
     if (L.n > 0) k_sym_count<V><<<blocks_for(L.n, 4), 256, 0, s>>>(L, lower, cnt);
@@ -1382,8 +1338,6 @@ void launch_sym_check(MatView<V> X, int *flag, hipStream_t s) {
 SFN_SYM_INST(double)
 SFN_SYM_INST(float)
 #undef SFN_SYM_INST
-
-int sort_rows_max() { return kSortMax; }
 
 // ===========================================================================
 // launchers

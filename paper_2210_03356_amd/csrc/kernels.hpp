@@ -127,7 +127,8 @@ BinCfg group_config(int group, int value_bytes);
 // cnt[c] += #{j > c : L(j, c) != 0}; out = a + b (row lengths);
 // place: L rows to the front of C rows, strictly-lower entries appended to
 // their column's mirror list (tcol/tval at toff[c] + arrival order; fill
-// zeroed); rank: each mirror list written ordered after the row's lower part.
+// zeroed); rank: each mirror list written ordered after the row's lower part
+// (llen null: at the start of the row, as for a transpose).
 template <typename V>
 void launch_sym_count(MatView<V> L, LowerRows lower, int32_t *cnt, hipStream_t s);
 void launch_add_len(const int32_t *a, const int32_t *b, int64_t n, int32_t *out, hipStream_t s);
@@ -213,18 +214,12 @@ void launch_identity(int64_t n, int64_t *beg, int32_t *len, int32_t *col, double
 template <typename V>
 void launch_col_abs_sum(MatView<V> X, double *colsum, hipStream_t s);
 // transpose: count per column, then fill rows of X^T at tp[j] + atomic slot;
-// rows of the result are unordered until launch_sort_rows
+// rows of the result are unordered until ranked with launch_sym_rank
 template <typename V>
 void launch_transpose_count(MatView<V> X, int32_t *cnt, hipStream_t s);
 template <typename V>
 void launch_transpose_fill(MatView<V> X, const int64_t *tp, int32_t *fill, int32_t *tcol, V *tval,
                            hipStream_t s);
-// sort every row of a compact CSR by column; rows longer than sort_rows_max()
-// set *flag and are left unsorted
-template <typename V>
-void launch_sort_rows(const int64_t *rp, int32_t *col, V *val, int64_t n, int *flag,
-                      hipStream_t s);
-int sort_rows_max();
 // diag[i] = X_ii in FP64 (0 when not stored)
 template <typename V>
 void launch_diag(MatView<V> X, double *diag, hipStream_t s);
