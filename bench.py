@@ -117,10 +117,16 @@ def device_trace(res):
     import paper_2210_03356_amd as sf
     sf.release_cached()   # the library's cached blocks back to HIP, for torch's copies
     rp, ci, va = res.to_torch()
-    n = rp.numel() - 1
-    r = torch.repeat_interleave(torch.arange(n, device=rp.device), rp[1:] - rp[:-1])
-    t = float(va[ci.long() == r].double().sum())
-    del rp, ci, va, r
+    nnz = ci.numel()
+    t = 0.0
+    step = 1 << 26  # entries per chunk (masks of billions of entries overflow in torch)
+    for s0 in range(0, nnz, step):
+        s1 = min(nnz, s0 + step)
+        pos = torch.arange(s0, s1, device=rp.device, dtype=torch.int64)
+        row = torch.searchsorted(rp, pos, right=True) - 1
+        diag = ci[s0:s1].long() == row
+        t += float(torch.where(diag, va[s0:s1].double(), 0.0).sum())
+    del rp, ci, va
     return t
 
 

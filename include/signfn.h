@@ -149,7 +149,8 @@ typedef struct {
                             of X^_k thinned by delta <= tol/16 in Frobenius norm
                             (tried where Lemma 2.1.1 predicts convergence, and on the
                             first residual after the mixed mode's refinement; nnz_r is
-                            then that of I - Xt^2) */
+                            then that of I - Xt^2, of its lower triangle when X^_k is
+                            exactly symmetric; I - Xt^2 is not stored) */
     double ms;           /* wall time of the step */
 } sign_iter_stats;
 

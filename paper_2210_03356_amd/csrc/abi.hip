@@ -159,6 +159,7 @@ LoopOut mixed_precision(Workspace &w, const sign_csr *A, double c, const sign_op
         const double af = std::sqrt(w.sum_rows(w.rs3, n));
         for (int sweep = 0; sweep < o.refine_steps; ++sweep) {
             const double t0 = now_s();
+            w.note("refine sweep %d: X %lld entries", sweep, (long long)X.nnz);
             product<double>(w, As, X, nullptr, 1.0, 0.0, 0.0, P, nullptr, nullptr);
             // C = A X - X A
             product<double>(w, X, As, &P, -1.0, 1.0, 0.0, Cm, nullptr, &w.rs1);
@@ -181,8 +182,19 @@ LoopOut mixed_precision(Workspace &w, const sign_csr *A, double c, const sign_op
                 break;
             }
             const double omega = 1.0 / (2.0 * mean_abs);
-            product<double>(w, X, Cm, &X, -omega, 1.0, 0.0, Xb, nullptr, nullptr);
-            filter<double, double>(w, Xb, o.c_fixed * o.tol, Xn, nullptr, nullptr);
+            P = DMat<double>();  // not needed until the next sweep: give its memory back
+            P.bind(w.al);
+            // X - omega X C, filtered with the fixed budget; the product forms the
+            // filter's histogram and stores only entries some cut could keep
+            const double tau = o.c_fixed * o.tol;
+            w.hist.ensure(sizeof(uint64_t) * kBuckets);
+            w.rs5.ensure(sizeof(double) * n);
+            SFN_HIP(hipMemsetAsync(w.hist.get(), 0, sizeof(uint64_t) * kBuckets, w.s));
+            SFN_HIP(hipMemsetAsync(w.rs5.get(), 0, sizeof(double) * n, w.s));
+            const FusedFilter fuse{tau, w.hist.as<uint64_t>(), w.rs5.as<double>()};
+            product<double>(w, X, Cm, &X, -omega, 1.0, 0.0, Xb, nullptr, nullptr, false, false,
+                            &fuse);
+            filter<double, double>(w, Xb, tau, Xn, nullptr, nullptr, 0, true);
             w.note("refine sweep %d: estimated error %.3e, nnz C %lld, X %lld (%.1f ms)", sweep,
                    est, (long long)Cm.nnz, (long long)Xn.nnz, 1e3 * (now_s() - t0));
             std::swap(X, Xn);

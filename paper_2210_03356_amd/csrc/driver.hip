@@ -30,20 +30,23 @@ Workspace::Workspace(Allocator *a, size_t staging_bytes) : al(a), s(a->stream) {
     }
     if (const char *se = std::getenv("SIGNFN_SYMMETRIC")) allow_sym = se[0] != '0';
     if (const char *pe = std::getenv("SIGNFN_PROGRESS")) progress = pe[0] == '1';
-    if (staging_bytes == 0) {
-        // a quarter of the memory that is free or idle in the caching pool,
-        // capped so that one reservation stays a modest share of HBM
-        size_t fr = 0, tot = 0;
-        if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
-            (void)hipGetLastError();
-            fr = size_t(8) << 30;
-        }
-        const size_t avail = fr + (a->alloc ? 0 : Pool::instance().cached_bytes());
-        staging_bytes = std::min<size_t>(size_t(48) << 30,
-                                         std::max<size_t>(size_t(256) << 20, avail / 4));
-    }
-    staging_limit = staging_bytes;
+    staging_auto = staging_bytes == 0;
+    staging_limit = staging_auto ? auto_staging() : staging_bytes;
     for (auto &e : ev) SFN_HIP(hipEventCreate(&e));
+}
+
+// A quarter of the memory that is free, idle in the caching pool or held by
+// the staging buffers themselves, capped so that one reservation stays a
+// modest share of HBM.
+size_t Workspace::auto_staging() const {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+        (void)hipGetLastError();
+        fr = size_t(8) << 30;
+    }
+    const size_t avail = fr + (al->alloc ? 0 : Pool::instance().cached_bytes()) +
+                         stage_col.size() + stage_val.size();
+    return std::min<size_t>(size_t(24) << 30, std::max<size_t>(size_t(256) << 20, avail / 4));
 }
 
 Workspace::~Workspace() {
@@ -149,9 +152,12 @@ int safe_drop_bucket(double tau, double U) {
 }
 
 template <typename V>
+// no_store: only the per-row sums of squares and the entry counts of C are
+// formed (C gets its row lengths and starts but no entries).
 void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D,
                   double coef, double dcoef, double diag, DMat<V> &C, DevBuf *sq_prod,
-                  DevBuf *sq_out, LowerRows lower, const FusedFilter *ff) {
+                  DevBuf *sq_out, LowerRows lower, const FusedFilter *ff,
+                  bool no_store = false) {
     const int64_t n = A.n;
     hipStream_t s = w.s;
     if (B.n != n || (D && D->n != n)) throw Error(SIGN_EINVAL, "product: shape mismatch");
@@ -192,6 +198,7 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
     w.products += tot[1];
     ProductEpi epi;
     epi.lower = lower;
+    epi.no_store = no_store ? 1 : 0;
     // B with a few entries per row (e.g. B = A): lane-per-slot accumulation
     epi.short_b = B.nnz <= 16 * std::max<int64_t>(B.n, 1);
     if (ff) {
@@ -205,10 +212,15 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
 
     // batches of rows whose reserved output fits the staging budget
     const size_t entry = sizeof(int32_t) + sizeof(V);
+    if (w.staging_auto) w.staging_limit = w.auto_staging();  // memory use changes as iterates grow
     const int64_t budget = std::max<int64_t>((int64_t)(w.staging_limit / entry), n);
+    if (w.progress && total_cap > (int64_t)1 << 30 && !w.al->alloc)
+        w.note("product: %lld rows, %lld reserved entries, staging %.1f GB, pool %.1f GB in use, "
+               "%.1f GB cached", (long long)n, (long long)total_cap, w.staging_limit / 1e9,
+               Pool::instance().used_bytes() / 1e9, Pool::instance().cached_bytes() / 1e9);
     std::vector<int64_t> cuts{0};
     std::vector<int64_t> capoff_h;
-    if (total_cap <= budget) {
+    if (total_cap <= budget || no_store) {
         cuts.push_back(n);
     } else {
         capoff_h.resize(n + 1);
@@ -227,8 +239,22 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
         }
     }
     const int64_t a_extent = A.capacity();
-    w.cursor.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(a_extent, 1));
-    w.cnext.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(a_extent, 1));
+    // The per-A-entry arrays (cursors, merged group lists) cover the A entries
+    // of one batch when the product runs in several batches and A is compact:
+    // batch [r0, r1) then uses A's index range [beg[r0], beg[r1]), and the
+    // arrays are addressed through pointers shifted by beg[r0].
+    std::vector<int64_t> abeg_h;
+    if (cuts.size() > 2) {
+        std::vector<int32_t> alen_h(n);
+        abeg_h.resize(n + 1);
+        SFN_HIP(hipMemcpyAsync(abeg_h.data(), A.begp(), sizeof(int64_t) * (n + 1),
+                               hipMemcpyDeviceToHost, s));
+        SFN_HIP(hipMemcpyAsync(alen_h.data(), A.lenp(), sizeof(int32_t) * n,
+                               hipMemcpyDeviceToHost, s));
+        SFN_HIP(hipStreamSynchronize(s));
+        for (int64_t i = 0; i < n && !abeg_h.empty(); ++i)
+            if (abeg_h[i] + alen_h[i] != abeg_h[i + 1]) abeg_h.clear();  // not compact
+    }
     w.bins.ensure(sizeof(int32_t) * kClasses * (size_t)std::max<int64_t>(n, 1));
     w.counts.ensure(sizeof(int32_t) * kClasses);
     w.cstat.ensure(sizeof(int64_t) * 8 * kClasses);
@@ -242,22 +268,35 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
     // FP32 products and products with B = A favour 4).
     int group = w.row_group;
     if (w.auto_group && pst[1] > 0) group = 2048ull * pst[0] < 200ull * pst[1] ? 4 : 8;
-    if (group > 1) {
-        const size_t ext = (size_t)std::max<int64_t>(a_extent, 1);
-        w.mk.ensure(sizeof(int32_t) * ext);
-        w.mm.ensure(sizeof(uint32_t) * ext);
-        w.mc.ensure(sizeof(int32_t) * ext);
-        w.cv.ensure(sizeof(V) * ext);
-        w.mlen.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1));
-    }
+    if (group > 1) w.mlen.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1));
 
     int64_t running = 0;
     for (size_t b = 0; b + 1 < cuts.size(); ++b) {
         const int64_t r0 = cuts[b], r1 = cuts[b + 1];
         const int64_t base = capoff_h.empty() ? 0 : capoff_h[r0];
         const int64_t bcap = capoff_h.empty() ? total_cap : capoff_h[r1] - base;
-        w.stage_col.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(bcap, 1));
-        w.stage_val.ensure(sizeof(V) * (size_t)std::max<int64_t>(bcap, 1));
+        if (!no_store) {
+            w.stage_col.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(bcap, 1));
+            w.stage_val.ensure(sizeof(V) * (size_t)std::max<int64_t>(bcap, 1));
+        }
+        const int64_t abase = abeg_h.empty() ? 0 : abeg_h[r0];
+        const size_t aext =
+            (size_t)std::max<int64_t>(abeg_h.empty() ? a_extent : abeg_h[r1] - abase, 1);
+        w.cursor.ensure(sizeof(int32_t) * aext);
+        w.cnext.ensure(sizeof(int32_t) * aext);
+        if (group > 1) {
+            w.mk.ensure(sizeof(int32_t) * aext);
+            w.mm.ensure(sizeof(uint32_t) * aext);
+            w.mc.ensure(sizeof(int32_t) * aext);
+            w.cv.ensure(sizeof(V) * aext);
+        }
+        // indexed by A entry: every index a kernel uses lies in [abase, abase + aext)
+        int32_t *cursor_a = w.cursor.as<int32_t>() - abase;
+        int32_t *cnext_a = w.cnext.as<int32_t>() - abase;
+        int32_t *mk_a = group > 1 ? w.mk.as<int32_t>() - abase : nullptr;
+        uint32_t *mm_a = group > 1 ? w.mm.as<uint32_t>() - abase : nullptr;
+        int32_t *mc_a = group > 1 ? w.mc.as<int32_t>() - abase : nullptr;
+        V *cv_a = group > 1 ? w.cv.as<V>() - abase : nullptr;
         SFN_HIP(hipMemsetAsync(w.counts.get(), 0, sizeof(int32_t) * kClasses, s));
         SFN_HIP(hipMemsetAsync(w.cstat.get(), 0, sizeof(int64_t) * 8 * kClasses, s));
         launch_bin_rows(w.span.as<int32_t>(), w.work.as<int64_t>(), r0, r1, kSmallTile, kMidTile,
@@ -271,17 +310,15 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
         SFN_HIP(hipEventRecord(w.ev[0], s));
         if (cnt[4] > 0) {
             const int32_t *leads = w.bins.as<int32_t>() + (int64_t)4 * n;
-            launch_merge_group<V>(group, leads, cnt[4], A.view(), B.view(), w.mk.as<int32_t>(),
-                                  w.mm.as<uint32_t>(), w.mc.as<int32_t>(), w.cv.as<V>(),
-                                  w.mlen.as<int32_t>(), w.cstat.as<int64_t>() + 4 * 8 + 5, s);
+            launch_merge_group<V>(group, leads, cnt[4], A.view(), B.view(), mk_a, mm_a, mc_a,
+                                  cv_a, w.mlen.as<int32_t>(), w.cstat.as<int64_t>() + 4 * 8 + 5,
+                                  s);
             SFN_HIP(hipEventRecord(w.ev[1], s));
-            launch_spgemm_group<V>(group, leads, cnt[4], w.mk.as<int32_t>(),
-                                   w.mm.as<uint32_t>(), w.mc.as<int32_t>(), w.cv.as<V>(),
+            launch_spgemm_group<V>(group, leads, cnt[4], mk_a, mm_a, mc_a, cv_a,
                                    w.mlen.as<int32_t>(), A.view(), B.view(), Dv, coef, dcoef,
                                    diag, w.lo.as<int32_t>(), w.span.as<int32_t>(), base,
                                    w.capoff.as<int64_t>(), w.stage_col.as<int32_t>(),
-                                   w.stage_val.as<V>(), C.lenp(), w.cursor.as<int32_t>(),
-                                   w.cnext.as<int32_t>(),
+                                   w.stage_val.as<V>(), C.lenp(), cursor_a, cnext_a,
                                    sq_prod ? sq_prod->as<double>() : nullptr,
                                    sq_out ? sq_out->as<double>() : nullptr,
                                    w.cstat.as<int64_t>() + 4 * 8 + 4, epi, s);
@@ -294,7 +331,7 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
                              B.view(), Dv, coef, dcoef, diag, w.lo.as<int32_t>(),
                              w.span.as<int32_t>(), base, w.capoff.as<int64_t>(),
                              w.stage_col.as<int32_t>(), w.stage_val.as<V>(), C.lenp(),
-                             w.cursor.as<int32_t>(), w.cnext.as<int32_t>(),
+                             cursor_a, cnext_a,
                              sq_prod ? sq_prod->as<double>() : nullptr,
                              sq_out ? sq_out->as<double>() : nullptr,
                              w.cstat.as<int64_t>() + cls * 8 + 4, epi, s);
@@ -341,6 +378,16 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
             c.gathered += cls == 4 ? q[5] : q[1];
             c.bytes += bytes;
             w.spgemm_bytes += bytes;
+        }
+        if (no_store) {
+            running = end;
+            continue;
+        }
+        if (b == 0 && cuts.size() > 2 && bcap > 0) {
+            // size C once from the first batch's fill ratio, so that later
+            // batches rarely grow it (a grow keeps the old block alongside)
+            const double est = 1.1 * (double)end * (double)total_cap / (double)bcap;
+            C.ensure_entries(std::max<int64_t>(end, (int64_t)std::min(est, (double)total_cap)));
         }
         C.ensure_entries(end, running);
         launch_copy_rows<V>(w.capoff.as<int64_t>(), base, C.lenp(),
@@ -406,6 +453,19 @@ void product(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D,
     product_rows<V>(w, A, B, D, coef, dcoef, diag, L, sq_prod, sq_out, lower, ff);
     symmetrize<V>(w, L, C, lower);
 }
+
+template <typename V>
+int64_t product_sumsq(Workspace &w, const DMat<V> &A, const DMat<V> &B, double coef,
+                      double diag, DevBuf *sq_out, bool sym) {
+    LowerRows lower;
+    lower.all = sym ? 1 : 0;
+    DMat<V> C;
+    C.bind(w.al);
+    product_rows<V>(w, A, B, nullptr, coef, 0.0, diag, C, nullptr, sq_out, lower, nullptr, true);
+    return C.nnz;
+}
+template int64_t product_sumsq<double>(Workspace &, const DMat<double> &, const DMat<double> &,
+                                       double, double, DevBuf *, bool);
 
 template <typename V>
 bool is_symmetric(Workspace &w, const DMat<V> &X) {
@@ -580,14 +640,15 @@ double norm_one_inf(Workspace &w, const DMat<double> &X) {
 //   ||I - X^2||_F <= ||I - Xt^2||_F + 2 ||Xt||_2 delta + delta^2,
 // with ||Xt||_2 <= sqrt(||X||_1 ||X||_inf) (dropping entries lowers both), and
 // for an exactly symmetric Xt also ||Xt||_2^2 = ||Xt^2||_2 <= 1 + ||I - Xt^2||_F.
-// R receives I - Xt^2.
+// nnz_r receives the entry count of I - Xt^2 (of its lower triangle when sym).
 double thinned_residual_bound(Workspace &w, const DMat<double> &X, bool sym, double tol,
-                              DMat<double> &Xt, DMat<double> &R) {
+                              DMat<double> &Xt, int64_t *nnz_r) {
     const int64_t n = X.n;
     const double s_one_inf = sym ? 1.0 : std::sqrt(norm_one_inf(w, X));
     const double tau_c = tol / (16.0 * s_one_inf);
     filter<double, double>(w, X, tau_c, Xt, nullptr, &w.rs4);
-    product<double>(w, Xt, Xt, nullptr, -1.0, 0.0, 1.0, R, nullptr, &w.rs1, sym);
+    // only the norm of I - Xt^2 is needed: nothing is stored
+    *nnz_r = product_sumsq<double>(w, Xt, Xt, -1.0, 1.0, &w.rs1, sym);
     const std::vector<double> sums = w.sum_rows_many({&w.rs1, &w.rs4}, n);
     const double et = std::sqrt(sums[0]);
     const double delta = std::sqrt(sums[1]);
@@ -629,6 +690,7 @@ LoopOut nsf_loop(Workspace &w, DMat<V> &X, const LoopParams &p,
         // caller expects the first iterate to be converged already.)
         double e = -1.0;
         int e_bound = 0;
+        int64_t nnz_cert = 0;
         if constexpr (sizeof(V) == 8) {
             bool try_cert = p.stop_rule == 0 && k == 1 && p.cert_first;
             if (p.stop_rule == 0 && k >= 2) {
@@ -639,7 +701,7 @@ LoopOut nsf_loop(Workspace &w, DMat<V> &X, const LoopParams &p,
             if (try_cert) {
                 DMat<double> Xt;
                 Xt.bind(w.al);
-                const double b = thinned_residual_bound(w, X, sym, p.tol, Xt, R);
+                const double b = thinned_residual_bound(w, X, sym, p.tol, Xt, &nnz_cert);
                 if (b <= p.tol) { e = b; e_bound = 1; }
             }
         }
@@ -649,7 +711,8 @@ LoopOut nsf_loop(Workspace &w, DMat<V> &X, const LoopParams &p,
         }
         es.push_back(e);
         sign_iter_stats it{};
-        it.e = e; it.xfro = xf; it.nnz_x = X.nnz; it.nnz_r = R.nnz; it.fp32 = p.fp32;
+        it.e = e; it.xfro = xf; it.nnz_x = X.nnz; it.nnz_r = e_bound ? nnz_cert : R.nnz;
+        it.fp32 = p.fp32;
         it.e_bound = e_bound;
         out.iters = k - 1; out.e = e; out.xfro = xf;
         const bool conv = (p.stop_rule == 1) ? (d_prev < p.tol) : (e <= p.tol);

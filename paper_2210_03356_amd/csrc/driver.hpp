@@ -15,6 +15,8 @@ struct Workspace {
     Allocator *al;
     hipStream_t s;
     size_t staging_limit;  // bytes of gapped product output per batch
+    bool staging_auto;     // staging_limit follows the free memory (see auto_staging)
+    size_t auto_staging() const;
     DevBuf lo, span, cap, work, capoff, workoff, tmp, bins, counts, cursor, stage_col, stage_val;
     DevBuf rs1, rs2, rs3, rs4, icnt, hist, tau, bstar, seg, red, flag, zero_b;
     DevBuf cstat, mk, mm, mc, cv, mlen, cnext;
@@ -78,6 +80,14 @@ void product(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D,
              const uint8_t *row_sym = nullptr);
 // (row_sym: per-row flags instead of sym, for block-diagonal batches whose
 // symmetric blocks -- and only those -- take the symmetric route)
+
+// Per-row sums of squares of C = diag*I + coef*A*B into sq_out without storing C
+// (sym as in product: only the lower triangle is formed, the sums weighted so
+// that they are the full matrix's).  Returns the entry count of C (of its lower
+// triangle when sym).
+template <typename V>
+int64_t product_sumsq(Workspace &w, const DMat<V> &A, const DMat<V> &B, double coef,
+                      double diag, DevBuf *sq_out, bool sym);
 
 // C (full, compact) from the lower triangle L (compact) of a symmetric matrix
 // (or of the rows of its symmetric diagonal blocks flagged in lower.rows).

@@ -878,9 +878,11 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
                                               bucket_of(as_f64(v)) >= epi.keep_from);
                 const uint64_t m = __ballot(nz);
                 if (nz) {
-                    const int64_t pos = obase + o + lanes_below(m);
-                    out_col[pos] = wlo + s;
-                    out_val[pos] = v;
+                    if (!epi.no_store) {
+                        const int64_t pos = obase + o + lanes_below(m);
+                        out_col[pos] = wlo + s;
+                        out_val[pos] = v;
+                    }
                     y += sym_weight(low, wlo + s, i + r) * as_f64(v) * as_f64(v);
                 }
                 o += __popcll(m);

@@ -46,6 +46,7 @@ struct ProductEpi {
     double *sq_pre = nullptr;  // [row] sum of squares of the entries not stored
                                //    because of keep_from (weighted likewise)
     int short_b = 0;           // B's rows are short: each lane walks its own slot's row
+    int no_store = 0;          // form row lengths and sums of squares only, store nothing
 };
 
 struct BinCfg {

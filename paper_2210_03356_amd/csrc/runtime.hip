@@ -70,6 +70,24 @@ void *Pool::get(size_t bytes) {
     const size_t b = align_up(bytes ? bytes : 1, kAlign);
     std::lock_guard<std::mutex> lk(mu_);
     auto it = free_.lower_bound(b);
+    if (b >= kSegment && it != free_.end() && it->second->size > b + b / 4) {
+        // a large request that would split a much larger cached block: take a
+        // segment of its own while HIP has room, so that the block's tail is
+        // not stranded next to a live allocation (a segment is returned only
+        // when wholly free)
+        char *p = nullptr;
+        if (hipMalloc((void **)&p, align_up(b, size_t(2) << 20)) == hipSuccess) {
+            const size_t want = align_up(b, size_t(2) << 20);
+            Block *blk = new Block{p, want, false, nullptr, nullptr, (int)segs_.size()};
+            segs_.push_back({p, want});
+            seg_head_.push_back(blk);
+            insert_free(blk);
+            it = free_.lower_bound(b);
+            while (it->second != blk) ++it;
+        } else {
+            (void)hipGetLastError();
+        }
+    }
     if (it == free_.end()) {
         // a new segment: exactly the request when large, else a shared segment
         const size_t want = b >= kSegment ? align_up(b, size_t(2) << 20) : kSegment;
@@ -82,8 +100,15 @@ void *Pool::get(size_t bytes) {
         }
         if (e != hipSuccess) {
             (void)hipGetLastError();
+            size_t fr = 0, tot = 0;
+            if (hipMemGetInfo(&fr, &tot) != hipSuccess) (void)hipGetLastError();
+            size_t used = 0;
+            for (const auto &u : used_) used += u.second->size;
             throw Error(SIGN_ENOMEM, "device allocation of " + std::to_string(want) +
-                                         " bytes failed");
+                                         " bytes failed (pool: " + std::to_string(used) +
+                                         " bytes in use, " + std::to_string(cached_) +
+                                         " cached; device: " + std::to_string(fr) + " of " +
+                                         std::to_string(tot) + " free)");
         }
         Block *blk = new Block{p, want, false, nullptr, nullptr, (int)segs_.size()};
         segs_.push_back({p, want});
@@ -137,6 +162,13 @@ void Pool::trim() {
     release_free_segments(~size_t(0));
 }
 
+size_t Pool::used_bytes() {
+    std::lock_guard<std::mutex> lk(mu_);
+    size_t used = 0;
+    for (const auto &u : used_) used += u.second->size;
+    return used;
+}
+
 size_t Pool::cached_bytes() {
     std::lock_guard<std::mutex> lk(mu_);
     return cached_;
@@ -171,18 +203,35 @@ DevBuf &DevBuf::operator=(DevBuf &&o) noexcept {
 }
 
 void DevBuf::ensure(size_t bytes, size_t keep_bytes) {
+    // a large buffer whose contents are not kept and that would be less than
+    // half used is given back and allocated anew at the new size: iterates
+    // trade buffers (swaps) and would otherwise each keep the largest size any
+    // of them ever had
+    constexpr size_t kShrinkFrom = size_t(1) << 30;
+    if (p_ && !keep_bytes && bytes_ >= kShrinkFrom && bytes < bytes_ / 2) {
+        SFN_HIP(hipStreamSynchronize(al_->stream));
+        al_->put(p_);
+        p_ = nullptr;
+        bytes_ = 0;
+    }
     if (bytes <= bytes_ && p_) return;
-    // grow geometrically so repeated growth stays cheap
-    size_t want = std::max(bytes, bytes_ + bytes_ / 2);
+    // grow geometrically so repeated growth stays cheap, by at most a quarter
+    // beyond the request (these buffers reach tens of GB)
+    const size_t want = std::max(bytes, std::min(bytes_ + bytes_ / 2, bytes + bytes / 4));
+    if (p_ && !keep_bytes) {
+        // nothing to keep: release the old block first, so both never coexist
+        SFN_HIP(hipStreamSynchronize(al_->stream));
+        al_->put(p_);
+        p_ = nullptr;
+        bytes_ = 0;
+    }
     void *np = al_->get(want);
-    if (p_ && keep_bytes) {
+    if (p_) {
         SFN_HIP(hipMemcpyAsync(np, p_, std::min(keep_bytes, bytes_), hipMemcpyDeviceToDevice,
                                al_->stream));
         SFN_HIP(hipStreamSynchronize(al_->stream));
-    } else if (p_) {
-        SFN_HIP(hipStreamSynchronize(al_->stream));
+        al_->put(p_);
     }
-    if (p_) al_->put(p_);
     p_ = np;
     bytes_ = want;
 }

@@ -45,6 +45,7 @@ class Pool {
     void put(void *p);
     void trim();             // return entirely free segments to the driver
     size_t cached_bytes();   // free bytes held in segments
+    size_t used_bytes();     // bytes handed out and not yet returned
 
   private:
     struct Block {
@@ -85,7 +86,9 @@ class DevBuf {
     DevBuf &operator=(DevBuf &&o) noexcept;
     ~DevBuf() { reset(); }
     void bind(Allocator *a) { al_ = a; }
-    // ensure at least `bytes`; contents are kept only if keep_bytes > 0 (prefix copied)
+    // ensure at least `bytes`; contents are kept only if keep_bytes > 0 (prefix copied);
+    // without keep_bytes, a buffer of 1 GB or more that would be less than half used
+    // is reallocated at the new size
     void ensure(size_t bytes, size_t keep_bytes = 0);
     void reset();
     void *get() const { return p_; }

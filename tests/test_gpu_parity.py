@@ -267,6 +267,26 @@ def test_certified_last_residual(sf, name):
     assert e_full <= last["e"] <= kw["tol"], (e_full, last["e"])
     assert r.stats()["res_fro"] == last["e"]
 
+
+@pytest.mark.parametrize("group", ["4", "8"])
+@pytest.mark.parametrize("name", ["lap2d_48", "convdiff_30"])
+def test_products_in_many_batches(sf, monkeypatch, name, group):
+    """A staging budget of 1 MB splits every product into many row batches, whose
+    cursors and merged group lists cover only the batch's A entries: the solve
+    gives what the one-batch solve gives."""
+    monkeypatch.setenv("SIGNFN_ROW_GROUP", group)
+    make, kw = CASES[name]
+    A = make()
+    one = sf.sign_ns(_dev(sf, A), sf.default_opts(**kw))
+    many = sf.sign_ns(_dev(sf, A), sf.default_opts(staging_bytes=1 << 20, **kw))
+    assert one.status == "OK" and many.status == "OK"
+    assert many.stats()["iters"] == one.stats()["iters"]
+    X1, X2 = one.to_scipy(), many.to_scipy()
+    assert sp.linalg.norm(X2 - X1) <= 1e-13 * sp.linalg.norm(X1)
+    # the same arithmetic row by row: every product is the oracle's within rounding
+    ref = oracle.nsf(A, **kw).to_scipy()
+    assert sp.linalg.norm(X2 - ref) <= 1e-10 * sp.linalg.norm(ref)
+
 NMF_CASES = {
     "lap2d_10": (lambda: W.laplacian_2d(10, jitter=0.05, seed=2, m=8.0), {}),
     "lap2d_24": (lambda: W.laplacian_2d(24, jitter=0.05, seed=2, m=8.0), {}),
