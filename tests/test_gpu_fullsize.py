@@ -165,42 +165,6 @@ def test_c4_scaled_against_dense_sign(sf, precision, rel_tol):
     assert abs(np.trace(X) - A.meta["inertia"]) <= 1e-6
 
 
-def test_c4_named_size_mixed(sf):
-    """3D 7-point on the named 64^3 (n = 262,144) in mixed precision, the largest
-    solve here (a result of about 2.5e9 entries): X^2 = I and XA = AX on sampled
-    rows, trace = inertia, and the residual bound reached.  (No dense patch sign
-    is affordable for 3D rows at this accuracy; 16^3 carries the whole-matrix check.)"""
-    sf.release_cached()
-    A = W.config_matrix("c4")
-    assert A.n == 64 ** 3
-    res = sf.sign_ns(sf.DeviceCsr.from_host(A),
-                     sf.default_opts(tol=1e-10, filter_y=1, precision=1))
-    assert res.status == "OK"
-    assert res.stats()["res_fro"] <= 1e-10
-    rows = _rows(A)
-    sq, comm = _properties(res, A, rows)
-    assert sq <= 1e-8, sq
-    assert comm <= 1e-8, comm
-    assert abs(_trace_chunked(res) - A.meta["inertia"]) <= 1e-6 * A.n
-    del res
-    sf.release_cached()
-
-
-def _trace_chunked(res):
-    """trace(X) for results beyond 2^31 entries (torch masks overflow there)."""
-    import torch
-    import paper_2210_03356_amd as pkg
-    pkg.release_cached()
-    rp, ci, va = res.to_torch()
-    t, step = 0.0, 1 << 26
-    for s0 in range(0, ci.numel(), step):
-        s1 = min(ci.numel(), s0 + step)
-        pos = torch.arange(s0, s1, device=rp.device, dtype=torch.int64)
-        row = torch.searchsorted(rp, pos, right=True) - 1
-        t += float(torch.where(ci[s0:s1].long() == row, va[s0:s1].double(), 0.0).sum())
-    return t
-
-
 def test_c1_full_against_closed_form(sf):
     """1D tridiag(-1, 0, -1), n = 1024, stop rule on the step: the whole result
     against the sine-basis closed form."""
