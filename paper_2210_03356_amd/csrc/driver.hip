@@ -212,7 +212,10 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
 
     // batches of rows whose reserved output fits the staging budget
     const size_t entry = sizeof(int32_t) + sizeof(V);
-    if (w.staging_auto) w.staging_limit = w.auto_staging();  // memory use changes as iterates grow
+    // memory use changes as iterates grow: the budget follows it for products
+    // that need more than a gigabyte of staging (smaller ones keep the last one)
+    if (w.staging_auto && (double)total_cap * (double)entry > (double)(size_t(1) << 30))
+        w.staging_limit = w.auto_staging();
     const int64_t budget = std::max<int64_t>((int64_t)(w.staging_limit / entry), n);
     if (w.progress && total_cap > (int64_t)1 << 30 && !w.al->alloc)
         w.note("product: %lld rows, %lld reserved entries, staging %.1f GB, pool %.1f GB in use, "

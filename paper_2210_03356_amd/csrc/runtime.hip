@@ -23,6 +23,7 @@ namespace {
 constexpr size_t kAlign = 512;                     // sub-allocation granularity
 constexpr size_t kMinSplit = size_t(1) << 20;      // smallest remainder kept as a block
 constexpr size_t kSegment = size_t(2) << 30;       // segment size for small requests
+constexpr size_t kHuge = size_t(8) << 30;          // requests that get a segment of their own
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 }  // namespace
 
@@ -70,11 +71,12 @@ void *Pool::get(size_t bytes) {
     const size_t b = align_up(bytes ? bytes : 1, kAlign);
     std::lock_guard<std::mutex> lk(mu_);
     auto it = free_.lower_bound(b);
-    if (b >= kSegment && it != free_.end() && it->second->size > b + b / 4) {
-        // a large request that would split a much larger cached block: take a
+    if (b >= kHuge && it != free_.end() && it->second->size > b + b / 4) {
+        // a huge request that would split a much larger cached block: take a
         // segment of its own while HIP has room, so that the block's tail is
         // not stranded next to a live allocation (a segment is returned only
-        // when wholly free)
+        // when wholly free).  Smaller requests reuse cached blocks: a fresh
+        // hipMalloc for each would cost more than the memory it saves.
         char *p = nullptr;
         if (hipMalloc((void **)&p, align_up(b, size_t(2) << 20)) == hipSuccess) {
             const size_t want = align_up(b, size_t(2) << 20);
