@@ -625,6 +625,24 @@ double nmf_budget(double e, double xfro, double zfro, double tol, double c_fixed
 }
 
 namespace {
+// Dst = Src (compact FP64), a device copy
+void copy_mat(Workspace &w, const DMat<double> &Src, DMat<double> &Dst) {
+    const int64_t n = Src.n;
+    Dst.ensure_rows(n);
+    Dst.ensure_entries(Src.nnz);
+    SFN_HIP(hipMemcpyAsync(Dst.begp(), Src.begp(), sizeof(int64_t) * (n + 1),
+                           hipMemcpyDeviceToDevice, w.s));
+    SFN_HIP(hipMemcpyAsync(Dst.lenp(), Src.lenp(), sizeof(int32_t) * n, hipMemcpyDeviceToDevice,
+                           w.s));
+    if (Src.nnz > 0) {
+        SFN_HIP(hipMemcpyAsync(Dst.colp(), Src.colp(), sizeof(int32_t) * Src.nnz,
+                               hipMemcpyDeviceToDevice, w.s));
+        SFN_HIP(hipMemcpyAsync(Dst.valp(), Src.valp(), sizeof(double) * Src.nnz,
+                               hipMemcpyDeviceToDevice, w.s));
+    }
+    Dst.nnz = Src.nnz;
+}
+
 // ||X||_1 * ||X||_inf of a compact FP64 matrix
 double norm_one_inf(Workspace &w, const DMat<double> &X) {
     const int64_t n = X.n;
@@ -854,7 +872,14 @@ LoopOut nmf_loop(Workspace &w, DMat<double> &X, const LoopParams &p,
         }
         // Z ~ X^_k^{-1} by filtered Newton-Schulz inversion Z <- Z + Z (I - X^_k Z)
         double r = std::numeric_limits<double>::infinity();
-        if (have_z) {
+        if (e < 0.5) {
+            // near convergence X^_k is its own best inverse guess: ||I - X^_k Z_0||
+            // is then e_k itself, and I - X^_k Z_0 = R^_k is already formed
+            copy_mat(w, X, Z);
+            std::swap(T, R);
+            r = e;
+            have_z = true;
+        } else if (have_z) {
             product<double>(w, X, Z, nullptr, -1.0, 0.0, 1.0, T, nullptr, &w.rs1);
             r = std::sqrt(w.sum_rows(w.rs1, n));
             if (!(r < 0.5)) have_z = false;
@@ -880,6 +905,7 @@ LoopOut nmf_loop(Workspace &w, DMat<double> &X, const LoopParams &p,
         }
         inner_steps += steps;
         have_z = true;
+        w.note("newton k=%d: %d inverse steps to %.3e", k, steps, r);
         row_sumsq(w, Z, w.rs2);
         const double zf = std::sqrt(w.sum_rows(w.rs2, n));
         // Xbar_{k+1} = 1/2 (X^_k + X^_k^{-1})  (Alg. 3.1.1 step 3)
