@@ -1055,14 +1055,6 @@ __global__ void k_row_segments(const int64_t *seg_rows, int32_t *row_seg) {
     if (r < seg_rows[s + 1]) row_seg[r] = s;
 }
 
-__global__ void k_shift_cols(const int64_t *rp, const int32_t *row_seg, const int32_t *delta,
-                             int64_t n, int32_t *col) {
-    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
-    if (i >= n) return;
-    const int d = delta[row_seg[i]];
-    for (int64_t p = rp[i] + lane_id(); p < rp[i + 1]; p += kWave) col[p] += d;
-}
-
 // ---------------------------------------------------------------------------
 // identity, column norms, transpose (filtered Newton: inverse start)
 // ---------------------------------------------------------------------------
@@ -1668,23 +1660,11 @@ template void launch_scatter_keep<float, double>(MatView<float>, const int32_t *
 template void launch_scatter_keep<double, float>(MatView<double>, const int32_t *, const int *,
                                                  const int64_t *, int32_t *, float *, hipStream_t);
 
-void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
-    if (n > 0) k_fill<int32_t><<<blocks_for(n, 256), 256, 0, s>>>(p, n, v);
-}
-void launch_fill_f64(double *p, int64_t n, double v, hipStream_t s) {
-    if (n > 0) k_fill<double><<<blocks_for(n, 256), 256, 0, s>>>(p, n, v);
-}
-
 void launch_row_segments(const int64_t *seg_rows, int nseg, int64_t max_seg_rows, int32_t *row_seg,
                          hipStream_t s) {
     if (nseg <= 0 || max_seg_rows <= 0) return;
     dim3 grid(blocks_for(max_seg_rows, 256), nseg);
     k_row_segments<<<grid, 256, 0, s>>>(seg_rows, row_seg);
-}
-
-void launch_shift_cols(const int64_t *rp, const int32_t *row_seg, const int32_t *delta,
-                       int64_t n, int32_t *col, hipStream_t s) {
-    if (n > 0) k_shift_cols<<<blocks_for(n, 4), 256, 0, s>>>(rp, row_seg, delta, n, col);
 }
 
 }  // namespace sfn

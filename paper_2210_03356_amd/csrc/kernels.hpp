@@ -185,14 +185,9 @@ void launch_scatter_keep(MatView<V> X, const int32_t *row_seg, const int *bstar,
                          const int64_t *dst_ptr, int32_t *dcol, Vo *dval, hipStream_t s);
 
 // ---- misc -----------------------------------------------------------------------
-void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
-void launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
 // row_seg[r] = s for rows of segment s
 void launch_row_segments(const int64_t *seg_rows, int nseg, int64_t max_seg_rows, int32_t *row_seg,
                          hipStream_t s);
-// Add delta[seg] to the columns of each row (block-diagonal relayout).
-void launch_shift_cols(const int64_t *rp, const int32_t *row_seg, const int32_t *delta,
-                       int64_t n, int32_t *col, hipStream_t s);
 
 // ---- batch relayout (serving) -------------------------------------------------
 // Row block [src_row, src_row + nrows) of src moves to [dst_row, ...) of the
