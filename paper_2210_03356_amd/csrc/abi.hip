@@ -152,8 +152,8 @@ LoopOut mixed_precision(Workspace &w, const sign_csr *A, double c, const sign_op
         iters += lo.iters;
     }
     if (o.refine_steps > 0) {
-        DMat<double> As, P, Cm, Xb, Xn;
-        for (DMat<double> *m : {&As, &P, &Cm, &Xb, &Xn}) m->bind(w.al);
+        DMat<double> As, P, Cm, Cf, Xb, Xn;
+        for (DMat<double> *m : {&As, &P, &Cm, &Cf, &Xb, &Xn}) m->bind(w.al);
         load_scaled<double>(w, A, 1.0 / c, As);
         row_sumsq(w, As, w.rs3);
         const double af = std::sqrt(w.sum_rows(w.rs3, n));
@@ -184,6 +184,11 @@ LoopOut mixed_precision(Workspace &w, const sign_csr *A, double c, const sign_op
             const double omega = 1.0 / (2.0 * mean_abs);
             P = DMat<double>();  // not needed until the next sweep: give its memory back
             P.bind(w.al);
+            // C thinned by G with ||G||_F <= tol mean|lambda| / 16: the correction then
+            // moves by omega X G, which changes ||I - X^2|| by at most about
+            // 2 omega ||G|| = ||G|| / mean|lambda| <= tol/16 (||X||_2 ~ 1), and C's
+            // smallest entries (at the edge of its pattern) need not be multiplied
+            filter<double, double>(w, Cm, o.tol * mean_abs / 16.0, Cf, nullptr, nullptr);
             // X - omega X C, filtered with the fixed budget; the product forms the
             // filter's histogram and stores only entries some cut could keep
             const double tau = o.c_fixed * o.tol;
@@ -192,11 +197,12 @@ LoopOut mixed_precision(Workspace &w, const sign_csr *A, double c, const sign_op
             SFN_HIP(hipMemsetAsync(w.hist.get(), 0, sizeof(uint64_t) * kBuckets, w.s));
             SFN_HIP(hipMemsetAsync(w.rs5.get(), 0, sizeof(double) * n, w.s));
             const FusedFilter fuse{tau, w.hist.as<uint64_t>(), w.rs5.as<double>()};
-            product<double>(w, X, Cm, &X, -omega, 1.0, 0.0, Xb, nullptr, nullptr, false, false,
+            product<double>(w, X, Cf, &X, -omega, 1.0, 0.0, Xb, nullptr, nullptr, false, false,
                             &fuse);
             filter<double, double>(w, Xb, tau, Xn, nullptr, nullptr, 0, true);
-            w.note("refine sweep %d: estimated error %.3e, nnz C %lld, X %lld (%.1f ms)", sweep,
-                   est, (long long)Cm.nnz, (long long)Xn.nnz, 1e3 * (now_s() - t0));
+            w.note("refine sweep %d: estimated error %.3e, nnz C %lld -> %lld, X %lld (%.1f ms)",
+                   sweep, est, (long long)Cm.nnz, (long long)Cf.nnz, (long long)Xn.nnz,
+                   1e3 * (now_s() - t0));
             std::swap(X, Xn);
             p64.sym = 0;  // X - w X [A, X] is not exactly symmetric
         }
