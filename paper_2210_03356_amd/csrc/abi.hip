@@ -131,6 +131,9 @@ LoopOut mixed_precision(Workspace &w, const sign_csr *A, double c, const sign_op
     LoopParams p32{o.tol, o.c_fixed, o.switch_res, 0, o.max_iter, o.filter_y, 1};
     p32.sym = w.allow_sym && is_symmetric<float>(w, X32);
     p32.tol = std::max(o.tol, 32.0 * 5.960464477539063e-08 * std::sqrt((double)n));
+    // the FP32 phase ends when its next residual is predicted below tol32/4; the
+    // FP64 polish forms that residual anyway, so the FP32 one is not formed
+    p32.predict_stop = o.polish_steps > 0 ? 1 : 0;
     const LoopOut l32 = nsf_loop<float>(w, X32, p32, trace);
     convert<float, double>(w, X32, X);
     X32 = DMat<float>();

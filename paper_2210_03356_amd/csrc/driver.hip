@@ -700,6 +700,18 @@ LoopOut nsf_loop(Workspace &w, DMat<V> &X, const LoopParams &p,
             out.xfro = xf;
             break;
         }
+        if (p.predict_stop && p.stop_rule == 0 && k >= 2) {
+            // Lemma 2.1.1 and the last cut bound e_k by about 3/4 e_{k-1}^2 + 2||F_k||
+            const double ep = es.back();
+            const double pred = 0.75 * ep * ep * (1.0 + ep / 3.0) + 2.5 * ff_prev;
+            if (pred <= 0.25 * p.tol) {
+                out.status = SIGN_OK;
+                out.iters = k - 1;
+                out.xfro = xf;
+                out.e = pred;
+                break;
+            }
+        }
         // residual of the current iterate: R^_k = I - X^_k^2
         // symmetric products keep X^ exactly symmetric only when R^ stays the
         // exact polynomial I - X^2 (R^ not filtered): then X^R^ is symmetric too

@@ -145,6 +145,9 @@ struct LoopParams {
     int check_last = 1;
     // 1: certify the first residual from a thinned copy too (FP64; see nsf_loop)
     int cert_first = 0;
+    // 1: stop, without forming it, once the next residual is predicted at most
+    // tol/4 (a caller that forms it itself, in higher precision; status SIGN_OK)
+    int predict_stop = 0;
 };
 
 struct LoopOut {
