@@ -643,6 +643,13 @@ void copy_mat(Workspace &w, const DMat<double> &Src, DMat<double> &Dst) {
     Dst.nnz = Src.nnz;
 }
 
+// ||M||_inf (largest absolute row sum) of a compact FP64 matrix
+double inf_norm(Workspace &w, const DMat<double> &M) {
+    w.rs4.ensure(sizeof(double) * std::max<int64_t>(M.n, 1));
+    launch_row_abs_sum(M.begp(), M.valp(), 0, M.n, w.rs4.as<double>(), w.s);
+    return w.max_rows(w.rs4, M.n);
+}
+
 // ||X||_1 * ||X||_inf of a compact FP64 matrix
 double norm_one_inf(Workspace &w, const DMat<double> &X) {
     const int64_t n = X.n;
@@ -840,8 +847,8 @@ void transpose(Workspace &w, const DMat<double> &X, DMat<double> &Out) {
 LoopOut nmf_loop(Workspace &w, DMat<double> &X, const LoopParams &p,
                  std::vector<sign_iter_stats> &trace, int &inner_steps) {
     const int64_t n = X.n;
-    DMat<double> I, R, Z, T, Zb, Xb, Xn, D;
-    for (DMat<double> *m : {&I, &R, &Z, &T, &Zb, &Xb, &Xn, &D}) m->bind(w.al);
+    DMat<double> I, R, Z, T, T2, Zb, Xb, Xn, D;
+    for (DMat<double> *m : {&I, &R, &Z, &T, &T2, &Zb, &Xb, &Xn, &D}) m->bind(w.al);
     I.ensure_rows(n);
     I.ensure_entries(n);
     launch_identity(n, I.begp(), I.lenp(), I.colp(), I.valp(), w.s);
@@ -882,21 +889,41 @@ LoopOut nmf_loop(Workspace &w, DMat<double> &X, const LoopParams &p,
             w.report("newton", k, it);
             break;
         }
-        // Z ~ X^_k^{-1} by filtered Newton-Schulz inversion Z <- Z + Z (I - X^_k Z)
+        // Z ~ X^_k^{-1} by filtered Newton-Schulz inversion Z <- Z + Z (I - X^_k Z).
+        // Its residual T = I - X^_k Z squares every step, so it converges from any
+        // start with ||T_0|| < 1 in a submultiplicative norm; a start is taken when
+        // ||T_0||_inf < 1/2, in this order of preference:
+        //  - X^_k itself (T_0 = R^_k, already formed): near convergence X^-1 ~ X;
+        //  - the previous inverse Z or 2Z: for an eigenvalue x of the previous
+        //    iterate the new one is (x + 1/x)/2, and I - X^_k Z and I - 2 X^_k Z have
+        //    eigenvalues (1 - 1/x^2)/2 and -1/x^2, so 2Z is the better start while
+        //    |x| > sqrt(3) (the early steps from an unscaled A), Z after;
+        //  - X^T / (||X||_1 ||X||_inf), which always converges.
         double r = std::numeric_limits<double>::infinity();
-        if (e < 0.5) {
-            // near convergence X^_k is its own best inverse guess: ||I - X^_k Z_0||
-            // is then e_k itself, and I - X^_k Z_0 = R^_k is already formed
+        bool started = false;
+        if (inf_norm(w, R) < 0.5) {
             copy_mat(w, X, Z);
             std::swap(T, R);
             r = e;
-            have_z = true;
+            started = true;
         } else if (have_z) {
             product<double>(w, X, Z, nullptr, -1.0, 0.0, 1.0, T, nullptr, &w.rs1);
-            r = std::sqrt(w.sum_rows(w.rs1, n));
-            if (!(r < 0.5)) have_z = false;
+            const double r1 = std::sqrt(w.sum_rows(w.rs1, n));
+            const double n1 = inf_norm(w, T);
+            // I - 2 X^_k Z = 2T - I
+            product<double>(w, I, T, nullptr, 2.0, 0.0, -1.0, T2, nullptr, &w.rs2);
+            const double n2 = inf_norm(w, T2);
+            if (n2 < n1 && n2 < 0.5) {
+                launch_scale_copy<double, double>(Z.valp(), Z.valp(), Z.nnz, 2.0, w.s);
+                std::swap(T, T2);
+                r = std::sqrt(w.sum_rows(w.rs2, n));
+                started = true;
+            } else if (n1 < 0.5) {
+                r = r1;
+                started = true;
+            }
         }
-        if (!have_z) {
+        if (!started) {
             // Z_0 = X^T / (||X||_1 ||X||_inf): ||I - X Z_0||_2 < 1 for nonsingular X
             const double sc = norm_one_inf(w, X);
             transpose(w, X, Z);
@@ -904,6 +931,7 @@ LoopOut nmf_loop(Workspace &w, DMat<double> &X, const LoopParams &p,
             product<double>(w, X, Z, nullptr, -1.0, 0.0, 1.0, T, nullptr, &w.rs1);
             r = std::sqrt(w.sum_rows(w.rs1, n));
         }
+        have_z = true;
         int steps = 0;
         double r_prev = std::numeric_limits<double>::infinity();
         while (r > target && steps < 200 && !(r < 1e-8 && r > 0.5 * r_prev)) {
