@@ -296,6 +296,7 @@ def main():
     torch.cuda.set_device(0)
     sf.load()
     A, kw = build_workload(args.config, args.grid)
+    g = args.grid or {"c1": 0, "c2": 256, "c3": 512, "c4": 64}[args.config]  # grid side
     if args.filter_y is not None:
         kw["filter_y"] = args.filter_y
     opts = sf.default_opts(precision=args.precision, **kw)
@@ -380,10 +381,10 @@ def main():
         "dtype": "f64" if args.precision == 0 else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"{args.config}: " + {
-            "c1": "1D tridiag(-1,0,-1)",
-            "c2": "2D 5-point 256x256 - (4+U[-.05,.05]) + 8*stagger",
-            "c3": "2D upwind conv-diff 512x512, beta*h, - 4 + 8*stagger",
-            "c4": "3D 7-point 64^3 - 6 + U[-.5,.5] + 12*stagger"}[args.config],
+            "c1": f"1D tridiag(-1,0,-1), n={A.n}",
+            "c2": f"2D 5-point {g}x{g} - (4+U[-.05,.05]) + 8*stagger",
+            "c3": f"2D upwind conv-diff {g}x{g}, beta*h, - 4 + 8*stagger",
+            "c4": f"3D 7-point {g}^3 - 6 + U[-.5,.5] + 12*stagger"}[args.config],
             "n": A.n, "nnz": A.nnz, "tol": kw["tol"], "stop_rule": kw["stop_rule"],
             "filter_y": kw["filter_y"], "precision": args.precision, "method": args.method},
         "solves_per_s": round(1e3 / ms_per_step, 4),
@@ -391,6 +392,8 @@ def main():
         "inner_steps": st["inner_steps"],
         "nnz_result": st["nnz"],
         "products": int(agg["products"] / max(args.steps, 1)),
+        "products_per_s": round(agg["products"] / (agg["spgemm_ms"] * 1e-3), 1)
+        if agg["spgemm_ms"] > 0 else None,
         "spgemm_ms_per_step": round(agg["spgemm_ms"] / max(args.steps, 1), 2),
         "spgemm_gbs": round(agg["spgemm_bytes"] / (agg["spgemm_ms"] * 1e-3) / 1e9, 1)
         if agg["spgemm_ms"] > 0 else None,
