@@ -424,3 +424,31 @@ def test_thinned_residual_bound(oracle_lib, make, sym):
             else:
                 s = one_inf
             assert e <= (et + 2.0 * s * delta + delta * delta) * (1 + 1e-9) + 1e-14
+
+
+# ---------------------------------------------------------------------------
+# the inverse starts of the filtered Newton iteration: for X' = (X + X^-1)/2,
+# I - X' X^-1 = (I - X^-2)/2 and I - X' (2 X^-1) = -X^-2, and the inverse
+# Newton-Schulz residual squares every step (checked on dense matrices)
+# ---------------------------------------------------------------------------
+def test_newton_inverse_start_identities():
+    rng = np.random.default_rng(3)
+    n = 40
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.concatenate([rng.uniform(1.5, 9.0, n // 2), -rng.uniform(1.5, 9.0, n - n // 2)])
+    X = (Q * lam) @ Q.T
+    Xi = np.linalg.inv(X)
+    Xn = 0.5 * (X + Xi)
+    I = np.eye(n)
+    assert np.allclose(I - Xn @ Xi, 0.5 * (I - Xi @ Xi), atol=1e-12)
+    assert np.allclose(I - Xn @ (2.0 * Xi), -(Xi @ Xi), atol=1e-12)
+    # per eigenvalue, 2 X^-1 is the better start exactly when |x| > sqrt(3)
+    e1 = np.abs(0.5 * (1 - 1 / lam ** 2))
+    e2 = np.abs(1 / lam ** 2)
+    assert np.array_equal(e2 < e1, np.abs(lam) > math.sqrt(3))
+    # T_{j+1} = T_j^2 for Z_{j+1} = Z_j + Z_j T_j, T_j = I - X Z_j (any X, Z)
+    A = rng.standard_normal((n, n))
+    Z = 0.01 * rng.standard_normal((n, n))
+    T = I - A @ Z
+    Z1 = Z + Z @ T
+    assert np.allclose(I - A @ Z1, T @ T, atol=1e-10)
