@@ -155,12 +155,16 @@ LoopOut mixed_precision(Workspace &w, const sign_csr *A, double c, const sign_op
         iters += lo.iters;
     }
     if (o.refine_steps > 0) {
-        DMat<double> As, P, Cm, Cf, Xb, Xn;
-        for (DMat<double> *m : {&As, &P, &Cm, &Cf, &Xb, &Xn}) m->bind(w.al);
+        DMat<double> As;
+        As.bind(w.al);
         load_scaled<double>(w, A, 1.0 / c, As);
         row_sumsq(w, As, w.rs3);
         const double af = std::sqrt(w.sum_rows(w.rs3, n));
         for (int sweep = 0; sweep < o.refine_steps; ++sweep) {
+            // a sweep's matrices (and the previous X, swapped into Xn) are released
+            // at its end: only X and A carry over
+            DMat<double> P, Cm, Cf, Xb, Xn;
+            for (DMat<double> *m : {&P, &Cm, &Cf, &Xb, &Xn}) m->bind(w.al);
             const double t0 = now_s();
             w.note("refine sweep %d: X %lld entries", sweep, (long long)X.nnz);
             product<double>(w, As, X, nullptr, 1.0, 0.0, 0.0, P, nullptr, nullptr);
