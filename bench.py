@@ -212,6 +212,49 @@ def serve_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def gapless_bench(args):
+    """Gapless stress row: the literal (m = 0) matrix of a configuration, whose sign is
+    dense.  Reports the growth of nnz per iteration, the time per iteration and the
+    bytes an iterate and its residual would take at the configuration's full size; not a
+    parity case (there is no gap, so no accuracy claim)."""
+    import torch
+    import paper_2210_03356_amd as sf
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    sf.load()
+    cfg = args.config if args.config != "c1" else "c2"
+    A = W.config_matrix(cfg, N=args.grid or {"c2": 128, "c3": 128, "c4": 24}[cfg], literal=True)
+    tol = {"c2": 1e-12, "c3": 1e-12, "c4": 1e-10}[cfg]
+    opts = sf.default_opts(tol=tol, max_iter=args.gapless_iters,
+                           filter_y=1 if cfg in ("c3", "c4") else 0)
+    dA = sf.DeviceCsr.from_host(A, device="cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    status, trace, err = "?", [], None
+    try:
+        res = sf.sign_ns(dA, opts)
+        status, trace = res.status, res.trace()
+    except sf.SignError as e:  # out of memory is a finding here, not a failure
+        status, err = "ERROR", str(e)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    full_n = {"c2": 256 ** 2, "c3": 512 ** 2, "c4": 64 ** 3}[cfg]
+    rows = [{"k": i + 1, "e": t["e"], "nnz_x_per_row": round(t["nnz_x"] / A.n, 1),
+             "nnz_r_per_row": round(t["nnz_r"] / A.n, 1), "ms": round(t["ms"], 1)}
+            for i, t in enumerate(trace)]
+    dense_at = next((r["k"] for r in rows if r["nnz_x_per_row"] >= 0.5 * A.n), None)
+    line = {"metric": "gapless stress: nnz growth of the literal (m = 0) matrix",
+            "value": rows[-1]["nnz_x_per_row"] if rows else None, "unit": "nnz/row",
+            "higher_is_better": False, "n_gpus": 1, "data": "synthetic", "dtype": "f64",
+            "config": {"workload": f"{cfg} literal (m = 0), grid {int(round(A.n ** (1 / (3 if cfg == 'c4' else 2))))}",
+                       "n": A.n, "nnz": A.nnz, "tol": tol, "max_iter": args.gapless_iters},
+            "status": status, "error": err, "wall_s": round(wall, 2),
+            "iterations": rows, "half_dense_at_iteration": dense_at,
+            "full_size_dense_iterate_gb": round(12.0 * full_n * full_n / 1e9, 1)}
+    print(json.dumps(line), flush=True)
+
+
 def ode_bench(args):
     """Section 4.2 matrix [[0, B], [I, 0]], B = tridiag(1/16, 7/8, 1/16): NSF and
     unfiltered NS on the GPU, error against the closed form of eq. 1.26, and the
@@ -277,6 +320,9 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=50.0)
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--ode", action="store_true", help="Section 4.2 matrix benchmark instead")
+    ap.add_argument("--gapless", action="store_true",
+                    help="gapless stress row: the literal (m = 0) matrix, nnz growth per iteration")
+    ap.add_argument("--gapless-iters", type=int, default=10)
     ap.add_argument("--ode-sizes", type=int, nargs="*", default=None)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -286,6 +332,8 @@ def main():
         sys.exit(2)
     if args.serve:
         return serve_bench(args)
+    if args.gapless:
+        return gapless_bench(args)
     if args.ode:
         return ode_bench(args)
 
