@@ -182,6 +182,8 @@ def serve_bench(args):
                 if r is not None:
                     done[t] = (j, r.status, r.stats()["res_fro"])
                     del r
+                    if len(done) % 200 == 0:
+                        print(f"# served {len(done)}/{len(reqs)}", file=sys.stderr, flush=True)
         time.sleep(0.0005)
     wall = time.perf_counter() - t0
     st = srv.stats()
@@ -190,9 +192,11 @@ def serve_bench(args):
     # the same requests solved one by one (no batching), same GPU and tolerances
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    for A, r in zip(mats, reqs):
+    for q, (A, r) in enumerate(zip(mats, reqs)):
         res = sf.sign_ns(sf.DeviceCsr.from_host(A), sf.default_opts(tol=r["tol"]))
         del res
+        if (q + 1) % 200 == 0:
+            print(f"# sequential {q + 1}/{len(reqs)}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     seq = time.perf_counter() - t1
     line = {
