@@ -970,20 +970,31 @@ __device__ double bucket_hi(int b) {
     return ldexp(1.0 + (double)(j + 1) / 16.0, E);
 }
 
-__global__ void k_select(const uint64_t *hist, const double *tau, int nseg, int *bstar) {
+// One workgroup per segment: the bucket terms count_b * hi_b^2 are formed in
+// parallel into LDS (each the same FP64 operations as a sequential pass), then
+// one thread adds them in ascending order, uncontracted, and stops at the cut.
+constexpr int kSelectThreads = 256;
+__global__ __launch_bounds__(kSelectThreads) void k_select(const uint64_t *hist,
+                                                           const double *tau, int nseg,
+                                                           int *bstar) {
 #pragma clang fp contract(off)
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double add[kBucketTop];
+    const int s = blockIdx.x;
     if (s >= nseg) return;
     const uint64_t *c = hist + (int64_t)s * kBuckets;
+    for (int b = threadIdx.x; b < kBucketTop; b += kSelectThreads) {
+        const double h = bucket_hi(b);
+        const double hh = h * h;
+        add[b] = (double)c[b] * hh;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
     const double t2 = tau[s] * tau[s];
     double acc = 0.0;
     int b = 0;
     while (b < kBucketTop) {
-        const double h = bucket_hi(b);
-        const double hh = h * h;
-        const double add = (double)c[b] * hh;
-        if (acc + add > t2) break;
-        acc = acc + add;
+        if (acc + add[b] > t2) break;
+        acc = acc + add[b];
         ++b;
     }
     bstar[s] = b;
@@ -1627,7 +1638,7 @@ template void launch_histogram<float>(MatView<float>, const int64_t *, int, int6
                                       LowerRows, hipStream_t);
 
 void launch_select(const uint64_t *hist, const double *tau, int nseg, int *bstar, hipStream_t s) {
-    if (nseg > 0) k_select<<<blocks_for(nseg, 64), 64, 0, s>>>(hist, tau, nseg, bstar);
+    if (nseg > 0) k_select<<<nseg, kSelectThreads, 0, s>>>(hist, tau, nseg, bstar);
 }
 
 template <typename V>
