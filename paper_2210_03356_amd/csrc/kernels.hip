@@ -704,6 +704,10 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
         for (int t0 = wave * step; t0 < ml; t0 += NW * step) {
             const int t = t0 + lane;
             const bool own = lane < step && t < ml;
+            // after the first window a slot's next column alone says whether it has
+            // entries in this one: a batch with none skips its descriptor loads
+            // (its cursors stay as they are)
+            if (!first && !__ballot(own && cnext[mbeg + t] < whi)) continue;
             int bl = 0, cur = 0, nc = INT_MIN, msk = 0;
             int64_t bb = 0;
             V a[R];  // this lane's slot: coefficient of each row of the group (0 if absent)
