@@ -194,14 +194,14 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanChunk = kScanThreads * kScanItems;
 
-template <typename T>
+template <typename T, int NT = kScanThreads>
 __device__ int64_t block_excl_scan(int64_t v, int64_t *sh_w, int64_t *total) {
     const int lane = lane_id(), w = wave_id();
     const int64_t inc = wave_incl_scan(v);
     if (lane == kWave - 1) sh_w[w] = inc;
     __syncthreads();
     int64_t before = 0, tot = 0;
-    for (int q = 0; q < kScanThreads / kWave; ++q) {
+    for (int q = 0; q < NT / kWave; ++q) {
         if (q < w) before += sh_w[q];
         tot += sh_w[q];
     }
@@ -262,6 +262,32 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_final(const T *in, int64_
         run += vals[q];
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = init + part[nb];
+}
+
+// the whole scan in one workgroup, for n <= kScanOneMax: short arrays (small
+// matrices, few segments) then cost one launch instead of three
+constexpr int kScanOneThreads = 1024;
+constexpr int64_t kScanOneMax = (int64_t)kScanOneThreads * kScanItems;
+
+template <typename T>
+__global__ __launch_bounds__(kScanOneThreads) void k_scan_one(const T *in, int64_t n,
+                                                              int64_t init, int64_t *out) {
+    __shared__ int64_t shw[kScanOneThreads / kWave];
+    int64_t vals[kScanItems];
+    int64_t s = 0;
+    for (int q = 0; q < kScanItems; ++q) {
+        const int64_t i = (int64_t)threadIdx.x * kScanItems + q;
+        vals[q] = i < n ? (int64_t)in[i] : 0;
+        s += vals[q];
+    }
+    int64_t tot;
+    int64_t run = init + block_excl_scan<T, kScanOneThreads>(s, shw, &tot);
+    for (int q = 0; q < kScanItems; ++q) {
+        const int64_t i = (int64_t)threadIdx.x * kScanItems + q;
+        if (i < n) out[i] = run;
+        run += vals[q];
+    }
+    if (threadIdx.x == 0) out[n] = init + tot;
 }
 
 // ---------------------------------------------------------------------------
@@ -982,26 +1008,50 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const uint64_t *hist,
                                                            const double *tau, int nseg,
                                                            int *bstar) {
 #pragma clang fp contract(off)
-    __shared__ double add[kBucketTop];
+    constexpr int kBatch = 32;
+    constexpr int kPadded = (kBucketTop + kBatch - 1) / kBatch * kBatch;
+    __shared__ double add[kPadded];
     const int s = blockIdx.x;
     if (s >= nseg) return;
     const uint64_t *c = hist + (int64_t)s * kBuckets;
-    for (int b = threadIdx.x; b < kBucketTop; b += kSelectThreads) {
-        const double h = bucket_hi(b);
+    // zero terms past the top bucket: adding 0 never crosses the budget
+    for (int b = threadIdx.x; b < kPadded; b += kSelectThreads) {
+        const double h = b < kBucketTop ? bucket_hi(b) : 0.0;
         const double hh = h * h;
-        add[b] = (double)c[b] * hh;
+        add[b] = b < kBucketTop ? (double)c[b] * hh : 0.0;
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
+    // Ascending walk: the cut is the first bucket whose term takes the running
+    // sum past tau^2.  Terms are read in register batches; within a batch the
+    // running sums are formed first and compared afterwards: up to the first
+    // crossing they are the plain walk's sums, in its order, and the sums
+    // formed past it are discarded.  Only the additions sit on the dependent
+    // chain.
     const double t2 = tau[s] * tau[s];
     double acc = 0.0;
-    int b = 0;
-    while (b < kBucketTop) {
-        if (acc + add[b] > t2) break;
-        acc = acc + add[b];
-        ++b;
+    int b = kBucketTop;
+    for (int base = 0; base < kPadded; base += kBatch) {
+        double t[kBatch], ps[kBatch];
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) t[q] = add[base + q];
+        double a = acc;
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) {
+            a = a + t[q];
+            ps[q] = a;
+        }
+        int hit = kBatch;
+#pragma unroll
+        for (int q = kBatch - 1; q >= 0; --q)
+            if (ps[q] > t2) hit = q;
+        if (hit < kBatch) {
+            b = base + hit;
+            break;
+        }
+        acc = a;
     }
-    bstar[s] = b;
+    bstar[s] = b < kBucketTop ? b : kBucketTop;
 }
 
 template <typename V>
@@ -1141,7 +1191,9 @@ __global__ void k_add_len(const int32_t *a, const int32_t *b, int64_t n, int32_t
 template <typename V>
 __global__ void k_sym_place(MatView<V> L, LowerRows lower, const int64_t *cbeg, int32_t *ccol,
                             V *cval, const int64_t *toff, int32_t *fill, int32_t *tcol, V *tval) {
-    const int64_t j = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
+    // consecutive rows on one XCD: the mirror entries they append to a row c
+    // are then neighbours in that XCD's L2 and leave it as whole lines
+    const int64_t j = (int64_t)xcd_row(blockIdx.x, gridDim.x) * (blockDim.x / kWave) + wave_id();
     if (j >= L.n) return;
     const bool low = lower.of(j);
     const int64_t b = L.beg[j], o = cbeg[j];
@@ -1201,7 +1253,11 @@ __global__ __launch_bounds__(kRankThreads) void k_sym_rank(
     __syncthreads();  // red and wtot are reused below
     int done = 0;  // keys ranked in earlier chunks
     for (int64_t k0 = kmin; k0 <= kmax; k0 += kRankChunk) {
-        for (int q = threadIdx.x; q < NWORD; q += kRankThreads) bits[q] = 0u;
+        // words that can hold a key of this chunk; the others are neither
+        // cleared nor counted
+        const int64_t span = ((kmax - k0) >> 5) + 1;
+        const int nw = span < NWORD ? (int)span : NWORD;
+        for (int q = threadIdx.x; q < nw; q += kRankThreads) bits[q] = 0u;
         __syncthreads();
         for (int q = threadIdx.x; q < m; q += kRankThreads) {
             const int64_t d = (int64_t)tcol[tb + q] - k0;
@@ -1210,7 +1266,10 @@ __global__ __launch_bounds__(kRankThreads) void k_sym_rank(
         __syncthreads();
         // exclusive prefix of popcounts over the words (PER consecutive words per thread)
         int loc = 0;
-        for (int u = 0; u < PER; ++u) loc += __popc(bits[threadIdx.x * PER + u]);
+        for (int u = 0; u < PER; ++u) {
+            const int q = threadIdx.x * PER + u;
+            if (q < nw) loc += __popc(bits[q]);
+        }
         const int inc = (int)wave_incl_scan((int64_t)loc);
         if (lane == kWave - 1) wtot[wave] = inc;
         __syncthreads();
@@ -1220,8 +1279,11 @@ __global__ __launch_bounds__(kRankThreads) void k_sym_rank(
             total += wtot[w];
         }
         for (int u = 0; u < PER; ++u) {
-            wpre[threadIdx.x * PER + u] = before;
-            before += __popc(bits[threadIdx.x * PER + u]);
+            const int q = threadIdx.x * PER + u;
+            if (q < nw) {
+                wpre[q] = before;
+                before += __popc(bits[q]);
+            }
         }
         __syncthreads();
         for (int q = threadIdx.x; q < m; q += kRankThreads) {
@@ -1390,6 +1452,10 @@ static void scan_impl(const T *in, int64_t n, int64_t *out, int64_t *tmp, int64_
     const int64_t nb = (n + kScanChunk - 1) / kScanChunk;
     if (nb == 0) {
         k_fill<int64_t><<<1, 1, 0, s>>>(out, 1, init);
+        return;
+    }
+    if (n <= kScanOneMax) {
+        k_scan_one<T><<<1, kScanOneThreads, 0, s>>>(in, n, init, out);
         return;
     }
     k_scan_partial<T><<<(unsigned)nb, kScanThreads, 0, s>>>(in, n, tmp);
