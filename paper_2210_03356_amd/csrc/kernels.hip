@@ -605,6 +605,15 @@ __device__ __forceinline__ void gather_chunk(const MatView<V> &B, int64_t bb, in
     }
 }
 
+// Whether a chunk loaded at position p of a B row of length bl lies wholly
+// inside the window (all its entries exist and the last, the largest column,
+// is below whi); uniform over the wave.
+template <int U>
+__device__ __forceinline__ bool chunk_full(const int (&c)[U], int p, int bl, int whi) {
+    const int last = __builtin_amdgcn_readlane(c[U - 1], kWave - 1);
+    return p + U * kWave <= bl && last < whi;
+}
+
 // Adds one chunk loaded by gather_chunk at position p of a B row of length bl
 // (columns c, values bv) times the group's coefficients aq into the LDS windows
 // [wlo, whi) of the rows present at the slot (bits of mq; a uniform test).
@@ -804,16 +813,25 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
 #pragma unroll
                     for (int r = 0; r < R; ++r) aq[r] = rl_val(a[r], q);
                     const uint32_t mq = (uint32_t)rl_i32(msk, q);
-                    // the first chunk is accumulated straight after the next slot's
-                    // loads were issued; chunks after it are loaded on demand
+                    // A chunk lying wholly inside the window (its last entry in the
+                    // row and before whi) is followed by a refill from the same row:
+                    // that refill is issued before the chunk is accumulated, so its
+                    // latency overlaps the atomics (as the next slot's does).
+                    int cr[U];
+                    V br[U];
+                    if (chunk_full<U>(c, p, blq, whi))
+                        gather_chunk<V, U>(B, bbq, p + U * kWave, blq, lane, cr, br);
                     int nxt = INT_MAX;
                     int got = group_accumulate<V, R, T, U>(acc, c, bv, aq, mq, p, blq, wlo,
                                                            whi, lane, &nxt);
                     p += got;
-                    while (got == U * kWave) {
-                        gather_chunk<V, U>(B, bbq, p, blq, lane, c, bv);
+                    while (got == U * kWave) {  // the refill was issued above
+#pragma unroll
+                        for (int u = 0; u < U; ++u) { c[u] = cr[u]; bv[u] = br[u]; }
+                        if (chunk_full<U>(c, p, blq, whi))
+                            gather_chunk<V, U>(B, bbq, p + U * kWave, blq, lane, cr, br);
                         got = group_accumulate<V, R, T, U>(acc, c, bv, aq, mq, p, blq, wlo,
-                                                               whi, lane, &nxt);
+                                                           whi, lane, &nxt);
                         p += got;
                     }
                     // column of the first entry beyond the window, for the next one

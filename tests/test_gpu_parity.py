@@ -98,6 +98,16 @@ def test_spgemm_dense_rows_and_empty_rows(sf):
     _check_product(sf, A, A)
 
 
+@pytest.mark.parametrize("n", [2047, 2048, 2049, 8192, 8193])
+def test_spgemm_scan_boundaries(sf, n):
+    # row counts at the edges of one scan chunk (2048 entries) and of the
+    # one-workgroup scan (8192 entries): the product's capacities and row starts
+    # come from these scans
+    A = W.random_sparse(n, mean_row=4, seed=n)
+    B = W.random_sparse(n, mean_row=5, seed=n + 1)
+    _check_product(sf, A, B)
+
+
 def test_spgemm_tiny_and_identity(sf):
     one = W.Csr(n=1, indptr=np.array([0, 1], np.int64), indices=np.array([0], np.int32),
                 data=np.array([-3.0]))
@@ -134,10 +144,11 @@ def test_spgemm_fp32(sf):
     assert np.all(np.abs(va - ova) <= 2 ** -23 * 40 * bound)
 
 
-@pytest.mark.parametrize("seed", range(4))
-def test_filter_matches_oracle_selection(sf, seed):
+@pytest.mark.parametrize("seed,n", [(0, 3000), (1, 3000), (2, 3000), (3, 3000),
+                                    (4, 8192), (5, 8193), (6, 1)])
+def test_filter_matches_oracle_selection(sf, seed, n):
     rng = np.random.default_rng(seed)
-    A = W.random_sparse(3000, mean_row=20, seed=seed + 50)
+    A = W.random_sparse(n, mean_row=20, seed=seed + 50)
     A.data = np.exp(rng.uniform(-80, 1, A.nnz)) * rng.choice([-1, 1], A.nnz)
     A.data[A.data > 1] = 0.75
     tau = float(np.exp(rng.uniform(-60, -5)))
