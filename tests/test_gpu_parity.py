@@ -108,6 +108,32 @@ def test_spgemm_scan_boundaries(sf, n):
     _check_product(sf, A, B)
 
 
+@pytest.mark.parametrize("blen", [255, 256, 257, 512, 768])
+def test_spgemm_chunk_sized_b_rows(sf, blen):
+    # B rows of whole and almost whole 256-entry chunks (one gather step of the
+    # product kernel): a chunk that exactly fills the row or the window is followed
+    # by an empty or partial refill; A mixes short and long rows, so both the
+    # single-row and the row-group kernels read them
+    n = 4096
+    rng = np.random.default_rng(blen)
+    starts = rng.integers(0, n - blen, size=n)
+    B = sp.csr_matrix((rng.uniform(0.5, 1.5, n * blen),
+                       (np.repeat(np.arange(n), blen),
+                        (starts[:, None] + np.arange(blen)[None, :]).ravel())), shape=(n, n))
+    B.sort_indices()
+    rows, cols = [], []
+    for i in range(n):
+        k = 60 if i % 5 == 0 else int(rng.integers(1, 6))
+        c = np.unique(np.clip(i + rng.integers(-300, 300, size=k), 0, n - 1))
+        rows.append(np.full(len(c), i)); cols.append(c)
+    r = np.concatenate(rows); c = np.concatenate(cols)
+    A = sp.csr_matrix((rng.uniform(0.5, 1.5, len(r)), (r, c)), shape=(n, n))
+    A.sort_indices()
+    to_csr = lambda M: W.Csr(n=n, indptr=M.indptr.astype(np.int64),
+                             indices=M.indices.astype(np.int32), data=M.data)
+    _check_product(sf, to_csr(A), to_csr(B))
+
+
 def test_spgemm_tiny_and_identity(sf):
     one = W.Csr(n=1, indptr=np.array([0, 1], np.int64), indices=np.array([0], np.int32),
                 data=np.array([-3.0]))
