@@ -187,7 +187,7 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
     SFN_HIP(hipMemcpyAsync(&tot[1], w.workoff.as<int64_t>() + n, sizeof(int64_t),
                            hipMemcpyDeviceToHost, s));
     unsigned long long pst[2] = {0, 0};
-    if (w.auto_group) {
+    if (w.auto_group || w.progress) {  // (progress: reported with the product)
         w.pst.ensure(2 * sizeof(unsigned long long));
         SFN_HIP(hipMemsetAsync(w.pst.get(), 0, 2 * sizeof(unsigned long long), s));
         launch_row_density<V>(B.view(), w.pst.as<unsigned long long>(), s);
@@ -264,14 +264,21 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
     // row groups need A compact (rows i .. i+g-1 adjacent in storage) -- every
     // matrix built here is; the merged lists reuse A's index range
     // Groups of 8 rows (2048-column windows) halve the B traffic of groups of 4
-    // (4096), but every window costs a pass over the group's slots.  Where a B
-    // row holds few entries per window -- density within its column range
-    // times 2048 below ~200 -- that pass dominates and groups of 4 are faster
-    // (measured on the 2D workloads: 256^2 FP64 products favour 8, 512^2 and
-    // FP32 products and products with B = A favour 4).
+    // (4096), but every window costs a pass over the group's slots.  Measured
+    // per product on the 2D and 3D workloads, groups of 8 pay off only for FP64
+    // values, long A rows (hundreds of entries: the rows of a group then share
+    // most of their slots) and B rows holding many entries per window (density
+    // within their column range times 2048 of ~200 or more); FP32 products, A
+    // rows of a few entries (A·X with A the stencil) and sparse B rows run
+    // faster in groups of 4.
     int group = w.row_group;
-    if (w.auto_group && pst[1] > 0) group = 2048ull * pst[0] < 200ull * pst[1] ? 4 : 8;
+    if (w.auto_group && pst[1] > 0) {
+        const bool dense_b = 2048ull * pst[0] >= 200ull * pst[1];
+        const bool long_a = A.nnz >= 512 * n;
+        group = (sizeof(V) == 8 && long_a && dense_b) ? 8 : 4;
+    }
     if (group > 1) w.mlen.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1));
+    const double ms_before = w.spgemm_ms;
 
     int64_t running = 0;
     for (size_t b = 0; b + 1 < cuts.size(); ++b) {
@@ -399,6 +406,12 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
         running = end;
     }
     C.nnz = running;
+    if (w.progress && pst[1] > 0)
+        w.note("product: %lld rows, %s, groups of %d, B entries per 2048 columns %.0f, "
+               "A %.0f and B %.0f per row, output %lld, %.2f ms", (long long)n,
+               sizeof(V) == 4 ? "FP32" : "FP64", group,
+               2048.0 * (double)pst[0] / (double)pst[1], (double)A.nnz / (double)n,
+               (double)B.nnz / (double)n, (long long)running, w.spgemm_ms - ms_before);
 }
 
 
