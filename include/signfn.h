@@ -31,8 +31,9 @@
  *
  * Tuning (environment, read when a call starts): SIGNFN_ROW_GROUP = 1, 2, 4,
  * 8 or 16 output rows per workgroup of the product kernel for rows with wide
- * column spans (default per product: 8 for FP64 values with long A rows and B
- * rows dense within their column ranges, else 4); SIGNFN_SYMMETRIC=0 turns the
+ * column spans (default per product: 2 for A or B rows of a few entries, 8 for
+ * FP64 values with long A rows and B rows dense within their column ranges,
+ * else 4); SIGNFN_SYMMETRIC=0 turns the
  * symmetric products off; SIGNFN_PROGRESS=1 prints one line per finished
  * iteration (and per product) to stderr.
  */

@@ -270,12 +270,17 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
     // most of their slots) and B rows holding many entries per window (density
     // within their column range times 2048 of ~200 or more); FP32 products, A
     // rows of a few entries (A·X with A the stencil) and sparse B rows run
-    // faster in groups of 4.
+    // faster in groups of 4, and products with A or B rows of a few entries
+    // (A·X and X·A with A the stencil) in pairs (two 512-thread workgroups
+    // per CU).
     int group = w.row_group;
     if (w.auto_group && pst[1] > 0) {
         const bool dense_b = 2048ull * pst[0] >= 200ull * pst[1];
         const bool long_a = A.nnz >= 512 * n;
-        group = (sizeof(V) == 8 && long_a && dense_b) ? 8 : 4;
+        if (A.nnz < 64 * n || B.nnz <= 16 * n)
+            group = 2;
+        else
+            group = (sizeof(V) == 8 && long_a && dense_b) ? 8 : 4;
     }
     if (group > 1) w.mlen.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1));
     const double ms_before = w.spgemm_ms;
