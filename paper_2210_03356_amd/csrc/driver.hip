@@ -404,6 +404,14 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
             const double est = 1.1 * (double)end * (double)total_cap / (double)bcap;
             C.ensure_entries(std::max<int64_t>(end, (int64_t)std::min(est, (double)total_cap)));
         }
+        if (end > C.capacity() && !capoff_h.empty() && capoff_h[r1] > 0) {
+            // a grow copies the entries stored so far: grow once to what the fill
+            // ratio of the rows done so far predicts for the whole product
+            const double fill = (double)end / (double)capoff_h[r1];
+            const double est = (double)end + 1.1 * fill * (double)(total_cap - capoff_h[r1]);
+            C.ensure_entries(std::max<int64_t>(end, (int64_t)std::min(est, (double)total_cap)),
+                             running);
+        }
         C.ensure_entries(end, running);
         launch_copy_rows<V>(w.capoff.as<int64_t>(), base, C.lenp(),
                             w.stage_col.as<int32_t>(), w.stage_val.as<V>(), r0, r1,
