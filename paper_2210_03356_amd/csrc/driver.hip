@@ -272,12 +272,13 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
     // rows of a few entries (A·X with A the stencil) and sparse B rows run
     // faster in groups of 4, and products with A or B rows of a few entries
     // (A·X and X·A with A the stencil) in pairs (two 512-thread workgroups
-    // per CU).
+    // per CU).  A served batch (row mask set) mixes requests at different
+    // steps, whose rows the averages do not describe: it takes no pairs.
     int group = w.row_group;
     if (w.auto_group && pst[1] > 0) {
         const bool dense_b = 2048ull * pst[0] >= 200ull * pst[1];
         const bool long_a = A.nnz >= 512 * n;
-        if (A.nnz < 64 * n || B.nnz <= 16 * n)
+        if (!w.row_skip && (A.nnz < 64 * n || B.nnz <= 16 * n))
             group = 2;
         else
             group = (sizeof(V) == 8 && long_a && dense_b) ? 8 : 4;
