@@ -265,15 +265,15 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
     // matrix built here is; the merged lists reuse A's index range
     // Groups of 8 rows (2048-column windows) halve the B traffic of groups of 4
     // (4096), but every window costs a pass over the group's slots.  Measured
-    // per product on the 2D and 3D workloads, groups of 8 pay off only for FP64
-    // values, long A rows (hundreds of entries: the rows of a group then share
-    // most of their slots) and B rows holding many entries per window (density
-    // within their column range times 2048 of ~200 or more); FP32 products, A
-    // rows of a few entries (A·X with A the stencil) and sparse B rows run
-    // faster in groups of 4, and products with A or B rows of a few entries
-    // (A·X and X·A with A the stencil) in pairs (two 512-thread workgroups
-    // per CU).  A served batch (row mask set) mixes requests at different
-    // steps, whose rows the averages do not describe: it takes no pairs.
+    // per product on the 2D and 3D workloads: groups of 8 pay off only for FP64
+    // values with long A rows (hundreds of entries: the rows of a group then
+    // share most of their slots) and B rows holding many entries per window
+    // (density within their column range times 2048 of ~200 or more);
+    // products whose A or B rows hold a few entries (A·X and X·A with A the
+    // stencil) run fastest in pairs (two 512-thread workgroups per CU); all
+    // others (FP32 values, sparse B rows) in groups of 4.  A served batch (row
+    // mask set) mixes requests at different steps, whose rows the averages do
+    // not describe: it takes no pairs.
     int group = w.row_group;
     if (w.auto_group && pst[1] > 0) {
         const bool dense_b = 2048ull * pst[0] >= 200ull * pst[1];
