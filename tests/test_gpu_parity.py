@@ -282,6 +282,16 @@ def test_trace_records_budget_and_filter(sf):
     # residual histories agree until the rounding floor
     big = e_ref > 1e-10
     assert np.allclose(e_gpu[big], e_ref[big], rtol=1e-9)
+    # the GPU's own budgets: c4*tol before the switch, eq. 1.18 of the same step's
+    # e_k and ||X^_k||_F after it (Section 3.2, Section 4)
+    tau = np.array([t["tau"] for t in tr[:-1]])
+    e = e_gpu[:-1]
+    x = np.array([t["xfro"] for t in tr[:-1]])
+    after = e < 1e-6
+    assert after.any() and (~after).any()
+    assert np.all(tau[~after] == 1e-16)
+    np.testing.assert_allclose(tau[after], 0.75 * e[after] ** 2 / (3 * x[after] + x[after] ** 3),
+                               rtol=1e-14)
 
 
 

@@ -292,6 +292,80 @@ def test_filter_budget_respected_every_step(oracle_lib):
     assert np.all(r.trace["tau"][:k][after] < 1e-16)
 
 
+# Budgets worked out by hand from eq. 1.18, ||F|| <= (3/4) e^2 / (3x + x^3), and
+# eq. 1.13, ||F|| <= e^2 / (x + z), at points where the arithmetic is short:
+#   e = 4e-7, x = 1:  (3/4)(1.6e-13) / (3 + 1)      = 3e-14
+#   e = 6e-7, x = 3:  (3/4)(3.6e-13) / (9 + 27)     = 7.5e-15
+#   e = 2e-7, x = 2:  (3/4)(4e-14)   / (6 + 8)      = 3e-14 / 14
+#   e = 1e-7, x = 30: (3/4)(1e-14)   / (90 + 27000) = 7.5e-15 / 27090
+#   e = 1e-7, x = 2, z = 3: 1e-14 / 5 = 2e-15
+#   e = 3e-7, x = 1, z = 8: 9e-14 / 9 = 1e-14
+# Each slip fails at least one row: without the 3/4 row 1 gives 4e-14; x^2 for
+# x^3 gives 7.5e-15 * 2 in row 2; e for e^2 is off by 1e7; 3x -> x gives 6e-14 in
+# row 1; x*z for x+z gives 1e-14/6 and 9e-14/8.
+EQ_1_18_POINTS = [(4e-7, 1.0, 3e-14), (6e-7, 3.0, 7.5e-15), (2e-7, 2.0, 3e-14 / 14),
+                  (1e-7, 30.0, 7.5e-15 / 27090)]
+EQ_1_13_POINTS = [(1e-7, 2.0, 3.0, 2e-15), (3e-7, 1.0, 8.0, 1e-14)]
+
+
+@pytest.mark.parametrize("e,x,want", EQ_1_18_POINTS)
+def test_nsf_budget_hand_values_eq_1_18(oracle_lib, e, x, want):
+    assert oracle_lib.nsf_budget(e, x, 1e-12) == pytest.approx(want, rel=1e-14)
+
+
+@pytest.mark.parametrize("e,x,z,want", EQ_1_13_POINTS)
+def test_nmf_budget_hand_values_eq_1_13(oracle_lib, e, x, z, want):
+    assert oracle_lib.nmf_budget(e, x, z, 1e-12) == pytest.approx(want, rel=1e-14)
+
+
+def test_budgets_switch_at_the_residual_threshold(oracle_lib):
+    """Section 4: the fixed budget c*tol applies while e >= 1e-6, the adaptive one
+    below; the switch value and the constant are parameters."""
+    below = math.nextafter(1e-6, 0.0)
+    # just below the switch: (3/4)(1e-12)/36 for eq. 1.18 and 1e-12/6 for eq. 1.13
+    # (the latter is larger than the fixed budget: the formula, not a cap, applies)
+    for f, want in ((lambda e: oracle_lib.nsf_budget(e, 3.0, 1e-12), 0.75e-12 / 36),
+                    (lambda e: oracle_lib.nmf_budget(e, 3.0, 3.0, 1e-12), 1e-12 / 6)):
+        assert f(1e-6) == 1e-16
+        assert f(0.5) == 1e-16
+        assert f(below) == pytest.approx(want, rel=1e-14)
+    assert oracle_lib.nsf_budget(1e-3, 3.0, 1e-10, c_fixed=1e-2) == pytest.approx(1e-12,
+                                                                                 rel=1e-15)
+    # a switch moved up to 1e-2 puts e = 6e-7 ... 1e-3 on the adaptive side
+    assert oracle_lib.nsf_budget(1e-3, 1.0, 1e-12, switch_res=1e-2) == pytest.approx(
+        0.75e-6 / 4, rel=1e-14)
+
+
+def test_nsf_trace_budget_is_eq_1_18_of_the_same_step(oracle_lib):
+    """Every budget after the switch is eq. 1.18 of that step's e_k and ||X^_k||_F
+    (the index reading of the budget), every budget before it is c4*tol."""
+    A = W.laplacian_2d(30, jitter=0.05, seed=2, m=8.0)
+    r = oracle_lib.nsf(A, tol=1e-12)
+    k = r.iters
+    e, x, tau = r.trace["e"][:k], r.trace["xfro"][:k], r.trace["tau"][:k]
+    after = e < 1e-6
+    assert after.sum() >= 1 and (~after).sum() >= 3
+    assert np.all(tau[~after] == 1e-16)
+    np.testing.assert_allclose(tau[after], 0.75 * e[after] ** 2 / (3 * x[after] + x[after] ** 3),
+                               rtol=1e-14)
+    # ||X^_k||_F of a converging symmetric iterate approaches sqrt(n)
+    assert abs(x[-1] - math.sqrt(A.n)) < 1e-6 * math.sqrt(A.n)
+
+
+def test_nmf_trace_budget_is_eq_1_13(oracle_lib):
+    """After the switch the NMF budget is e^2/(||X^||_F + ||X^^-1||_F); near
+    convergence X^^-1 ~ X^ (X^2 ~ I), so it is e^2/(2||X^||_F) to O(e), far from
+    e^2/(||X^|| ||X^^-1||) ~ e^2/n or (3/4)e^2/(3x + x^3)."""
+    A = W.laplacian_2d(12, jitter=0.05, seed=2, m=8.0)
+    r = oracle_lib.nmf(A, tol=1e-12, scale=0.0)
+    k = r.iters
+    e, x, tau = r.trace["e"][:k], r.trace["xfro"][:k], r.trace["tau"][:k]
+    after = e < 1e-6
+    assert after.sum() >= 1
+    assert np.all(tau[~after] == 1e-16)
+    np.testing.assert_allclose(tau[after] * 2 * x[after] / e[after] ** 2, 1.0, atol=1e-5)
+
+
 def test_theorem_3_2_1_nsf_vs_ns(oracle_lib):
     """Once the residual is small, ||R^_k - R_k|| <= 3 ||R_k|| (eq. 1.18 budget)."""
     A = W.laplacian_2d(20, jitter=0.05, seed=2, m=8.0)
