@@ -29,6 +29,8 @@
  * Build: gcc -O2 -fopenmp -ffp-contract=off -shared -fPIC nsf_oracle.c -lm
  */
 #include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -379,6 +381,22 @@ static int wrap_input(int64_t n, const int64_t *rp, const int32_t *ci, const dou
     return 0;
 }
 
+/* Progress lines on stderr when ORACLE_PROGRESS=1 (long full-size runs). */
+static int progress_on(void) {
+    const char *p = getenv("ORACLE_PROGRESS");
+    return p && p[0] == '1';
+}
+
+static void progress(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    fputs("[oracle] ", stderr);
+    vfprintf(stderr, fmt, ap);
+    fputc('\n', stderr);
+    fflush(stderr);
+    va_end(ap);
+}
+
 /* Budget of eq. 1.18 after the switch (A4 reading), fixed budget before it. */
 double oracle_nsf_budget(double e, double xfro, double tol, double c_fixed, double switch_res) {
     if (e >= switch_res) return c_fixed * tol;
@@ -448,6 +466,9 @@ int oracle_nsf(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
         }
         res->iters = k - 1;
         res->res_fro = e;
+        if (progress_on())
+            progress("nsf k=%d e=%.3e nnz(X)=%lld nnz(R)=%lld", k, e, (long long)ocsr_nnz(&X),
+                     (long long)ocsr_nnz(&R));
         /* convergence test of the while loop */
         const int conv = (o->stop_rule == 1) ? (d_prev < o->tol) : (e <= o->tol);
         if (conv) { ocsr_free(&R); status = OR_OK; break; }
@@ -467,6 +488,7 @@ int oracle_nsf(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
         /* step 3: Xbar_{k+1} = X^_k + 1/2 X^_k R^_k */
         if (matmul(&X, &R, &P)) { ocsr_free(&R); goto oom; }
         ocsr_free(&R);
+        if (progress_on()) progress("nsf k=%d product X R: %lld entries", k, (long long)ocsr_nnz(&P));
         if (add(1.0, &X, 0.5, &P, &Xbar)) { ocsr_free(&P); goto oom; }
         const double d = 0.5 * sqrt(sumsq(&P));
         ocsr_free(&P);
