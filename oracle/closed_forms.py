@@ -147,3 +147,24 @@ def local_sign_row_similar(A, i: int, radius: int, d: np.ndarray):
     sS = dense_sign_sym(0.5 * (S + S.T))
     loc = int(np.searchsorted(idx, i))
     return idx, sS[loc] * (dB[loc] / dB)
+
+
+def local_sign_rows_similar(A, center: int, radius: int, reach: int, d: np.ndarray):
+    """local_sign_row_similar for every row within graph distance `reach` of
+    `center`, from one patch: the ball of radius radius + reach around the
+    centre contains the radius-`radius` ball of each such row, so each row is
+    at least `radius` hops from the patch boundary (same truncation bound).
+    Returns {row: (columns, values)}."""
+    idx = ball(A, center, radius + reach)
+    near = ball(A, center, reach)
+    sub = A.to_scipy()[idx][:, idx].toarray()
+    dB = np.asarray(d, dtype=np.float64)[idx]
+    S = sub * (dB[None, :] / dB[:, None])
+    if not np.allclose(S, S.T, rtol=0, atol=1e-13 * np.abs(S).max()):
+        raise ValueError("patch is not symmetric under the given scaling")
+    sS = dense_sign_sym(0.5 * (S + S.T))
+    out = {}
+    for i in near:
+        loc = int(np.searchsorted(idx, i))
+        out[int(i)] = (idx, sS[loc] * (dB[loc] / dB))
+    return out

@@ -461,6 +461,36 @@ def test_local_sign_row_similar_matches_schur():
         cf.local_sign_row_similar(A, 7, 4, np.ones(A.n))
 
 
+def test_local_sign_rows_from_one_patch():
+    """Rows taken from one shared patch: on a grid the patch covers entirely they
+    are the rows of the whole matrix's Schur sign (this pins the row-to-patch
+    index mapping); on a larger grid every row returned equals the single-row
+    patch of the same radius to the truncation level (the two patches differ, so
+    the rows agree to that level, not to rounding)."""
+    N = 12
+    A = W.convdiff_2d(N, beta=0.5, sigma=4.0, m=8.0)
+    d = np.sqrt(1.0 + A.meta["b"]) ** (np.arange(A.n) % N)
+    S = cf.dense_sign_schur(A.to_dense())
+    rows = cf.local_sign_rows_similar(A, 5 * N + 6, 30, 3, d)
+    assert len(rows) == 2 * 3 * 3 + 2 * 3 + 1      # the Manhattan ball of radius 3
+    for i, (idx, v) in rows.items():
+        assert len(idx) == A.n
+        assert np.abs(v - S[i]).max() <= 1e-13
+    N = 40
+    A = W.convdiff_2d(N, beta=0.5, sigma=4.0, m=8.0)
+    d = np.sqrt(1.0 + A.meta["b"]) ** (np.arange(A.n) % N)
+    rows = cf.local_sign_rows_similar(A, 20 * N + 17, 14, 2, d)
+    for i in (20 * N + 17, 20 * N + 19, 21 * N + 16, 18 * N + 17):
+        idx1, r1 = cf.local_sign_row_similar(A, i, 14, d)
+        idx2, r2 = rows[i]
+        full = np.zeros(A.n)
+        full[idx2] = r2
+        part = np.zeros(A.n)
+        part[idx1] = r1
+        # each is within the radius-14 truncation (~1e-11 here) of the sign
+        assert np.abs(full - part).max() <= 1e-10 * np.abs(part).max()
+
+
 # ---------------------------------------------------------------------------
 # the certified last residual: with Xt = X - D thinned by a filter cut,
 # ||I - X^2||_F <= ||I - Xt^2||_F + 2 ||Xt||_2 ||D||_F + ||D||_F^2,
