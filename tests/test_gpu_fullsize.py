@@ -1,14 +1,20 @@
 """Parity at the full workload sizes, in the launch configuration bench.py times.
 
-The FP64 oracle cannot solve these sizes in a test, so the HIP results are
-checked on sampled rows the oracle side can compute one by one: row i of the
-dense sign of the principal patch on the ball of graph radius r around i
-(exponential decay of the sign of a gapped matrix makes the patch row equal to
-row i of sign(A) to about q^r), plus properties that hold at any size: X^2 = I
-and XA = AX on sampled rows, and trace(X) = (# eigenvalues right) - (# left),
-which the staggered gap term fixes as the sum of (-1)^(x+y(+z)).
+C2 (256 x 256) is compared with the FP64 oracle's own solve of the same matrix,
+stored by tests/golden/make_fullsize_golden.py (a run of several minutes, too
+long for a test): the whole matrix through per-row hash probes, which estimate
+||X - S||_F, and entry by entry on complete stored rows.  For C3 (512 x 512),
+which the oracle cannot solve in the memory of a test machine, rows are checked
+against the dense sign of the principal patch on a ball of graph radius 34
+around them (the exponential decay of the sign of a gapped matrix makes the
+patch row equal to the row of sign(A) to about q^34), several hundred rows from
+shared patches, plus properties that hold at any size: X^2 = I and XA = AX on
+sampled rows, and trace(X) = (# eigenvalues right) - (# left), which the
+staggered gap term fixes as the sum of (-1)^(x+y(+z)).
 """
 import math
+import os
+import sys
 
 import numpy as np
 import pytest
@@ -115,40 +121,143 @@ def _c3_scaling(A):
     return np.sqrt(1.0 + A.meta["b"]) ** (np.arange(A.n) % N)
 
 
-def test_c2_full_fp64(sf):
-    """2D 256 x 256, FP64, tol 1e-12: sampled rows within 1e-10 of the sign."""
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+if GOLDEN not in sys.path:
+    sys.path.insert(0, GOLDEN)
+
+
+@pytest.fixture(scope="module")
+def c2_golden():
+    """The FP64 oracle's solve of the full C2 matrix (tests/golden/
+    make_fullsize_golden.py): summary, per-row probes and complete sample rows."""
+    import make_fullsize_golden as mk
+    g = dict(np.load(os.path.join(GOLDEN, "c2_fp64_oracle.npz")))
     A = W.config_matrix("c2")
+    assert str(g["fingerprint"]) == mk.fingerprint(A), "C2 generator changed since the golden run"
+    return A, g
+
+
+def _check_against_oracle(res, g, rel_tol):
+    """Whole matrix: sum_i (probe_i(X) - probe_i(S))^2 estimates ||X - S||_F^2 with
+    every entry of X and S taking part (tests/golden/probe.py); entry by entry on
+    the oracle's stored rows (union of the patterns); Frobenius norm and trace."""
+    import torch
+    import probe
+    import paper_2210_03356_amd as pkg
+    pkg.release_cached()
+    rp, ci, va = res.to_torch()
+    p = probe.row_probe_torch(rp, ci, va).cpu().numpy()
+    xfro = float(torch.linalg.vector_norm(va.double()))
+    del rp, ci, va
+    torch.cuda.empty_cache()
+    fro = float(g["fro"])
+    est = math.sqrt(float(np.sum((p - g["probe"]) ** 2))) / fro
+    assert est <= rel_tol, est
+    assert abs(xfro - fro) <= rel_tol * fro, (xfro, fro)
+    rows = g["rows"]
+    got = res.rows(rows)
+    off, worst, smax = 0, 0.0, 0.0
+    for i, L in zip(rows, g["row_len"]):
+        sc, sv = g["row_cols"][off:off + L], g["row_vals"][off:off + L]
+        off += L
+        gc_, gv = got[int(i)]
+        u = np.union1d(sc, gc_)
+        a = np.zeros(len(u))
+        b = np.zeros(len(u))
+        a[np.searchsorted(u, gc_)] = gv.astype(np.float64)
+        b[np.searchsorted(u, sc)] = sv
+        worst = max(worst, float(np.abs(a - b).max()) if len(u) else 0.0)
+        smax = max(smax, float(np.abs(sv).max()) if L else 0.0)
+    assert worst <= rel_tol * smax, (worst, smax)
+    assert len(rows) >= 64
+    return est, worst / smax
+
+
+def test_c2_full_fp64(sf, c2_golden):
+    """2D 256 x 256, FP64, tol 1e-12: the whole matrix against the FP64 oracle's
+    (rel. Frobenius <= 1e-10, entry-wise <= 1e-10 max|S| on its stored rows), plus
+    the sampled-row properties."""
+    A, g = c2_golden
     res = sf.sign_ns(sf.DeviceCsr.from_host(A), sf.default_opts(tol=1e-12))
     assert res.status == "OK"
+    _check_against_oracle(res, g, 1e-10)
     _check_sampled(res, A, lambda i: cf.local_sign_row(A, i, 34), 1e-10)
 
 
-def test_c2_full_mixed(sf):
-    """The same workload with FP32 bulk products and FP64 polish: within 1e-8."""
-    A = W.config_matrix("c2")
+def test_c2_full_mixed(sf, c2_golden):
+    """The same workload with FP32 bulk products and FP64 polish: within 1e-8 of
+    the FP64 oracle, whole matrix and entry-wise."""
+    A, g = c2_golden
     res = sf.sign_ns(sf.DeviceCsr.from_host(A), sf.default_opts(tol=1e-12, precision=1))
     assert res.status == "OK"
-    _check_sampled(res, A, lambda i: cf.local_sign_row(A, i, 34), 1e-8)
+    _check_against_oracle(res, g, 1e-8)
 
 
-def test_c2_full_newton(sf):
-    """Filtered Newton (inverse by filtered Newton-Schulz) at full size."""
-    A = W.config_matrix("c2")
+def test_c2_full_newton(sf, c2_golden):
+    """Filtered Newton (inverse by filtered Newton-Schulz) at full size: the sign is
+    unique, so the FP64 NSF oracle's result is its reference too."""
+    A, g = c2_golden
     res = sf.sign_newton(sf.DeviceCsr.from_host(A), sf.default_opts(tol=1e-12))
     assert res.status == "OK"
-    _check_sampled(res, A, lambda i: cf.local_sign_row(A, i, 34), 1e-10)
+    _check_against_oracle(res, g, 1e-10)
+
+
+# Patch centres (x, y) on the 512 x 512 grid: the centre, both sides of the
+# half-row boundary where a new 64-group XCD chunk starts, the four edges, a
+# corner and two interior points; each patch yields the rows within 4 hops.
+C3_CENTRES = [(256, 256), (256, 100), (255, 401), (0, 0), (511, 300), (3, 511), (137, 421),
+              (128, 16), (384, 200)]
+
+
+@pytest.fixture(scope="module")
+def c3_reference_rows():
+    A = W.config_matrix("c3")
+    d = _c3_scaling(A)
+    N = int(A.meta["shape"][0])
+    ref = {}
+    for x, y in C3_CENTRES:
+        ref.update(cf.local_sign_rows_similar(A, y * N + x, 34, 4, d))
+    assert len(ref) >= 256
+    return A, ref
 
 
 @pytest.mark.parametrize("precision,rel_tol", [(1, 1e-8), (0, 1e-10)])
-def test_c3_full(sf, precision, rel_tol):
+def test_c3_full(sf, c3_reference_rows, precision, rel_tol):
     """2D 512 x 512 upwind convection-diffusion (nonsymmetric), filter_y on,
-    mixed precision as configured and plain FP64."""
-    A = W.config_matrix("c3")
-    d = _c3_scaling(A)
+    mixed precision as configured and plain FP64: every reference row (patch
+    signs, at least 256 rows spread over XCD chunks, row groups and the grid's
+    edges) within rel_tol, and the sampled-row properties."""
+    A, ref = c3_reference_rows
     res = sf.sign_ns(sf.DeviceCsr.from_host(A),
                      sf.default_opts(tol=1e-12, filter_y=1, precision=precision))
     assert res.status == "OK"
+    rows = sorted(ref)
+    got = res.rows(rows)
+    worst = max(_row_error(got[i], *ref[i]) for i in rows)
+    assert worst <= rel_tol, worst
+    d = _c3_scaling(A)
     _check_sampled(res, A, lambda i: cf.local_sign_row_similar(A, i, 34, d), rel_tol)
+
+
+@pytest.mark.parametrize("nB", [500, 1000, 3000, 5000])
+def test_ode_matrix_paper_sizes(sf, nB):
+    """Section 4.2 at the sizes of Table 4.2.1: the whole result against the eq. 1.26
+    closed form, and the filtered-vs-unfiltered difference AE within 10x of the
+    paper's printed value."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "table_4_2_1.txt"))
+            if l.strip() and not l.startswith("#")]
+    paper_ae = {int(r[0]): float(r[2]) for r in rows}[nB]
+    A = W.ode_block_matrix(nB)
+    dA = sf.DeviceCsr.from_host(A)
+    f = sf.sign_ns(dA, sf.default_opts(tol=1e-12))
+    u = sf.sign_ns(dA, sf.default_opts(tol=1e-12, c_fixed=0.0, switch_res=0.0))
+    assert f.status == "OK" and u.status == "OK"
+    X = f.to_scipy()
+    S = cf.sign_ode_block(nB)
+    D = X.toarray() - S
+    assert np.linalg.norm(D) / np.linalg.norm(S) <= 1e-10
+    ae = float(np.sqrt(((X - u.to_scipy()).power(2)).sum()))
+    assert ae <= 10 * paper_ae, (ae, paper_ae)
 
 
 @pytest.mark.parametrize("precision,rel_tol", [(1, 1e-8), (0, 1e-10)])
