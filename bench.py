@@ -2,16 +2,19 @@
 """Benchmark of the filtered Newton-Schulz matrix sign on one MI355X.
 
 One "step" is one complete sign(A) solve (Algorithm 3.2.1: products, residual,
-budget, filter, compaction, norms) of the 2D 5-point workload: 256 x 256 grid
-(n = 65,536), shifted by 4 + U[-0.05, 0.05] (seed 2) with the staggered gap
-term 8*(-1)^(x+y), FP64, tol 1e-12.  The matrix is resident in HBM before the
-timed region; W untimed warm-up solves precede K timed ones.
+budget, filter, compaction, norms).  Default workload: the largest FP64
+configuration, 2D upwind convection-diffusion on a 512 x 512 grid (n = 262,144,
+nonsymmetric), beta = 0.5 with the staggered gap term 8*(-1)^(x+y), FP64, tol
+1e-12, residuals filtered too.  The matrix is resident in HBM before the timed
+region; W untimed warm-up solves precede K timed ones.
 
 Printed: ONE JSON line with time-to-solution, the roofline of the hottest
 numeric product kernel (per-launch algorithmic bytes over its average HIP-event
 duration on the solve's stream), the HBM traffic of that kernel from the
 committed rocprofv3 counter summary (null if the kernel source changed since),
-and the FP64 CPU oracle timed on the host as a baseline.
+and the FP64 CPU oracle timed on the host as a baseline: on a bounded sample of
+the workload's family, projected to the full size by the ratio of intermediate
+products, next to a full-size solve of the 256 x 256 workload timed outright.
 """
 import argparse
 import hashlib
@@ -26,7 +29,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "sign(A) time-to-solution at rel.err 1e-8"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spgemm_hbm_traffic_c2.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spgemm_hbm_traffic_{cfg}.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2210_03356_amd", "csrc", "kernels.hip")
 
 
@@ -44,11 +47,11 @@ def read_traffic(st, config: str, precision: int, grid=None, method="ns"):
     """Per-launch HBM bytes (FETCH + WRITE, copy-calibrated) of the hot kernel from the
     committed counter summary; None for other workloads or once the kernel source
     differs from the one the counters were taken on."""
-    if (config != "c2" or grid or precision != 0 or method != "ns"
-            or not os.path.exists(TRAFFIC_FILE)):
+    path = TRAFFIC_FILE.format(cfg=config)
+    if grid or precision != 0 or method != "ns" or not os.path.exists(path):
         return None
     vals = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
@@ -130,25 +133,70 @@ def device_trace(res):
     return t
 
 
-def cpu_baseline(cfg, grid_full, n_full):
-    """FP64 oracle (as is, all host threads) on a smaller grid of the same family,
-    scaled to the full size by the row count."""
-    import oracle
-    oracle.build(force=False)
-    sample_grid = {"c2": 96, "c1": None, "c3": 96, "c4": 20}[cfg]
-    A, kw = build_workload(cfg, sample_grid)
+def _oracle_threads():
     threads = len(os.sched_getaffinity(0))
     omp = os.environ.get("OMP_NUM_THREADS")
     if omp:
         threads = min(threads, int(omp))
+    return threads
+
+
+def _timed_oracle(A, kw, threads):
+    import oracle
+    oracle.build(force=False)
+    os.environ["ORACLE_PROGRESS"] = "1"   # one line per iteration on stderr
     t = time.perf_counter()
     r = oracle.nsf(A, nthreads=threads, **kw)
-    dt = time.perf_counter() - t
-    scale = n_full / A.n
-    return {"value": dt * scale, "unit": "s", "cores": threads, "kind": "oracle",
-            "sample": (f"full FP64 oracle solve of the same family on n={A.n} "
-                       f"({dt:.2f} s, {r.iters} updates, status {r.status}), scaled by "
-                       f"{n_full}/{A.n} rows")}
+    return time.perf_counter() - t, r
+
+
+SAMPLE_GRID = {"c1": None, "c2": 112, "c3": 128, "c4": 20}
+
+
+def cpu_baseline(cfg, products_full, solve, full_c2=True):
+    """FP64 oracle (as is, all host threads).  The full-size oracle solve of the
+    default workload does not fit a benchmark run (its iterates alone exceed tens
+    of GB and its time tens of minutes), so the oracle is timed on a bounded
+    sample -- the same family on a smaller grid -- and projected by the ratio of
+    intermediate products of the full and sample solves, both counted by the
+    library on this GPU with the same options.  Next to it, the oracle's full
+    solve of the 256 x 256 workload is timed outright in the same run."""
+    import paper_2210_03356_amd as sf
+    threads = _oracle_threads()
+    out = {"cores": threads}
+    if cfg == "c1":
+        A, kw = build_workload(cfg, None)
+        dt, r = _timed_oracle(A, kw, threads)
+        out.update(value=dt, unit="s", kind="oracle",
+                   sample=f"full FP64 oracle solve of the same matrix (n={A.n}, {r.iters} "
+                          f"updates, status {r.status})")
+        return out
+    g = SAMPLE_GRID[cfg]
+    A, kw = build_workload(cfg, g)
+    rs = solve(sf.DeviceCsr.from_host(A, device="cuda:0"), sf.default_opts(**kw))
+    p_sample = rs.stats()["products"]
+    del rs
+    print(f"# cpu baseline: oracle on the {cfg} family at grid {g} (n={A.n})", file=sys.stderr,
+          flush=True)
+    dt, r = _timed_oracle(A, kw, threads)
+    ratio = products_full / max(p_sample, 1)
+    out.update(value=dt * ratio, unit="s", kind="oracle, projected by intermediate products",
+               sample=(f"full FP64 oracle solve of the same family on a {g}x{g} grid (n={A.n}, "
+                       f"{dt:.2f} s, {r.iters} updates, status {r.status}), scaled by the "
+                       f"ratio of intermediate products of the full and sample solves "
+                       f"({products_full:.4g} / {p_sample:.4g} = {ratio:.1f}) counted by "
+                       f"the library on the GPU with the same options"),
+               sample_seconds=round(dt, 2), products_ratio=round(ratio, 2))
+    if full_c2:
+        A2, kw2 = build_workload("c2", None)
+        print(f"# cpu baseline: full-size oracle solve of c2 (n={A2.n})", file=sys.stderr,
+              flush=True)
+        dt2, r2 = _timed_oracle(A2, kw2, threads)
+        out["c2_full_oracle_s"] = round(dt2, 2)
+        out["c2_full_oracle"] = (f"FP64 oracle, 2D 5-point 256x256 (n={A2.n}), tol 1e-12: "
+                                 f"{r2.iters} updates, status {r2.status}, nnz {r2.nnz}, "
+                                 f"timed outright on {threads} threads")
+    return out
 
 
 def serve_bench(args):
@@ -309,13 +357,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--grid", type=int, default=None, help="override the grid size")
     ap.add_argument("--precision", type=int, default=0)
     ap.add_argument("--method", default="ns", choices=["ns", "newton"],
                     help="filtered Newton-Schulz (Alg. 3.2.1) or filtered Newton (Alg. 3.1.1)")
     ap.add_argument("--filter-y", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-full-c2", action="store_true",
+                    help="skip the outright oracle solve of the 256x256 workload")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--copy-calib-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (counter calibration)")
@@ -415,8 +465,16 @@ def main():
     del res
 
     cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.config, args.grid, A.n)
+    if not args.no_cpu_baseline and not args.grid:
+        p_full = agg["products"] / max(args.steps, 1)
+        if args.precision != 0 or args.method != "ns":
+            # the oracle is FP64 filtered Newton-Schulz: count the products of
+            # that solve on the GPU for the projection
+            r64 = sf.sign_ns(dA, sf.default_opts(**kw))
+            p_full = r64.stats()["products"]
+            del r64
+        cpu = cpu_baseline(args.config, p_full, sf.sign_ns,
+                           full_c2=not args.no_cpu_full_c2)
 
     traffic = read_traffic(st, args.config, args.precision, args.grid, args.method)
     line = {
@@ -438,7 +496,9 @@ def main():
             "c3": f"2D upwind conv-diff {g}x{g}, beta*h, - 4 + 8*stagger",
             "c4": f"3D 7-point {g}^3 - 6 + U[-.5,.5] + 12*stagger"}[args.config],
             "n": A.n, "nnz": A.nnz, "tol": kw["tol"], "stop_rule": kw["stop_rule"],
-            "filter_y": kw["filter_y"], "precision": args.precision, "method": args.method},
+            "filter_y": kw["filter_y"], "precision": args.precision, "method": args.method,
+            "values": "FP64" if args.precision == 0 else
+                      "FP32 values, FP64 accumulation, FP64 norms/threshold, FP64 polish"},
         "solves_per_s": round(1e3 / ms_per_step, 4),
         "iters": st["iters"],
         "inner_steps": st["inner_steps"],
