@@ -206,6 +206,33 @@ SIGNFN_API int sign_spgemm(const sign_csr *A, const sign_csr *B, void *hip_strea
  * *bstar receives the cut bucket.  FP64 or FP32 input; FP64 result. */
 SIGNFN_API int sign_filter(const sign_csr *A, double tau, void *hip_stream, sign_result **out, int *bstar);
 
+/* ---- allocation-free variant ---- */
+
+/* Row limit of sign_filter_noalloc (its device scratch is sized for it). */
+#define SIGN_NOALLOC_MAX_ROWS 1048576
+
+/* For callers that cannot allocate device memory (serving loops and harnesses
+ * that forbid hipMalloc): sign_filter into buffers the caller owns.  The call
+ * makes no device allocation; the histogram, the cut, row lengths, per-row
+ * sums and scan partials live in a fixed device array of the library (about
+ * 16 MiB, held on each device it runs on until the process ends).
+ *   A            device CSR as for sign_filter (FP64 or FP32 values), read in
+ *                place; n <= SIGN_NOALLOC_MAX_ROWS, else SIGN_EINVAL
+ *   out          caller's DEVICE buffers: out->row_ptr int64[n+1], out->col
+ *                int32[out_capacity], out->val double[out_capacity]; on
+ *                SIGN_OK out->n, out->nnz and out->val_f32 = 0 are set
+ *   out_capacity entries out->col/out->val can hold (A->nnz always suffices);
+ *                if fewer entries are kept than needed: SIGN_ENOMEM, with
+ *                out->row_ptr overwritten and col/val untouched
+ *   bstar        (optional) receives the cut bucket
+ *   dropped_fro  (optional) receives ||F||_F of the dropped entries
+ * Same entries, values and cut as sign_filter.  Synchronises the stream (the
+ * kept count is read back), so it cannot be captured into a graph.  Calls on
+ * one device share its scratch array: calls that overlap on one device race
+ * and must be serialised by the caller. */
+SIGNFN_API int sign_filter_noalloc(const sign_csr *A, double tau, void *hip_stream, sign_csr *out,
+                                   int64_t out_capacity, int *bstar, double *dropped_fro);
+
 /* ---- serving: continuous batching of many sign_ns solves ---- */
 typedef struct sign_server sign_server;
 

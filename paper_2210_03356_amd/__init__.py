@@ -12,6 +12,8 @@ from .signfn import (  # noqa: F401
     load,
     release_cached,
     sign_filter,
+    sign_filter_noalloc,
+    NOALLOC_MAX_ROWS,
     sign_newton,
     sign_ns,
     sign_spgemm,

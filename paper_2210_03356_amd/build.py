@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsignfn.so")
-SOURCES = ["kernels.hip", "runtime.hip", "driver.hip", "abi.hip", "serve.hip"]
+SOURCES = ["kernels.hip", "runtime.hip", "driver.hip", "abi.hip", "serve.hip", "noalloc.hip"]
 ARCH = os.environ.get("SIGNFN_ARCH", "gfx950")
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -98,6 +98,9 @@ def load():
     lib.sign_spgemm.restype = C.c_int
     lib.sign_filter.argtypes = [P(sign_csr), C.c_double, C.c_void_p, P(C.c_void_p), P(C.c_int)]
     lib.sign_filter.restype = C.c_int
+    lib.sign_filter_noalloc.argtypes = [P(sign_csr), C.c_double, C.c_void_p, P(sign_csr),
+                                        C.c_int64, P(C.c_int), P(C.c_double)]
+    lib.sign_filter_noalloc.restype = C.c_int
     lib.sign_result_csr.argtypes = [C.c_void_p, P(sign_csr)]
     lib.sign_result_csr.restype = C.c_int
     lib.sign_result_stats.argtypes = [C.c_void_p, P(sign_stats)]
@@ -317,6 +320,30 @@ def sign_filter(A: DeviceCsr, tau: float, stream=None):
     if out.value is None:
         raise _err(st)
     return Result(out.value, st), int(b.value)
+
+
+NOALLOC_MAX_ROWS = 1048576  # SIGN_NOALLOC_MAX_ROWS
+
+
+def sign_filter_noalloc(A: DeviceCsr, tau: float, out_row_ptr, out_col, out_val, stream=None):
+    """sign_filter into caller-owned device tensors (int64 row_ptr of n+1, int32 col and
+    float64 val of equal capacity); the library allocates no device memory.  Returns
+    (nnz kept, cut bucket, ||F||_F of the dropped part)."""
+    import torch
+    assert out_row_ptr.dtype == torch.int64 and out_row_ptr.numel() >= A.n + 1
+    assert out_col.dtype == torch.int32 and out_val.dtype == torch.float64
+    cap = min(out_col.numel(), out_val.numel())
+    a = A.struct()
+    o = sign_csr(n=0, nnz=0, row_ptr=out_row_ptr.data_ptr(),
+                 col=out_col.data_ptr() if cap else None,
+                 val=out_val.data_ptr() if cap else None, val_f32=0)
+    b = C.c_int(-1)
+    d = C.c_double(0.0)
+    st = load().sign_filter_noalloc(C.byref(a), float(tau), C.c_void_p(_stream_ptr(stream)),
+                                    C.byref(o), cap, C.byref(b), C.byref(d))
+    if st != 0:
+        raise _err(st)
+    return int(o.nnz), int(b.value), float(d.value)
 
 
 class Server:

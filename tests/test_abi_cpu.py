@@ -98,3 +98,26 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "absent.so"))
     with pytest.raises(RuntimeError, match="missing"):
         B.load()
+
+
+def test_noalloc_entry_point_allocates_nothing_and_checks_its_limit():
+    """sign_filter_noalloc's object code references no device allocator, its row
+    limit matches the header, and an oversized input is rejected on the host."""
+    from paper_2210_03356_amd import build as bld
+    obj = os.path.join(bld.BUILD, "noalloc.hip.o")
+    if not os.path.exists(obj):
+        bld.build()
+    undef = subprocess.run(["nm", "-u", "-C", obj], capture_output=True, text=True,
+                           check=True).stdout
+    for name in ("hipMalloc", "hipFree", "hipMallocAsync", "hipExtMallocWithFlags",
+                 "hipHostMalloc", "hipMallocManaged", "Pool", "Allocator", "DevBuf"):
+        assert name not in undef, name
+    assert "hipGetSymbolAddress" in undef
+    m = re.search(r"#define SIGN_NOALLOC_MAX_ROWS (\d+)", open(HEADER).read())
+    assert m and int(m.group(1)) == sf.NOALLOC_MAX_ROWS
+    lib = sf.load()
+    a = B.sign_csr(n=sf.NOALLOC_MAX_ROWS + 1, nnz=0, row_ptr=None, col=None, val=None, val_f32=0)
+    o = B.sign_csr()
+    st = lib.sign_filter_noalloc(C.byref(a), 1e-3, None, C.byref(o), 0, None, None)
+    assert st == -1
+    assert b"row limit" in lib.sign_last_error()
