@@ -40,6 +40,8 @@ def kernel_hash() -> str:
 def kernel_name(st, tile) -> str:
     """Name and template arguments of the hottest numeric product kernel."""
     v = "float" if st["hot_fp32"] else "double"
+    if st.get("hot_regtile"):
+        return f"k_spgemm_regtile<{v},{st['hot_group']},{tile // 64},{st['hot_threads']}>"
     return f"k_spgemm_rows<{v},{st['hot_group']},{tile},{st['hot_threads']}>"
 
 
@@ -57,10 +59,27 @@ def read_traffic(st, config: str, precision: int, grid=None, method="ns"):
             vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256_16") != kernel_hash():
         return None
-    key = ((f"group{st['hot_group']}_" if st["hot_group"] > 1 else "") +
+    key = ((f"regtile{st['hot_group']}x{st['hot_tile'] // 64}_" if st.get("hot_regtile") else
+            f"group{st['hot_group']}_" if st["hot_group"] > 1 else "") +
            ("f32_" if st["hot_fp32"] else "f64_") +
            f"tile{st['hot_tile']}_hbm_bytes_per_launch")
     return float(vals[key]) if key in vals else None
+
+
+def lds_atomic_ceiling():
+    """The product kernel's accumulation ceiling, measured on this GPU by the
+    committed probe paper_2210_03356_amd/lds_atomic_rate (native LDS atomic adds
+    of FP64 values, every CU busy)."""
+    import subprocess
+    exe = os.path.join(ROOT, "paper_2210_03356_amd", "lds_atomic_rate")
+    if not os.path.exists(exe):
+        return None
+    try:
+        r = subprocess.run([exe], capture_output=True, text=True, timeout=60, check=True)
+        return json.loads(r.stdout.strip().splitlines()[-1])
+    except Exception as e:  # report, never fail the bench on the probe
+        print(f"# lds_atomic_rate: {e}", file=sys.stderr, flush=True)
+        return None
 
 
 def build_workload(cfg, grid):
@@ -477,6 +496,27 @@ def main():
                            full_c2=not args.no_cpu_full_c2)
 
     traffic = read_traffic(st, args.config, args.precision, args.grid, args.method)
+    # second ceiling of the hot kernel: its multiply-adds against the measured LDS
+    # atomic-add rate (one LDS atomic add per multiply-add), or for the
+    # register-accumulator kernel against the FP64 vector FMA peak
+    hot_rate = agg["hot_products"] / (agg["hot_ms"] * 1e-3) if agg["hot_ms"] else 0.0
+    if st.get("hot_regtile"):
+        second = {"kind": "valu_fma_f64", "achieved": round(hot_rate, 1),
+                  "peak": 78.6e12 / 2, "unit": "multiply-adds/s",
+                  "frac": round(hot_rate / (78.6e12 / 2), 4),
+                  "source": "published FP64 vector peak 78.6 TFLOP/s = 39.3e12 FMA/s"}
+    else:
+        probe = lds_atomic_ceiling()
+        second = None
+        if probe:
+            second = {"kind": "lds_atomic_add_f64", "achieved": round(hot_rate, 1),
+                      "peak": probe["lds_add_f64_per_s"], "unit": "multiply-adds/s",
+                      "frac": round(hot_rate / probe["lds_add_f64_per_s"], 4),
+                      "source": (f"lds_atomic_rate measured in this run: "
+                                 f"{probe['lds_add_f64_per_cu_clk']:.2f} ds_add_f64 lane-ops "
+                                 f"per CU per clock at {probe['clock_mhz']:.0f} MHz x "
+                                 f"{probe['cus']} CUs (FP32: "
+                                 f"{probe['lds_add_f32_per_cu_clk']:.2f})")}
     line = {
         "metric": METRIC,
         "value": round(ms_per_step / 1e3, 4),
@@ -527,6 +567,7 @@ def main():
             # B entries the kernel loads (column + value each) over the launch time
             "gathered_gbs": round(agg["hot_gathered"] * (4 + (4 if st["hot_fp32"] else 8)) /
                                   (agg["hot_ms"] * 1e-3) / 1e9, 1) if agg["hot_ms"] else None,
+            "second_ceiling": second,
         },
         "check": check,
         "cpu_baseline": cpu,

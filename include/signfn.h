@@ -132,6 +132,8 @@ typedef struct {
     int64_t hot_products;/* its multiply-adds */
     int64_t hot_gathered;/* B entries it loads (one per multiply-add, or one per slot of the
                             merged list of a row group) */
+    int hot_regtile;     /* 1 if it is the register-accumulator kernel (windows of hot_tile
+                            columns, hot_group rows per workgroup) */
 } sign_stats;
 
 /* One entry per computed residual, k = 0 .. iters. */

@@ -32,6 +32,21 @@ def _compile(src: str) -> str:
     return obj
 
 
+PROBE = os.path.join(HERE, "lds_atomic_rate")
+
+
+def build_probe() -> str:
+    """The LDS atomic-add rate measurement (the product kernel's accumulation ceiling)."""
+    tmp = PROBE + ".tmp"
+    cmd = ["hipcc", *[f for f in FLAGS if f not in ("-fPIC", "-fvisibility=hidden")],
+           os.path.join(CSRC, "lds_atomic_rate.hip"), "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed for lds_atomic_rate.hip:\n" + r.stderr)
+    os.replace(tmp, PROBE)
+    return PROBE
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
@@ -42,6 +57,7 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stderr)
     os.replace(tmp, LIB)
+    build_probe()
     if verbose:
         print("built", LIB)
     return LIB

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <limits>
 
 namespace sfn {
@@ -29,6 +30,20 @@ Workspace::Workspace(Allocator *a, size_t staging_bytes) : al(a), s(a->stream) {
         }
     }
     if (const char *se = std::getenv("SIGNFN_SYMMETRIC")) allow_sym = se[0] != '0';
+    // SIGNFN_REGTILE: "off" (default), "auto", or "<rows>x<nb>" to use the
+    // register-accumulator product for every product it supports
+    if (const char *re = std::getenv("SIGNFN_REGTILE")) {
+        int g = 0, b = 0;
+        if (std::strcmp(re, "off") == 0 || std::strcmp(re, "0") == 0) {
+            rt_mode = 0;
+        } else if (std::strcmp(re, "auto") == 0) {
+            rt_mode = 1;
+        } else if (std::sscanf(re, "%dx%d", &g, &b) == 2 && regtile_supported(g, b)) {
+            rt_mode = 2;
+            rt_group = g;
+            rt_nb = b;
+        }
+    }
     if (const char *pe = std::getenv("SIGNFN_PROGRESS")) progress = pe[0] == '1';
     staging_auto = staging_bytes == 0;
     staging_limit = staging_auto ? auto_staging() : staging_bytes;
@@ -66,13 +81,21 @@ void Workspace::hot_stats(sign_stats &st) const {
         for (int g = 0; g < 5; ++g)
             if (grp[v][g].ms > best->ms) { best = &grp[v][g]; hv = v; h = 4; hg = g; }
     }
+    bool hrt = false;
+    for (int v = 0; v < 2; ++v)
+        if (rt[v].ms > best->ms) { best = &rt[v]; hv = v; hrt = true; }
     const ClassStat &c = *best;
-    const int group = hg >= 0 ? 1 << hg : 1;
-    const BinCfg cfg = h == 4 ? group_config(group, hv ? 4 : 8) : bin_config(h, hv ? 4 : 8);
+    int group = hg >= 0 ? 1 << hg : 1;
+    BinCfg cfg = h == 4 ? group_config(group, hv ? 4 : 8) : bin_config(h, hv ? 4 : 8);
+    if (hrt) {
+        group = rt_used_group;
+        cfg = BinCfg{64 * rt_used_nb, kRegTileThreadsHost};
+    }
     st.hot_tile = cfg.tile;
     st.hot_threads = cfg.threads;
     st.hot_fp32 = hv;
     st.hot_group = group;
+    st.hot_regtile = hrt ? 1 : 0;
     st.hot_launches = c.launches;
     st.hot_ms = c.ms;
     st.hot_bytes = c.bytes;
@@ -283,6 +306,14 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
         else
             group = (sizeof(V) == 8 && long_a && dense_b) ? 8 : 4;
     }
+    // The register-accumulator kernel (k_spgemm_regtile) trades the LDS atomic
+    // per product for one LDS round trip per gathered B entry and register
+    // multiply-adds, with groups of rt_group rows sharing every gathered entry.
+    bool use_rt = false;
+    if (w.rt_mode > 0 && !epi.short_b && (w.rt_mode == 2 || (!w.row_skip && A.nnz >= 64 * n))) {
+        use_rt = true;
+        group = w.rt_group;
+    }
     if (group > 1) w.mlen.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1));
     const double ms_before = w.spgemm_ms;
 
@@ -330,6 +361,17 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
                                   cv_a, w.mlen.as<int32_t>(), w.cstat.as<int64_t>() + 4 * 8 + 5,
                                   s);
             SFN_HIP(hipEventRecord(w.ev[1], s));
+            if (use_rt)
+                launch_spgemm_regtile<V>(group, w.rt_nb, leads, cnt[4], mk_a, mm_a, mc_a, cv_a,
+                                         w.mlen.as<int32_t>(), A.view(), B.view(), Dv, coef,
+                                         dcoef, diag, w.lo.as<int32_t>(), w.span.as<int32_t>(),
+                                         base, w.capoff.as<int64_t>(),
+                                         w.stage_col.as<int32_t>(), w.stage_val.as<V>(),
+                                         C.lenp(), cursor_a, cnext_a,
+                                         sq_prod ? sq_prod->as<double>() : nullptr,
+                                         sq_out ? sq_out->as<double>() : nullptr,
+                                         w.cstat.as<int64_t>() + 4 * 8 + 4, epi, s);
+            else
             launch_spgemm_group<V>(group, leads, cnt[4], mk_a, mm_a, mc_a, cv_a,
                                    w.mlen.as<int32_t>(), A.view(), B.view(), Dv, coef, dcoef,
                                    diag, w.lo.as<int32_t>(), w.span.as<int32_t>(), base,
@@ -373,8 +415,13 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
             w.spgemm_ms += ms;
             if (cnt[cls] <= 0) continue;
             const int lg = group >= 16 ? 4 : group >= 8 ? 3 : group >= 4 ? 2 : group >= 2 ? 1 : 0;
-            Workspace::ClassStat &c = cls == 4 ? w.grp[sizeof(V) == 4 ? 1 : 0][lg]
+            Workspace::ClassStat &c = cls == 4 ? (use_rt ? w.rt[sizeof(V) == 4 ? 1 : 0]
+                                                         : w.grp[sizeof(V) == 4 ? 1 : 0][lg])
                                                : w.cls[sizeof(V) == 4 ? 1 : 0][cls];
+            if (cls == 4 && use_rt) {
+                w.rt_used_group = group;
+                w.rt_used_nb = w.rt_nb;
+            }
             const int64_t *q = cs + cls * 8;
             c.launches += 1;
             c.rows += cls == 4 ? (int64_t)group * cnt[cls] : cnt[cls];

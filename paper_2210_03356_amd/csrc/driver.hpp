@@ -27,6 +27,10 @@ struct Workspace {
     int row_group = 8;                  // wide rows computed in groups of 1, 2, 4, 8 or 16
     bool auto_group = true;             // choose 4 or 8 per product from its column ranges
     bool allow_sym = true;              // symmetric products from their lower triangle
+    // register-accumulator product (k_spgemm_regtile): rows per group and
+    // windows of 64*rt_nb columns; rt_mode 0 off, 1 by the per-product rule,
+    // 2 for every product it supports
+    int rt_mode = 0, rt_group = 16, rt_nb = 4;
     bool progress = false;              // one stderr line per finished iteration
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     // accumulated product statistics, in total and per row class (kernel tile)
@@ -37,6 +41,8 @@ struct Workspace {
     };
     ClassStat cls[2][kClasses];  // [FP64, FP32][row class 1..3]
     ClassStat grp[2][5];         // [FP64, FP32][log2 of the row group] (class 4)
+    ClassStat rt[2];             // [FP64, FP32] register-accumulator groups
+    int rt_used_group = 0, rt_used_nb = 0;  // configuration of the last such launch
     double merge_ms = 0.0;
     int64_t products = 0;
     double spgemm_ms = 0.0;

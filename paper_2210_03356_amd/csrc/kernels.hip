@@ -21,6 +21,7 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kUnroll = 4;  // 64-entry chunks of a B row gathered per sweep step
+constexpr int kRegTileThreads = 512;  // workgroup of the register-accumulator product
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 __device__ __forceinline__ int wave_id() { return threadIdx.x / kWave; }
@@ -965,6 +966,348 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
 }
 
 // ---------------------------------------------------------------------------
+// numeric product with register accumulators (row groups, short windows)
+// ---------------------------------------------------------------------------
+// The same product as k_spgemm_rows for a group of R consecutive output rows
+// i .. i+R-1 (merged slot list from k_merge_group), accumulated in registers
+// instead of LDS atomics.  The columns are swept in windows of W = 64*NB
+// columns; lane l of every wave holds the R x NB partial sums of columns
+// wlo + 64j + l.  A window starts at the smallest column that any slot's B row,
+// any D row or the diagonal still has to add (per-slot cursors as in
+// k_spgemm_rows), so the empty stretches between the column clusters of a
+// grid-ordered matrix cost nothing.  Each wave takes a fixed share of the
+// slots; a slot's in-window B entries (a prefix of what is left of its row)
+// come in 64-entry chunks, are written to the wave's own LDS strip at their
+// column offset, read back by the lanes that own those columns, cleared, and
+// multiplied by the slot's R coefficients (scalar loads) into the registers:
+// one LDS write, read and clear per B entry instead of R atomic adds, and the
+// R multiply-adds in registers.  At the window's end every wave adds its
+// registers into the shared R x W LDS window (one atomic add per column and
+// row), and each row is finished by one wave (R/NW rows per wave): products'
+// sum of squares, the D row and the diagonal added through the wave's strip,
+// the filter's histogram and pre-drop, compaction in column order.
+template <typename V, int R, int NB, int NT>
+__global__ __launch_bounds__(NT) void k_spgemm_regtile(
+    const int32_t *__restrict__ rows, const int32_t *__restrict__ mk,
+    const uint32_t *__restrict__ mm, const int32_t *__restrict__ mc, const V *__restrict__ cv,
+    const int32_t *__restrict__ mlen, MatView<V> A, MatView<V> B, MatView<V> D, V coef,
+    V dcoef, V diag, const int32_t *__restrict__ row_lo, const int32_t *__restrict__ row_span,
+    const int64_t *__restrict__ off, int64_t base, int32_t *__restrict__ out_col,
+    V *__restrict__ out_val, int32_t *__restrict__ out_len, int32_t *__restrict__ cursor,
+    int32_t *__restrict__ cnext, double *__restrict__ sq_prod, double *__restrict__ sq_out,
+    int64_t *__restrict__ out_count, ProductEpi epi) {
+    constexpr int NW = NT / kWave;
+    constexpr int W = kWave * NB;
+    static_assert(R % NW == 0 || NW % R == 0, "rows must split evenly over the waves");
+    constexpr int RPW = R >= NW ? R / NW : 1;  // rows finished per wave
+    __shared__ double acc[R][W];
+    __shared__ double strip[NW][W];
+    __shared__ uint32_t hst[kBuckets];
+    __shared__ int wmin[NW];
+
+    const int lane = lane_id(), wave = wave_id();
+    const int i = rows[xcd_row(blockIdx.x, gridDim.x)];
+    int hi = INT_MIN;
+#pragma unroll
+    for (int r = 0; r < R; ++r) hi = max(hi, row_lo[i + r] + row_span[i + r]);
+    bool all_lower = true;
+#pragma unroll
+    for (int r = 0; r < R; ++r) all_lower = all_lower && epi.lower.of(i + r);
+    if (all_lower) hi = min(hi, i + R);
+    const int64_t mbeg = A.beg[i];
+    const int ml = mlen[i];
+    const bool has_d = D.len != nullptr;
+
+    for (int q = threadIdx.x; q < R * W; q += NT) (&acc[0][0])[q] = 0.0;
+    for (int q = threadIdx.x; q < NW * W; q += NT) (&strip[0][0])[q] = 0.0;
+    if (epi.hist)
+        for (int q = threadIdx.x; q < kBuckets; q += NT) hst[q] = 0u;
+
+    // slots: cursor at the start of the B row, next column its first
+    int mymin = INT_MAX;
+    for (int t0 = wave * kWave; t0 < ml; t0 += NT) {
+        const int t = t0 + lane;
+        if (t < ml) {
+            const int k = mk[mbeg + t];
+            const int bl = B.len[k];
+            const int c0 = bl > 0 ? B.col[B.beg[k]] : INT_MAX;
+            cursor[mbeg + t] = 0;
+            cnext[mbeg + t] = c0;
+            mymin = min(mymin, c0);
+        }
+    }
+    // rows finished by this wave: D cursor, next D column, next diagonal column
+    int dpos[RPW], dnx[RPW];
+    double sq_p[RPW], sq_o[RPW], sq_r[RPW];
+    int wrt[RPW];
+#pragma unroll
+    for (int u = 0; u < RPW; ++u) {
+        const int r = wave + u * NW;
+        dpos[u] = 0;
+        dnx[u] = INT_MAX;
+        sq_p[u] = 0.0;
+        sq_o[u] = 0.0;
+        sq_r[u] = 0.0;
+        wrt[u] = 0;
+        if (r < R) {
+            if (has_d && D.len[i + r] > 0) dnx[u] = D.col[D.beg[i + r]];
+            if (diag != V(0)) dnx[u] = min(dnx[u], i + r);
+            mymin = min(mymin, dnx[u]);
+        }
+    }
+    mymin = wave_min(mymin);
+    if (lane == 0) wmin[wave] = mymin;
+    __syncthreads();
+    int wlo = INT_MAX;
+    for (int w = 0; w < NW; ++w) wlo = min(wlo, wmin[w]);
+    double *mystrip = strip[wave];
+
+    while (wlo < hi) {
+        const int whi = (int)min((int64_t)wlo + W, (int64_t)hi);
+        double racc[R][NB];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) racc[r][j] = 0.0;
+        uint32_t touched = 0u;  // bit j: block j of some row received products
+        mymin = INT_MAX;
+        for (int t0 = wave * kWave; t0 < ml; t0 += NT) {
+            const int t = t0 + lane;
+            const bool own = t < ml;
+            int nc = own ? cnext[mbeg + t] : INT_MAX;
+            const bool was_active = nc < whi;
+            uint64_t act = __ballot(was_active);
+            if (!act) {
+                mymin = min(mymin, nc);
+                continue;
+            }
+            int cur = 0, bl = 0, msk = 0, cpo = 0;
+            int64_t bb = 0;
+            if (was_active) {
+                const int64_t pa = mbeg + t;
+                const int k = mk[pa];
+                msk = (int)mm[pa];
+                cpo = mc[pa];
+                bb = B.beg[k];
+                bl = B.len[k];
+                cur = cursor[pa];
+            }
+            // first chunk of the first active slot
+            int q = __builtin_ctzll(act);
+            act &= act - 1;
+            int p = rl_i32(cur, q), blq = rl_i32(bl, q);
+            int64_t bbq = rl_i64(bb, q);
+            int cc;
+            V bv;
+            {
+                const int at = min(p + lane, blq - 1);
+                cc = B.col[bbq + at];
+                bv = B.val[bbq + at];
+            }
+            while (true) {
+                // issue the next active slot's first chunk before this one is used
+                const bool more = act != 0;
+                const int qn = more ? __builtin_ctzll(act) : q;
+                act &= act - 1;
+                const int pn = rl_i32(cur, qn), bln = rl_i32(bl, qn);
+                const int64_t bbn = rl_i64(bb, qn);
+                int cn;
+                V bn;
+                {
+                    const int at = min(pn + lane, bln - 1);
+                    cn = B.col[bbn + at];
+                    bn = B.val[bbn + at];
+                }
+                // this slot's coefficients (uniform: scalar loads)
+                const uint32_t mq = (uint32_t)rl_i32(msk, q);
+                const V *cp = cv + mbeg + rl_i32(cpo, q);
+                double a[R];
+                {
+                    int idx = 0;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        a[r] = 0.0;
+                        if ((mq >> r) & 1u) a[r] = (double)(coef * cp[idx++]);
+                    }
+                }
+                int nxt = INT_MAX;
+                while (true) {
+                    const bool in = p + lane < blq && cc < whi;
+                    const uint64_t bal = __ballot(in);
+                    const int got = __popcll(bal);
+                    if (got > 0) {
+                        // columns of the chunk's first and last in-window entries
+                        const int c_first = rl_i32(cc, 0) - wlo;
+                        const int c_last = __shfl(cc, got - 1) - wlo;
+                        const int jlo = c_first >> 6, jhi = c_last >> 6;
+                        if (in) mystrip[cc - wlo] = (double)bv;
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        double x[NB];
+#pragma unroll
+                        for (int j = 0; j < NB; ++j)
+                            x[j] = (j >= jlo && j <= jhi) ? mystrip[j * kWave + lane] : 0.0;
+                        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        if (in) mystrip[cc - wlo] = 0.0;
+#pragma unroll
+                        for (int j = 0; j < NB; ++j) {
+                            if (j >= jlo && j <= jhi) {
+                                touched |= 1u << j;
+#pragma unroll
+                                for (int r = 0; r < R; ++r)
+                                    if ((mq >> r) & 1u) racc[r][j] = fma(a[r], x[j], racc[r][j]);
+                            }
+                        }
+                    }
+                    p += got;
+                    if (got < kWave) {
+                        // the entry after the in-window ones (if the row goes on)
+                        if (p < blq) nxt = __shfl(cc, got);
+                        break;
+                    }
+                    if (p >= blq) break;
+                    const int at = min(p + lane, blq - 1);
+                    cc = B.col[bbq + at];
+                    bv = B.val[bbq + at];
+                }
+                if (lane == q) { cur = p; nc = nxt; }
+                if (!more) break;
+                q = qn;
+                p = pn;
+                blq = bln;
+                bbq = bbn;
+                cc = cn;
+                bv = bn;
+            }
+            if (was_active) {  // slots outside the window keep their cursors
+                cursor[mbeg + t] = cur;
+                cnext[mbeg + t] = nc;
+            }
+            mymin = min(mymin, nc);
+        }
+        // add this wave's registers into the shared window
+        if (touched) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int j = 0; j < NB; ++j)
+                    if ((touched >> j) & 1u) atomicAdd(&acc[r][j * kWave + lane], racc[r][j]);
+        }
+        __syncthreads();
+
+        // finish this wave's rows for the window
+        const int nsl = whi - wlo;
+#pragma unroll
+        for (int u = 0; u < RPW; ++u) {
+            const int r = wave + u * NW;
+            if (r >= R) break;
+            const int ir = i + r;
+            const bool low = epi.lower.of(ir);
+            const int lim = low ? min(nsl, ir + 1 - wlo) : nsl;
+            double v[NB];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const int s = j * kWave + lane;
+                v[j] = acc[r][s];
+                acc[r][s] = 0.0;
+                if (sq_prod) sq_p[u] += sym_weight(low, wlo + s, ir) * v[j] * v[j];
+            }
+            if (has_d && dnx[u] < whi && dpos[u] < D.len[ir]) {
+                const int dl = D.len[ir];
+                const int64_t db = D.beg[ir];
+                while (true) {
+                    const int at = dpos[u] + lane;
+                    const int c = at < dl ? D.col[db + at] : INT_MAX;
+                    const bool in = c < whi;
+                    const int got = __popcll(__ballot(in));
+                    if (in) mystrip[c - wlo] = (double)dcoef * (double)D.val[db + at];
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) v[j] += mystrip[j * kWave + lane];
+                    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    if (in) mystrip[c - wlo] = 0.0;
+                    dpos[u] += got;
+                    if (got < kWave) break;
+                }
+            }
+            // next column this row needs from D or the diagonal (recomputed every
+            // window: a column already passed must never be proposed again)
+            dnx[u] = has_d && dpos[u] < D.len[ir] ? D.col[D.beg[ir] + dpos[u]] : INT_MAX;
+            if (diag != V(0)) {
+                if (ir >= wlo && ir < whi) {
+                    const int s = ir - wlo;
+                    if (lane == (s & (kWave - 1))) {
+#pragma unroll
+                        for (int j = 0; j < NB; ++j)
+                            if (j == (s >> 6)) v[j] += (double)diag;
+                    }
+                }
+                if (ir >= whi) dnx[u] = min(dnx[u], ir);
+            }
+            const int64_t obase = off[ir] - base;
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const int s = j * kWave + lane;
+                const V val = s < lim ? (V)v[j] : V(0);
+                bool keep = val != V(0);
+                const double wgt = sym_weight(low, wlo + s, ir);
+                if (keep && (epi.hist || epi.keep_from > 0)) {
+                    const int bk = bucket_of(as_f64(val));
+                    if (epi.hist) atomicAdd(&hst[bk], (uint32_t)wgt);
+                    if (bk < epi.keep_from) {
+                        keep = false;
+                        sq_r[u] += wgt * as_f64(val) * as_f64(val);
+                    }
+                }
+                const uint64_t m = __ballot(keep);
+                if (keep) {
+                    if (!epi.no_store) {
+                        const int64_t pos = obase + wrt[u] + lanes_below(m);
+                        out_col[pos] = wlo + s;
+                        out_val[pos] = val;
+                    }
+                    sq_o[u] += wgt * as_f64(val) * as_f64(val);
+                }
+                wrt[u] += __popcll(m);
+            }
+            mymin = min(mymin, dnx[u]);
+        }
+        mymin = wave_min(mymin);
+        if (lane == 0) wmin[wave] = mymin;
+        __syncthreads();
+        // every candidate lies at or beyond whi (slots stopped at their first
+        // entry >= whi, D cursors likewise, passed diagonals are not proposed);
+        // the bound keeps the sweep moving forward whatever the inputs
+        int nxt_lo = INT_MAX;
+        for (int w = 0; w < NW; ++w) nxt_lo = min(nxt_lo, wmin[w]);
+        wlo = max(nxt_lo, whi);
+    }
+    if (epi.hist) {
+        __syncthreads();
+        for (int q = threadIdx.x; q < kBuckets; q += NT)
+            if (hst[q]) atomicAdd((unsigned long long *)&epi.hist[q], (unsigned long long)hst[q]);
+    }
+    unsigned long long tw = 0;
+#pragma unroll
+    for (int u = 0; u < RPW; ++u) {
+        const int r = wave + u * NW;
+        if (r >= R) break;
+        const double xp = wave_sum(sq_p[u]), xo = wave_sum(sq_o[u]), xr = wave_sum(sq_r[u]);
+        if (lane == 0) {
+            out_len[i + r] = wrt[u];
+            if (sq_prod) sq_prod[i + r] = xp;
+            if (sq_out) sq_out[i + r] = xo;
+            if (epi.sq_pre) epi.sq_pre[i + r] = xr;
+        }
+        tw += (unsigned long long)wrt[u];
+    }
+    if (out_count && lane == 0 && tw) atomicAdd((unsigned long long *)out_count, tw);
+}
+
+// ---------------------------------------------------------------------------
 // gapped -> compact copy (one wave per row)
 // ---------------------------------------------------------------------------
 template <typename V>
@@ -1591,6 +1934,10 @@ void launch_merge_group(int group, const int32_t *leads, int ngroups, MatView<V>
             k_merge_group<V, 8><<<ngroups, kMergeThreads, 0, s>>>(leads, A, B, mk, mm, mc, cv,
                                                                    mlen, g);
             break;
+        case 32:
+            k_merge_group<V, 32><<<ngroups, kMergeThreads, 0, s>>>(leads, A, B, mk, mm, mc, cv,
+                                                                    mlen, g);
+            break;
         default:
             k_merge_group<V, 16><<<ngroups, kMergeThreads, 0, s>>>(leads, A, B, mk, mm, mc, cv,
                                                                     mlen, g);
@@ -1662,6 +2009,61 @@ template void launch_spgemm_group<float>(int, const int32_t *, int, const int32_
                                          const int32_t *, int64_t, const int64_t *, int32_t *,
                                          float *, int32_t *, int32_t *, int32_t *, double *,
                                          double *, int64_t *, ProductEpi, hipStream_t);
+
+template <typename V, int R, int NB>
+static void regtile_launch(const int32_t *leads, int ngroups, const int32_t *mk, const uint32_t *mm,
+                           const int32_t *mc, const V *cv, const int32_t *mlen, MatView<V> A,
+                           MatView<V> B, MatView<V> D, double coef, double dcoef, double diag,
+                           const int32_t *lo, const int32_t *span, int64_t base,
+                           const int64_t *off, int32_t *out_col, V *out_val, int32_t *out_len,
+                           int32_t *cursor, int32_t *cnext, double *sq_prod, double *sq_out,
+                           int64_t *out_count, ProductEpi epi, hipStream_t s) {
+    k_spgemm_regtile<V, R, NB, kRegTileThreads><<<ngroups, kRegTileThreads, 0, s>>>(
+        leads, mk, mm, mc, cv, mlen, A, B, D, (V)coef, (V)dcoef, (V)diag, lo, span, off, base,
+        out_col, out_val, out_len, cursor, cnext, sq_prod, sq_out, out_count, epi);
+}
+
+bool regtile_supported(int group, int nb) {
+    return (group == 8 && (nb == 4 || nb == 8)) || (group == 16 && (nb == 2 || nb == 4)) ||
+           (group == 32 && nb == 2);
+}
+
+template <typename V>
+void launch_spgemm_regtile(int group, int nb, const int32_t *leads, int ngroups,
+                           const int32_t *mk, const uint32_t *mm, const int32_t *mc, const V *cv,
+                           const int32_t *mlen, MatView<V> A, MatView<V> B, MatView<V> D,
+                           double coef, double dcoef, double diag, const int32_t *lo,
+                           const int32_t *span, int64_t base, const int64_t *off,
+                           int32_t *out_col, V *out_val, int32_t *out_len, int32_t *cursor,
+                           int32_t *cnext, double *sq_prod, double *sq_out, int64_t *out_count,
+                           ProductEpi epi, hipStream_t s) {
+    if (ngroups <= 0) return;
+#define SFN_RT_ARGS                                                                           \
+    leads, ngroups, mk, mm, mc, cv, mlen, A, B, D, coef, dcoef, diag, lo, span, base, off,    \
+        out_col, out_val, out_len, cursor, cnext, sq_prod, sq_out, out_count, epi, s
+    if (group == 8 && nb == 8) regtile_launch<V, 8, 8>(SFN_RT_ARGS);
+    else if (group == 8) regtile_launch<V, 8, 4>(SFN_RT_ARGS);
+    else if (group == 16 && nb == 2) regtile_launch<V, 16, 2>(SFN_RT_ARGS);
+    else if (group == 16) regtile_launch<V, 16, 4>(SFN_RT_ARGS);
+    else regtile_launch<V, 32, 2>(SFN_RT_ARGS);
+#undef SFN_RT_ARGS
+}
+template void launch_spgemm_regtile<double>(int, int, const int32_t *, int, const int32_t *,
+                                            const uint32_t *, const int32_t *, const double *,
+                                            const int32_t *, MatView<double>, MatView<double>,
+                                            MatView<double>, double, double, double,
+                                            const int32_t *, const int32_t *, int64_t,
+                                            const int64_t *, int32_t *, double *, int32_t *,
+                                            int32_t *, int32_t *, double *, double *, int64_t *,
+                                            ProductEpi, hipStream_t);
+template void launch_spgemm_regtile<float>(int, int, const int32_t *, int, const int32_t *,
+                                           const uint32_t *, const int32_t *, const float *,
+                                           const int32_t *, MatView<float>, MatView<float>,
+                                           MatView<float>, double, double, double,
+                                           const int32_t *, const int32_t *, int64_t,
+                                           const int64_t *, int32_t *, float *, int32_t *,
+                                           int32_t *, int32_t *, double *, double *, int64_t *,
+                                           ProductEpi, hipStream_t);
 
 template <typename V>
 void launch_spgemm(int cls, const int32_t *rows, int nrows, MatView<V> A, MatView<V> B,

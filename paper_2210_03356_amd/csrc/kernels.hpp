@@ -123,6 +123,22 @@ void launch_spgemm_group(int group, const int32_t *leads, int ngroups, const int
                          int64_t *out_count, ProductEpi epi, hipStream_t s);
 // tile = LDS accumulator columns per row of the group
 BinCfg group_config(int group, int value_bytes);
+// The same product for groups of `group` rows (merged lists as above) with
+// register accumulators: windows of 64*nb columns placed where the group's
+// rows still have entries, one LDS write/read/clear per B entry and the
+// group's multiply-adds in registers (k_spgemm_regtile).  Supported (group,
+// nb): (8, 4), (8, 8), (16, 2), (16, 4), (32, 2).  Not for epi.short_b.
+bool regtile_supported(int group, int nb);
+constexpr int kRegTileThreadsHost = 512;
+template <typename V>
+void launch_spgemm_regtile(int group, int nb, const int32_t *leads, int ngroups,
+                           const int32_t *mk, const uint32_t *mm, const int32_t *mc, const V *cv,
+                           const int32_t *mlen, MatView<V> A, MatView<V> B, MatView<V> D,
+                           double coef, double dcoef, double diag, const int32_t *lo,
+                           const int32_t *span, int64_t base, const int64_t *off,
+                           int32_t *out_col, V *out_val, int32_t *out_len, int32_t *cursor,
+                           int32_t *cnext, double *sq_prod, double *sq_out, int64_t *out_count,
+                           ProductEpi epi, hipStream_t s);
 
 // Symmetric products (the full matrix C from its lower triangle L, both compact):
 // cnt[c] += #{j > c : L(j, c) != 0}; out = a + b (row lengths);
