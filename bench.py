@@ -274,6 +274,9 @@ def serve_bench(args):
         "requests": len(reqs), "arrival_rate_per_s": args.serve_rate,
         "wall_s": round(wall, 2), "ok_within_tol": ok, "ticks": st["ticks"],
         "max_active": st["max_active"], "busy_s": round(st["busy_seconds"], 2),
+        "failed": st["failed"],
+        "tick_breakdown_s": {k: round(st[k + "_seconds"], 2)
+                             for k in ("relayout", "residual", "update", "filter")},
         "sequential_sign_ns_solves_per_s": round(len(reqs) / seq, 3),
         "offered_load_vs_sequential": round(args.serve_rate * seq / len(reqs), 2),
         "config": {"workload": "c5: Poisson stream, 1D (sigma=2, m=4) / 2D (sigma=4, m=8) / "

@@ -243,6 +243,10 @@ typedef struct {
     size_t hbm_budget_bytes; /* admission budget for resident iterates; 0 = automatic */
     int max_slots;           /* maximum requests advanced together; 0 = 64 */
     int max_queue;           /* maximum queued requests; 0 = 100000 */
+    size_t mem_limit_bytes;  /* hard cap on the device memory of the batch (iterates,
+                                residuals, product staging); 0 = none.  A tick that
+                                would exceed it fails only the request with the most
+                                resident entries (SIGN_ENOMEM); the others go on */
 } sign_server_opts;
 
 SIGNFN_API int sign_server_create(const sign_server_opts *o, sign_server **s);
@@ -265,6 +269,11 @@ typedef struct {
     double busy_seconds;       /* time with at least one request on the device */
     int64_t ticks;             /* batched iterations launched */
     int64_t max_active;        /* most requests advanced together */
+    int64_t failed;            /* requests that ended with an error */
+    /* wall time of the worker by phase (each phase ends when the device has
+       finished it): admission and batch relayout, residual products with
+       their norms and certifications, update products, filters/mirroring */
+    double relayout_seconds, residual_seconds, update_seconds, filter_seconds;
 } sign_server_stats;
 
 SIGNFN_API int sign_server_stats_get(sign_server *s, sign_server_stats *st);

@@ -63,11 +63,60 @@ double wall() {
         .count();
 }
 
+// Hard cap on the device memory held by the batch (sign_server_opts
+// mem_limit_bytes): the batch allocator refuses a request that would take the
+// bytes it holds beyond the cap, which surfaces as SIGN_ENOMEM on the host.
+struct MemCap {
+    std::mutex mu;
+    size_t limit = 0, held = 0;
+    std::unordered_map<void *, size_t> sizes;
+};
+
+void *cap_alloc(size_t bytes, void *, void *ctx) {
+    auto *c = static_cast<MemCap *>(ctx);
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (c->held + bytes > c->limit) return nullptr;
+    void *p = nullptr;
+    try {
+        p = Pool::instance().get(bytes);
+    } catch (const Error &) {
+        return nullptr;
+    }
+    c->held += bytes;
+    c->sizes[p] = bytes;
+    return p;
+}
+
+void cap_free(void *p, void *, void *ctx) {
+    auto *c = static_cast<MemCap *>(ctx);
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        auto it = c->sizes.find(p);
+        if (it != c->sizes.end()) {
+            c->held -= it->second;
+            c->sizes.erase(it);
+        }
+    }
+    Pool::instance().put(p);
+}
+
+// Per-request state a tick changes before its last product: restored when the
+// tick is abandoned (a request failed alone) and run again.
+struct TickMark {
+    Req *r;
+    size_t es, trace;
+    int n_up, n_flat;
+};
+
 }  // namespace
 
 struct sign_server {
     int device = 0;
     size_t budget = 0, used = 0;
+    MemCap cap;             // the batch allocator's cap (when mem_limit_bytes > 0)
+    Allocator al_out;       // results handed to callers: plain pool, no cap
+    int64_t failed = 0;
+    double t_relayout = 0.0, t_residual = 0.0, t_update = 0.0, t_filter = 0.0;
     int max_slots = 64, max_queue = 100000;
     hipStream_t stream = nullptr;
     Allocator al;
@@ -94,6 +143,11 @@ struct sign_server {
     void tick(Workspace &w);
     void finish(Req *r, int status, Workspace &w);
     void fail_all(int status, const std::string &msg);
+    // one request ends with an error; its rows stay masked until the next relayout
+    void fail_one(Req *r, int status, const std::string &msg);
+    // the live request holding the most entries of the batch iterate
+    Req *largest_live(Workspace &w);
+    void drop_temporaries(Workspace &w);
 };
 
 namespace {
@@ -193,6 +247,7 @@ void sign_server::fail_all(int status, const std::string &msg) {
             r->t_done = wall();
             used -= std::min(used, r->pred);
             ++completed;
+            ++failed;
         }
         r->in_batch = false;
         r->live = false;
@@ -204,15 +259,58 @@ void sign_server::fail_all(int status, const std::string &msg) {
     X.bind(&al);
 }
 
+void sign_server::fail_one(Req *r, int status, const std::string &msg) {
+    if (r->in_batch && r->live)
+        launch_fill_u8(skip.as<uint8_t>(), r->base, r->base + r->n, 1, stream);
+    std::lock_guard<std::mutex> lk(mu);
+    r->status = status;
+    r->err = msg;
+    r->live = false;
+    r->t_done = wall();
+    used -= std::min(used, r->pred);
+    ++completed;
+    ++failed;
+}
+
+Req *sign_server::largest_live(Workspace &w) {
+    (void)w;
+    std::vector<int64_t> beg((size_t)X.n + 1, 0);
+    if (X.n > 0 && X.begp())
+        SFN_HIP(hipMemcpyAsync(beg.data(), X.begp(), sizeof(int64_t) * (X.n + 1),
+                               hipMemcpyDeviceToHost, stream));
+    SFN_HIP(hipStreamSynchronize(stream));
+    Req *best = nullptr;
+    int64_t most = -1;
+    for (Req *r : active) {
+        if (!r->live) continue;
+        const int64_t e = (r->base + r->n <= X.n) ? beg[r->base + r->n] - beg[r->base] : 0;
+        if (e > most || (e == most && best && r->n > best->n)) { most = e; best = r; }
+    }
+    return best;
+}
+
+void sign_server::drop_temporaries(Workspace &w) {
+    (void)hipStreamSynchronize(stream);
+    for (DMat<double> *m : {&R, &Xb, &Xn, &Xl, &Xt}) {
+        *m = DMat<double>();
+        m->bind(&al);
+    }
+    for (DevBuf *b : {&w.stage_col, &w.stage_val, &w.cursor, &w.cnext, &w.mk, &w.mm, &w.mc,
+                      &w.cv, &w.symtcol, &w.symtval})
+        b->reset();
+    w.row_skip = nullptr;
+}
+
 void sign_server::finish(Req *r, int status, Workspace &w) {
-    // copy the request's rows out of the batch, columns back to 0-based
+    // copy the request's rows out of the batch, columns back to 0-based (into
+    // memory the caller owns after the poll: the plain pool, not the batch cap)
     DMat<double> out;
-    out.bind(&al);
+    out.bind(&al_out);
     std::vector<SegMove> mv{{X.view(), r->base, 0, r->n, -r->base}};
     DevBuf tab(&al);
     assemble(w, tab, mv, r->n, out);
     SFN_HIP(hipStreamSynchronize(stream));
-    sign_result *res = result_from(al, out);
+    sign_result *res = result_from(al_out, out);
     res->trace = std::move(r->trace);
     sign_stats &st = res->stats;
     st.status = status;
@@ -234,29 +332,25 @@ void sign_server::finish(Req *r, int status, Workspace &w) {
     ++completed;
 }
 
+// Admission and compaction: the live requests of the current batch move to
+// the front (finished ones leave), the admitted ones are appended as new
+// diagonal blocks.  Nothing of the server's state changes until the new batch
+// matrix and its tables exist, so a failure (an allocation refused) leaves the
+// running batch as it was and concerns only the admitted requests.
 void sign_server::relayout(std::vector<Req *> &admit, Workspace &w) {
-    std::vector<Req *> keep;
-    {
-        std::lock_guard<std::mutex> lk(mu);
-        for (Req *r : active) {
-            if (r->live) {
-                keep.push_back(r);
-            } else {
-                r->in_batch = false;
-                if (r->collected) delete r;
-            }
-        }
-        for (Req *r : admit) r->in_batch = true;
-    }
+    std::vector<Req *> keep, gone;
+    for (Req *r : active) (r->live ? keep : gone).push_back(r);
     std::vector<SegMove> mv;
+    std::vector<int64_t> base_new;
     int64_t rows = 0;
     for (Req *r : keep) {
         mv.push_back({X.view(), r->base, rows, r->n, rows - r->base});
-        r->base = rows;
+        base_new.push_back(rows);
         rows += r->n;
     }
     // upload and scale the new requests: X_1 = A / ||A||_inf
     std::vector<DMat<double>> fresh(admit.size());
+    std::vector<double> scale(admit.size(), 1.0);
     for (size_t q = 0; q < admit.size(); ++q) {
         Req *r = admit[q];
         DMat<double> &F = fresh[q];
@@ -275,39 +369,67 @@ void sign_server::relayout(std::vector<Req *> &admit, Workspace &w) {
         F.nnz = (int64_t)r->ci.size();
         w.rs1.ensure(sizeof(double) * r->n);
         launch_row_abs_sum(F.begp(), F.valp(), 0, r->n, w.rs1.as<double>(), stream);
-        r->c = r->o.scale > 0.0 ? r->o.scale : w.max_rows(w.rs1, r->n);
-        if (!(r->c > 0.0)) r->c = 1.0;
-        launch_scale_copy<double, double>(F.valp(), F.valp(), F.nnz, 1.0 / r->c, stream);
+        double c = r->o.scale > 0.0 ? r->o.scale : w.max_rows(w.rs1, r->n);
+        if (!(c > 0.0)) c = 1.0;
+        scale[q] = c;
+        launch_scale_copy<double, double>(F.valp(), F.valp(), F.nnz, 1.0 / c, stream);
         mv.push_back({F.view(), 0, rows, r->n, rows});
-        r->base = rows;
-        r->live = true;
+        base_new.push_back(rows);
         rows += r->n;
-        keep.push_back(r);
     }
     DMat<double> X2;
     X2.bind(&al);
     assemble(w, moves, mv, rows, X2);
+    // tables of the new batch, in buffers of their own until the commit (the
+    // running batch keeps its tables if an allocation is refused here)
+    const int S = (int)(keep.size() + admit.size());
+    DevBuf seg2(&al), rseg2(&al), skip2(&al), rsym2(&al);
+    seg2.ensure(sizeof(int64_t) * (S + 1));
+    rseg2.ensure(sizeof(int32_t) * std::max<int64_t>(rows, 1));
+    skip2.ensure(std::max<int64_t>(rows, 1));
+    rsym2.ensure(std::max<int64_t>(rows, 1));
+    w.rs3.ensure(sizeof(double) * std::max<int64_t>(rows, 1));
+    w.red.ensure(sizeof(double) * std::max(S, 1));
+    SFN_HIP(hipStreamSynchronize(stream));
+
+    // commit
+    std::swap(seg_d, seg2);
+    std::swap(row_seg, rseg2);
+    std::swap(skip, skip2);
+    std::swap(rowsym, rsym2);
     std::swap(X, X2);
     X2 = DMat<double>();
     fresh.clear();
+    const size_t nkeep = keep.size();
+    for (size_t q = 0; q < nkeep; ++q) keep[q]->base = base_new[q];
+    for (size_t q = 0; q < admit.size(); ++q) {
+        Req *r = admit[q];
+        r->base = base_new[nkeep + q];
+        r->c = scale[q];
+        r->live = true;
+        keep.push_back(r);
+    }
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        for (Req *r : gone) {
+            r->in_batch = false;
+            if (r->collected) delete r;
+        }
+        for (Req *r : admit) r->in_batch = true;
+    }
     active = keep;
     active_count = (int64_t)active.size();
     max_active = std::max<int64_t>(max_active, (int64_t)active.size());
     // segment tables
-    const int S = (int)active.size();
     std::vector<int64_t> seg_h(S + 1, 0);
     for (int q = 0; q < S; ++q) seg_h[q + 1] = seg_h[q] + active[q]->n;
-    seg_d.ensure(sizeof(int64_t) * (S + 1));
     SFN_HIP(hipMemcpyAsync(seg_d.get(), seg_h.data(), sizeof(int64_t) * (S + 1),
                            hipMemcpyHostToDevice, stream));
-    row_seg.ensure(sizeof(int32_t) * std::max<int64_t>(rows, 1));
-    skip.ensure(std::max<int64_t>(rows, 1));
     int64_t maxr = 0;
     for (Req *r : active) maxr = std::max(maxr, r->n);
     launch_row_segments(seg_d.as<int64_t>(), S, maxr, row_seg.as<int32_t>(), stream);
     launch_fill_u8(skip.as<uint8_t>(), 0, rows, 0, stream);
     // symmetric requests with unfiltered residuals take the symmetric products
-    rowsym.ensure(std::max<int64_t>(rows, 1));
     any_sym = false;
     for (Req *r : active) {
         const bool sy = r->sym && !r->o.filter_y;
@@ -324,6 +446,12 @@ void sign_server::relayout(std::vector<Req *> &admit, Workspace &w) {
 }
 
 void sign_server::tick(Workspace &w) {
+    double tp = wall();
+    auto phase = [&](double &acc) {
+        const double t = wall();
+        acc += t - tp;
+        tp = t;
+    };
     const int S = (int)active.size();
     const int64_t *segd = seg_d.as<int64_t>();
     w.row_skip = skip.as<uint8_t>();
@@ -391,6 +519,7 @@ void sign_server::tick(Workspace &w) {
             std::fill(bound.begin(), bound.end(), 0);
         }
     }
+    phase(t_residual);
     std::vector<double> tau(S, 0.0), tau_r(S, 0.0);
     bool any_live = false, any_fy = false;
     for (int q = 0; q < S; ++q) {
@@ -426,11 +555,13 @@ void sign_server::tick(Workspace &w) {
         tau[q] = nsf_budget(e, r->xf, r->o.tol, r->o.c_fixed, r->o.switch_res);
         if (r->o.filter_y) { tau_r[q] = tau[q]; any_fy = true; }
     }
+    phase(t_relayout);  // copies of the finished requests out of the batch
     if (!any_live) return;
     std::vector<int> bstar;
     if (any_fy) {
         filter_seg(w, R, seg_h, segd, row_seg.as<int32_t>(), tau_r, Xn, nullptr, nullptr, bstar);
         std::swap(R, Xn);
+        phase(t_filter);
     }
     // updates of all requests: Xbar = X^ + 1/2 X^ R^
     // (rows of symmetric requests: lower triangles, filtered with the entries
@@ -438,6 +569,7 @@ void sign_server::tick(Workspace &w) {
     product<double>(w, X, R, &X, 0.5, 1.0, 0.0, Xb, &w.rs2, nullptr, false, rs != nullptr,
                     nullptr, rs);
     const std::vector<double> d2 = seg_sums(w, w.rs2, segd, S);
+    phase(t_update);
     LowerRows lower;
     lower.rows = rs;
     if (rs) {
@@ -449,6 +581,7 @@ void sign_server::tick(Workspace &w) {
     }
     const std::vector<double> k2 = seg_sums(w, w.rs3, segd, S);
     const std::vector<double> f2 = seg_sums(w, w.rs4, segd, S);
+    phase(t_filter);
     for (int q = 0; q < S; ++q) {
         Req *r = active[q];
         if (!r->live) continue;
@@ -492,21 +625,72 @@ void sign_server::run() {
             }
         }
         const double t0 = wall();
+        // Failures are isolated where the cause is a refused allocation
+        // (SIGN_ENOMEM, a host-side error): a request that does not fit at
+        // admission fails alone (relayout leaves the batch as it was), and a
+        // tick that does not fit fails the live request holding the most entries,
+        // after which the tick runs again for the others from the state before it.
+        // Any other error (a HIP runtime failure) ends every active request.
         try {
-            if (!admit.empty()) relayout(admit, w);
-            bool has_live = false;
-            for (Req *r : active) has_live |= r->live;
-            if (has_live) tick(w);
-            SFN_HIP(hipStreamSynchronize(stream));
+            if (!admit.empty()) {
+                try {
+                    relayout(admit, w);
+                } catch (const Error &e) {
+                    if (e.status != SIGN_ENOMEM) throw;
+                    drop_temporaries(w);
+                    // admit them one at a time: only those that do not fit fail
+                    for (Req *r : admit) {
+                        std::vector<Req *> one{r};
+                        try {
+                            relayout(one, w);
+                        } catch (const Error &e1) {
+                            if (e1.status != SIGN_ENOMEM) throw;
+                            drop_temporaries(w);
+                            fail_one(r, SIGN_ENOMEM,
+                                     std::string("admission: ") + e1.what() +
+                                         " (the running batch is unaffected)");
+                        }
+                    }
+                }
+                t_relayout += wall() - t0;
+            }
+            for (;;) {
+                bool has_live = false;
+                for (Req *r : active) has_live |= r->live;
+                if (!has_live) break;
+                std::vector<TickMark> marks;
+                for (Req *r : active)
+                    if (r->live)
+                        marks.push_back({r, r->es.size(), r->trace.size(), r->n_up, r->n_flat});
+                try {
+                    tick(w);
+                    SFN_HIP(hipStreamSynchronize(stream));
+                    break;
+                } catch (const Error &e) {
+                    if (e.status != SIGN_ENOMEM) throw;
+                    drop_temporaries(w);
+                    // requests the abandoned tick finished keep their results; the
+                    // others return to their state before it
+                    for (const TickMark &m : marks) {
+                        if (!m.r->live) continue;
+                        m.r->es.resize(m.es);
+                        m.r->trace.resize(m.trace);
+                        m.r->n_up = m.n_up;
+                        m.r->n_flat = m.n_flat;
+                    }
+                    Req *victim = largest_live(w);
+                    if (!victim) break;
+                    fail_one(victim, SIGN_ENOMEM,
+                             std::string(e.what()) +
+                                 " (this request holds the most entries of the batch; the "
+                                 "other requests continue)");
+                }
+            }
         } catch (const Error &e) {
             w.row_skip = nullptr;
-            for (Req *r : admit)
-                if (std::find(active.begin(), active.end(), r) == active.end()) active.push_back(r);
             fail_all(e.status, e.what());
         } catch (const std::exception &e) {
             w.row_skip = nullptr;
-            for (Req *r : admit)
-                if (std::find(active.begin(), active.end(), r) == active.end()) active.push_back(r);
             fail_all(SIGN_EDEVICE, e.what());
         }
         busy += wall() - t0;
@@ -537,6 +721,13 @@ int sign_server_create(const sign_server_opts *o, sign_server **s) {
             throw Error(SIGN_EDEVICE, "hipStreamCreate failed");
         }
         sv->al.stream = sv->stream;
+        sv->al_out.stream = sv->stream;
+        if (o->mem_limit_bytes > 0) {
+            sv->cap.limit = o->mem_limit_bytes;
+            sv->al.alloc = cap_alloc;
+            sv->al.release = cap_free;
+            sv->al.ctx = &sv->cap;
+        }
         for (DevBuf *b : {&sv->seg_d, &sv->row_seg, &sv->skip, &sv->moves, &sv->rowsym})
             b->bind(&sv->al);
         for (DMat<double> *m : {&sv->X, &sv->R, &sv->Xb, &sv->Xn, &sv->Xl, &sv->Xt})
@@ -631,6 +822,11 @@ int sign_server_stats_get(sign_server *s, sign_server_stats *st) {
     st->ticks = s->ticks;
     st->max_active = s->max_active;
     st->busy_seconds = s->busy;
+    st->failed = s->failed;
+    st->relayout_seconds = s->t_relayout;
+    st->residual_seconds = s->t_residual;
+    st->update_seconds = s->t_update;
+    st->filter_seconds = s->t_filter;
     if (!s->latencies_ms.empty()) {
         std::vector<double> v = s->latencies_ms;
         std::sort(v.begin(), v.end());

@@ -66,13 +66,16 @@ class sign_iter_stats(C.Structure):
 
 class sign_server_opts(C.Structure):
     _fields_ = [("device", C.c_int), ("hbm_budget_bytes", C.c_size_t), ("max_slots", C.c_int),
-                ("max_queue", C.c_int)]
+                ("max_queue", C.c_int), ("mem_limit_bytes", C.c_size_t)]
 
 
 class sign_server_stats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("active", C.c_int64),
                 ("queued", C.c_int64), ("p50_ms", C.c_double), ("p99_ms", C.c_double),
-                ("busy_seconds", C.c_double), ("ticks", C.c_int64), ("max_active", C.c_int64)]
+                ("busy_seconds", C.c_double), ("ticks", C.c_int64), ("max_active", C.c_int64),
+                ("failed", C.c_int64), ("relayout_seconds", C.c_double),
+                ("residual_seconds", C.c_double), ("update_seconds", C.c_double),
+                ("filter_seconds", C.c_double)]
 
 
 _lib = None
@@ -350,9 +353,10 @@ class Server:
     """Continuous-batching server (sign_server_*); requests are host CSR."""
 
     def __init__(self, device: int = 0, hbm_budget_bytes: int = 0, max_slots: int = 0,
-                 max_queue: int = 0):
+                 max_queue: int = 0, mem_limit_bytes: int = 0):
         o = sign_server_opts(device=device, hbm_budget_bytes=hbm_budget_bytes,
-                             max_slots=max_slots, max_queue=max_queue)
+                             max_slots=max_slots, max_queue=max_queue,
+                             mem_limit_bytes=mem_limit_bytes)
         p = C.c_void_p()
         st = load().sign_server_create(C.byref(o), C.byref(p))
         if st != 0:

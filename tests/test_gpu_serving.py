@@ -140,3 +140,78 @@ def test_poll_and_submit_errors(sf):
             srv.submit(A, sf.default_opts(precision=1))
     finally:
         srv.close()
+
+
+def _wait_outcomes(srv, tickets, timeout=180.0):
+    """{ticket: Result or SignError} once every ticket has ended."""
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets):
+        for t in tickets:
+            if t in out:
+                continue
+            try:
+                r = srv.poll(t)
+            except Exception as e:  # the request ended with an error
+                out[t] = e
+                continue
+            if r is not None:
+                out[t] = r
+        if time.time() - t0 > timeout:
+            raise TimeoutError(f"{len(out)}/{len(tickets)} done")
+        time.sleep(0.002)
+    return out
+
+
+def test_one_request_fails_alone_under_a_memory_cap(sf):
+    """With the batch's device memory capped (mem_limit_bytes), a request whose
+    iterates outgrow the cap ends with ENOMEM -- a refused allocation on the host,
+    no device fault -- while the requests sharing its batch go on from the state
+    before the failed tick and finish with their solo results."""
+    small = _requests()[:4]
+    big = W.laplacian_2d(128, jitter=0.05, seed=17, m=8.0)   # residuals of ~0.6 GB
+    srv = sf.Server(hbm_budget_bytes=1 << 40, mem_limit_bytes=256 << 20)
+    try:
+        tickets = [srv.submit(A, sf.default_opts(tol=tol)) for A, tol in small]
+        tb = srv.submit(big, sf.default_opts(tol=1e-10))
+        out = _wait_outcomes(srv, tickets + [tb])
+        st = srv.stats()
+    finally:
+        srv.close()
+    err = out[tb]
+    assert isinstance(err, sf.SignError) and err.status == -2, err
+    assert "other requests continue" in str(err)
+    assert st["failed"] == 1 and st["completed"] == len(small) + 1
+    for (A, tol), t in zip(small, tickets):
+        r = out[t]
+        assert not isinstance(r, Exception), r
+        assert r.status == "OK"
+        solo_r = sf.sign_ns(sf.DeviceCsr.from_host(A), sf.default_opts(tol=tol))
+        assert _rel(r.to_scipy(), solo_r.to_scipy()) <= 1e-12
+        assert r.stats()["iters"] == solo_r.stats()["iters"]
+        assert len(r.trace()) == len(solo_r.trace())
+
+
+def test_admission_that_does_not_fit_fails_alone(sf):
+    """A request whose upload alone exceeds the cap fails at admission; the running
+    batch is unaffected and later requests are served."""
+    reqs = _requests()[:2]
+    huge = W.laplacian_1d(2_000_000, sigma=2.0, jitter=0.05, seed=3, m=4.0)  # ~96 MB upload
+    srv = sf.Server(hbm_budget_bytes=1 << 40, mem_limit_bytes=64 << 20)
+    try:
+        first = [srv.submit(A, sf.default_opts(tol=tol)) for A, tol in reqs]
+        th = srv.submit(huge, sf.default_opts(tol=1e-6))
+        after = srv.submit(*(lambda A, tol: (A, sf.default_opts(tol=tol)))(*_requests()[2]))
+        out = _wait_outcomes(srv, first + [th, after])
+        st = srv.stats()
+    finally:
+        srv.close()
+    err = out[th]
+    assert isinstance(err, sf.SignError) and err.status == -2, err
+    assert "admission" in str(err)
+    assert st["failed"] == 1
+    for (A, tol), t in zip(reqs + [_requests()[2]], first + [after]):
+        r = out[t]
+        assert not isinstance(r, Exception), r
+        ref = oracle.nsf(A, tol=tol).to_scipy()
+        assert _rel(r.to_scipy(), ref) <= max(1e-10, 10 * tol)
