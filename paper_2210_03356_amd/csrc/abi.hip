@@ -112,8 +112,11 @@ void convert(Workspace &w, const DMat<Vi> &In, DMat<Vo> &Out) {
 }
 
 // Mixed precision (precision 1):
-//  1. the NSF loop in FP32 values / FP32 accumulation (FP64 norms, budget and
-//     scaling) to its rounding floor, tol32 = max(tol, 32 u32 sqrt(n)), with
+//  1. the NSF loop with FP32 values (each product's sums accumulated in FP64
+//     LDS -- a product of two FP32 values is exact in FP64, and LDS atomic adds
+//     of FP32 are far slower on this chip -- and rounded once to FP32 on
+//     store; FP64 norms, budget and scaling) to its rounding floor,
+//     tol32 = max(tol, 32 u32 sqrt(n)), with
 //     the budget c_fixed*tol32 that matches FP32 resolution;
 //  2. one FP64 Newton-Schulz step (removes the error part that commutes with
 //     the sign);

@@ -19,7 +19,7 @@ Workspace::Workspace(Allocator *a, size_t staging_bytes) : al(a), s(a->stream) {
     for (DevBuf *b : {&lo, &span, &cap, &work, &capoff, &workoff, &tmp, &bins, &counts, &cursor,
                       &stage_col, &stage_val, &rs1, &rs2, &rs3, &rs4, &icnt, &hist, &tau,
                       &bstar, &seg, &red, &flag, &zero_b, &cstat, &mk, &mm, &mc, &cv, &mlen, &cnext, &symcnt, &symoff, &symfill,
-                      &symtcol, &symtval, &rs5, &whole, &sums, &pst})
+                      &symtcol, &symtval, &rs5, &whole, &sums, &pst, &rb})
         b->bind(a);
     // rows per workgroup for wide rows: 1 (off), 2, 4, 8 or 16
     if (const char *ge = std::getenv("SIGNFN_ROW_GROUP")) {
@@ -101,6 +101,32 @@ void Workspace::hot_stats(sign_stats &st) const {
     st.hot_bytes = c.bytes;
     st.hot_products = c.products;
     st.hot_gathered = c.gathered;
+}
+
+int64_t *Workspace::pinned() {
+    // one small page-locked block per host thread, kept for the thread's life:
+    // read-backs land in it without a staging copy
+    thread_local int64_t *p = nullptr;
+    thread_local int64_t fallback[64];
+    if (!p) {
+        void *q = nullptr;
+        if (hipHostMalloc(&q, sizeof(int64_t) * 64, hipHostMallocDefault) == hipSuccess && q)
+            p = static_cast<int64_t *>(q);
+        else {
+            (void)hipGetLastError();
+            p = fallback;
+        }
+    }
+    return p;
+}
+
+const int64_t *Workspace::read_back(const ScalarGather &g) {
+    rb.ensure(sizeof(int64_t) * 64);
+    int64_t *h = pinned();
+    launch_gather_scalars(g, rb.as<int64_t>(), s);
+    SFN_HIP(hipMemcpyAsync(h, rb.get(), sizeof(int64_t) * (size_t)g.n, hipMemcpyDeviceToHost, s));
+    SFN_HIP(hipStreamSynchronize(s));
+    return h;
 }
 
 double Workspace::sum_rows(const DevBuf &rows, int64_t n) {
@@ -204,19 +230,29 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
                               0, s);
     launch_exclusive_scan_i64(w.work.as<int64_t>(), n, w.workoff.as<int64_t>(),
                               w.tmp.as<int64_t>(), 0, s);
+    // totals of the plan (and B's density) come back in one copy
     int64_t tot[2];
-    SFN_HIP(hipMemcpyAsync(&tot[0], w.capoff.as<int64_t>() + n, sizeof(int64_t),
-                           hipMemcpyDeviceToHost, s));
-    SFN_HIP(hipMemcpyAsync(&tot[1], w.workoff.as<int64_t>() + n, sizeof(int64_t),
-                           hipMemcpyDeviceToHost, s));
     unsigned long long pst[2] = {0, 0};
-    if (w.auto_group || w.progress) {  // (progress: reported with the product)
+    const bool want_pst = w.auto_group || w.progress;  // (progress: reported with the product)
+    ScalarGather pg;
+    pg.add(w.capoff.as<int64_t>() + n);
+    pg.add(w.workoff.as<int64_t>() + n);
+    if (want_pst) {
         w.pst.ensure(2 * sizeof(unsigned long long));
         SFN_HIP(hipMemsetAsync(w.pst.get(), 0, 2 * sizeof(unsigned long long), s));
         launch_row_density<V>(B.view(), w.pst.as<unsigned long long>(), s);
-        SFN_HIP(hipMemcpyAsync(pst, w.pst.get(), sizeof(pst), hipMemcpyDeviceToHost, s));
+        pg.add(w.pst.as<unsigned long long>());
+        pg.add(w.pst.as<unsigned long long>() + 1);
     }
-    SFN_HIP(hipStreamSynchronize(s));
+    {
+        const int64_t *h = w.read_back(pg);
+        tot[0] = h[0];
+        tot[1] = h[1];
+        if (want_pst) {
+            pst[0] = (unsigned long long)h[2];
+            pst[1] = (unsigned long long)h[3];
+        }
+    }
     const int64_t total_cap = tot[0];
     w.products += tot[1];
     ProductEpi epi;
@@ -398,9 +434,20 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
         // compact row starts of this batch, continuing from the previous batches
         launch_exclusive_scan_i32(C.lenp() + r0, r1 - r0, C.begp() + r0,
                                   w.tmp.as<int64_t>(), running, s);
-        int64_t cs[8 * kClasses];
-        SFN_HIP(hipMemcpyAsync(cs, w.cstat.get(), sizeof(cs), hipMemcpyDeviceToHost, s));
-        const int64_t end = read_scalar(C.begp() + r1, s);
+        // the class statistics and the stored total (gathered into the unused
+        // slot 0 of class 0) come back in one copy
+        int64_t *cs = Workspace::pinned();
+        {
+            ScalarGather eg;
+            eg.add(C.begp() + r1);
+            launch_gather_scalars(eg, w.cstat.as<int64_t>(), s);
+            SFN_HIP(hipMemcpyAsync(cs, w.cstat.get(), sizeof(int64_t) * 8 * kClasses,
+                                   hipMemcpyDeviceToHost, s));
+            SFN_HIP(hipStreamSynchronize(s));
+        }
+        int64_t cs_h[8 * kClasses];
+        std::memcpy(cs_h, cs, sizeof(cs_h));
+        const int64_t end = cs_h[0];
         {
             float mm = 0.f;
             SFN_HIP(hipEventElapsedTime(&mm, w.ev[0], w.ev[1]));
@@ -422,7 +469,7 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
                 w.rt_used_group = group;
                 w.rt_used_nb = w.rt_nb;
             }
-            const int64_t *q = cs + cls * 8;
+            const int64_t *q = cs_h + cls * 8;
             c.launches += 1;
             c.rows += cls == 4 ? (int64_t)group * cnt[cls] : cnt[cls];
             c.products += q[1];
@@ -498,10 +545,14 @@ void symmetrize(Workspace &w, const DMat<V> &L, DMat<V> &C, LowerRows lower) {
     launch_add_len(L.lenp(), w.symcnt.as<int32_t>(), n, C.lenp(), s);
     launch_exclusive_scan_i32(C.lenp(), n, C.begp(), w.tmp.as<int64_t>(), 0, s);
     int64_t tot[2];
-    SFN_HIP(hipMemcpyAsync(&tot[0], C.begp() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    SFN_HIP(hipMemcpyAsync(&tot[1], w.symoff.as<int64_t>() + n, sizeof(int64_t),
-                           hipMemcpyDeviceToHost, s));
-    SFN_HIP(hipStreamSynchronize(s));
+    {
+        ScalarGather g;
+        g.add(C.begp() + n);
+        g.add(w.symoff.as<int64_t>() + n);
+        const int64_t *h = w.read_back(g);
+        tot[0] = h[0];
+        tot[1] = h[1];
+    }
     C.ensure_entries(tot[0]);
     w.symtcol.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(tot[1], 1));
     w.symtval.ensure(sizeof(V) * (size_t)std::max<int64_t>(tot[1], 1));
@@ -563,13 +614,11 @@ int filter(Workspace &w, const DMat<V> &In, double tau, DMat<Vo> &Out, DevBuf *s
     w.hist.ensure(sizeof(uint64_t) * kBuckets);
     w.seg.ensure(2 * sizeof(int64_t));
     w.tau.ensure(sizeof(double));
-    w.bstar.ensure(sizeof(int));
+    w.bstar.ensure(sizeof(int64_t));  // read back as a 64-bit word
     w.tmp.ensure(sizeof(int64_t) * scan_tmp_elems(n));
     if (sq_keep) sq_keep->ensure(sizeof(double) * n);
     if (sq_drop) sq_drop->ensure(sizeof(double) * n);
-    const int64_t h[2] = {0, n};
-    SFN_HIP(hipMemcpyAsync(w.seg.get(), h, sizeof(h), hipMemcpyHostToDevice, s));
-    SFN_HIP(hipMemcpyAsync(w.tau.get(), &tau, sizeof(double), hipMemcpyHostToDevice, s));
+    launch_set_filter_args(w.seg.as<int64_t>(), n, w.tau.as<double>(), tau, s);
     if (!hist_ready) {
         SFN_HIP(hipMemsetAsync(w.hist.get(), 0, sizeof(uint64_t) * kBuckets, s));
             LowerRows lr;
@@ -584,18 +633,22 @@ int filter(Workspace &w, const DMat<V> &In, double tau, DMat<Vo> &Out, DevBuf *s
                          sq_drop ? sq_drop->as<double>() : nullptr, lrk, s);
     launch_exclusive_scan_i32(Out.lenp(), n, Out.begp(),
                               w.tmp.as<int64_t>(), 0, s);
+    // kept total, cut and (when asked) the candidate count in one copy
     int64_t total;
     int bstar;
-    SFN_HIP(hipMemcpyAsync(&total, Out.begp() + n, sizeof(int64_t),
-                           hipMemcpyDeviceToHost, s));
-    SFN_HIP(hipMemcpyAsync(&bstar, w.bstar.get(), sizeof(int), hipMemcpyDeviceToHost, s));
-    uint64_t hist_h[kBuckets];
-    if (candidates)
-        SFN_HIP(hipMemcpyAsync(hist_h, w.hist.get(), sizeof(hist_h), hipMemcpyDeviceToHost, s));
-    SFN_HIP(hipStreamSynchronize(s));
-    if (candidates) {
-        *candidates = 0;
-        for (int b = 0; b < kBuckets; ++b) *candidates += (int64_t)hist_h[b];
+    {
+        w.rb.ensure(sizeof(int64_t) * 64);
+        ScalarGather g;
+        g.add(Out.begp() + n);
+        g.add(w.bstar.get());
+        launch_gather_scalars(g, w.rb.as<int64_t>(), s);
+        if (candidates) launch_hist_total(w.hist.as<uint64_t>(), w.rb.as<int64_t>() + 2, s);
+        int64_t *h = Workspace::pinned();
+        SFN_HIP(hipMemcpyAsync(h, w.rb.get(), sizeof(int64_t) * 3, hipMemcpyDeviceToHost, s));
+        SFN_HIP(hipStreamSynchronize(s));
+        total = h[0];
+        bstar = (int)(uint32_t)(uint64_t)h[1];  // the low word holds the int
+        if (candidates) *candidates = h[2];
     }
     Out.ensure_entries(total);
     launch_scatter_keep<V, Vo>(In.view(), nullptr, w.bstar.as<int>(), Out.begp(),

@@ -56,6 +56,12 @@ struct Workspace {
     // several row-sum totals with one synchronisation
     std::vector<double> sum_rows_many(std::initializer_list<const DevBuf *> rows, int64_t n);
     DevBuf whole, sums;   // {0, n} segment for whole-matrix sums, their results
+    DevBuf rb;            // device record of scalars read back in one copy
+    // pinned host memory of the calling thread for read-backs (64 int64 words)
+    static int64_t *pinned();
+    // gathers the listed device scalars (int64 words) and copies them to
+    // pinned host memory in one transfer; synchronises the stream
+    const int64_t *read_back(const ScalarGather &g);
     int64_t whole_n = -1;
     double max_rows(const DevBuf &rows, int64_t n);
     // the progress line of an iteration that just ended (when progress is set)

@@ -2,7 +2,9 @@
 //
 // The numeric product is row-wise Gustavson: row i of C = diag*I + coef*A*B + D
 // is accumulated in an LDS-resident dense window of `tile` consecutive columns
-// with native LDS float atomics (ds_add_f64 / ds_add_f32).  Rows whose column
+// with native LDS atomic adds of FP64 values (for FP32-valued matrices too: the
+// product of two FP32 values is exact in FP64, and ds_add_f32 is far slower
+// here); k_spgemm_regtile is a register-accumulator variant.  Rows whose column
 // range exceeds the tile are swept in several windows; B's rows are sorted,
 // so each (row of A entry, window) pair resumes from a per-entry cursor and
 // every B entry is read once per output row.  The finished window is scanned
@@ -1891,6 +1893,45 @@ void launch_move_rows(const SegMove *t, int nseg, int64_t max_rows, const int64_
     if (nseg <= 0 || max_rows <= 0) return;
     k_move_rows<<<dim3(blocks_for(max_rows, 4), nseg), 256, 0, s>>>(t, dst_beg, dst_col, dst_val);
 }
+// One thread gathers scalars scattered over device memory into one record
+// (read back with a single copy); the bucket total of a histogram is summed by
+// one workgroup.
+__global__ void k_gather_scalars(ScalarGather g, int64_t *dst) {
+    for (int j = 0; j < g.n; ++j) dst[j] = *g.src[j];
+}
+
+__global__ __launch_bounds__(256) void k_hist_total(const uint64_t *hist, int64_t *dst) {
+    __shared__ unsigned long long part[256 / kWave];
+    unsigned long long t = 0;
+    for (int b = threadIdx.x; b < kBuckets; b += 256) t += hist[b];
+    t = wave_sum(t);
+    if (lane_id() == 0) part[wave_id()] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long a = 0;
+        for (int w = 0; w < 256 / kWave; ++w) a += part[w];
+        *dst = (int64_t)a;
+    }
+}
+
+__global__ void k_set_filter_args(int64_t *seg, int64_t n, double *tau_dev, double tau) {
+    seg[0] = 0;
+    seg[1] = n;
+    *tau_dev = tau;
+}
+
+void launch_gather_scalars(const ScalarGather &g, int64_t *dst, hipStream_t s) {
+    if (g.n > 0) k_gather_scalars<<<1, 1, 0, s>>>(g, dst);
+}
+
+void launch_hist_total(const uint64_t *hist, int64_t *dst, hipStream_t s) {
+    k_hist_total<<<1, 256, 0, s>>>(hist, dst);
+}
+
+void launch_set_filter_args(int64_t *seg, int64_t n, double *tau_dev, double tau, hipStream_t s) {
+    k_set_filter_args<<<1, 1, 0, s>>>(seg, n, tau_dev, tau);
+}
+
 void launch_fill_u8(uint8_t *p, int64_t lo, int64_t hi, uint8_t v, hipStream_t s) {
     if (hi > lo) k_fill_u8<<<blocks_for(hi - lo, 256), 256, 0, s>>>(p, lo, hi, v);
 }

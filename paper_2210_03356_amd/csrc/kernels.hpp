@@ -200,6 +200,20 @@ template <typename V, typename Vo>
 void launch_scatter_keep(MatView<V> X, const int32_t *row_seg, const int *bstar,
                          const int64_t *dst_ptr, int32_t *dcol, Vo *dval, hipStream_t s);
 
+// ---- read-back helpers -----------------------------------------------------------
+// dst[j] = *src[j] for j < n (int64 words), so scattered scalars come back to
+// the host in one copy
+struct ScalarGather {
+    const int64_t *src[8] = {};
+    int n = 0;
+    void add(const void *p) { src[n++] = static_cast<const int64_t *>(p); }
+};
+void launch_gather_scalars(const ScalarGather &g, int64_t *dst, hipStream_t s);
+// *dst = sum of the kBuckets counts of hist
+void launch_hist_total(const uint64_t *hist, int64_t *dst, hipStream_t s);
+// seg = {0, n}, *tau_dev = tau (one launch instead of two host copies)
+void launch_set_filter_args(int64_t *seg, int64_t n, double *tau_dev, double tau, hipStream_t s);
+
 // ---- misc -----------------------------------------------------------------------
 // row_seg[r] = s for rows of segment s
 void launch_row_segments(const int64_t *seg_rows, int nseg, int64_t max_seg_rows, int32_t *row_seg,
