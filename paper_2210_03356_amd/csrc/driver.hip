@@ -45,6 +45,10 @@ Workspace::Workspace(Allocator *a, size_t staging_bytes) : al(a), s(a->stream) {
         }
     }
     if (const char *pe = std::getenv("SIGNFN_PROGRESS")) progress = pe[0] == '1';
+    // SIGNFN_STAGING_BYTES: staging budget of every product when the call sets none
+    if (staging_bytes == 0)
+        if (const char *sb = std::getenv("SIGNFN_STAGING_BYTES"))
+            staging_bytes = (size_t)std::strtoull(sb, nullptr, 10);
     staging_auto = staging_bytes == 0;
     staging_limit = staging_auto ? auto_staging() : staging_bytes;
     for (auto &e : ev) SFN_HIP(hipEventCreate(&e));
@@ -504,6 +508,9 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
             // ratio of the rows done so far predicts for the whole product
             const double fill = (double)end / (double)capoff_h[r1];
             const double est = (double)end + 1.1 * fill * (double)(total_cap - capoff_h[r1]);
+            w.note("product: batch %zu of %zu outgrew the output (%lld > %lld entries), "
+                   "regrown from the fill ratio %.3f", b + 1, cuts.size() - 1, (long long)end,
+                   (long long)C.capacity(), fill);
             C.ensure_entries(std::max<int64_t>(end, (int64_t)std::min(est, (double)total_cap)),
                              running);
         }

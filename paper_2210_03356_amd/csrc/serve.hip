@@ -152,12 +152,46 @@ struct sign_server {
 
 namespace {
 
-// predicted bytes of the resident iterates of one request: X, R and the
-// candidate matrix in FP64 CSR with a fill ceiling of 500x the rows of A
-size_t predict_bytes(int64_t n, int64_t nnz) {
-    const double avg = std::max(1.0, (double)nnz / (double)n);
-    const double z = std::min((double)n, 500.0 * avg);
-    return (size_t)(12.0 * 3.0 * (double)n * z) + (size_t)(64 * n);
+// Admission table: entries per row that a request holds on the device at its
+// peak -- the iterate, its residual and the update's candidates -- by the average
+// row length of A (which tells the served stencils apart), the matrix order and the
+// tolerance.  Calibrated on FP64 oracle solves of the served families (1D
+// tridiagonal at n = 8192; 2D 5-point and convection-diffusion at 128^2 and 256^2;
+// tol 1e-6 / 1e-10 / 1e-12), peak x 1.25 rounded up; the 2D fill grows with the grid
+// until the sign's decay radius fits, so 2D has two size classes.  Entries: {largest
+// average row length, largest n (0: any), smallest tol, entries per row}; the first
+// match applies, and matrices matching none (e.g. 3D stencils) are predicted dense.
+struct FillEntry {
+    double avg_max;
+    int64_t n_max;
+    double tol_min;
+    double per_row;
+};
+constexpr FillEntry kFill[] = {
+    {3.5, 0, 1e-8, 260},
+    {3.5, 0, 1e-11, 360},
+    {3.5, 0, 0.0, 410},
+    {6.0, 16384, 1e-8, 6810},
+    {6.0, 16384, 1e-11, 11740},
+    {6.0, 16384, 0.0, 14390},
+    {6.0, 0, 1e-8, 8400},
+    {6.0, 0, 1e-11, 14340},
+    {6.0, 0, 0.0, 17720},
+};
+
+// predicted device bytes of one request at its peak: 12 B per FP64 CSR entry plus
+// per-row work arrays
+size_t predict_bytes(int64_t n, int64_t nnz, double tol) {
+    const double avg = (double)nnz / (double)n;
+    double per_row = 3.0 * (double)n;
+    for (const FillEntry &f : kFill) {
+        if (avg <= f.avg_max && (f.n_max == 0 || n <= f.n_max) && tol >= f.tol_min) {
+            per_row = f.per_row;
+            break;
+        }
+    }
+    per_row = std::min(per_row, 3.0 * (double)n);
+    return (size_t)(12.0 * (double)n * per_row) + (size_t)(64 * n);
 }
 
 void host_validate(const sign_csr *A) {
@@ -759,7 +793,7 @@ int sign_serve_submit(sign_server *s, const sign_csr *A, const sign_opts *o, uin
         r->ci.assign(A->col, A->col + A->nnz);
         r->va.assign((const double *)A->val, (const double *)A->val + A->nnz);
         r->o = *o;
-        r->pred = predict_bytes(A->n, A->nnz);
+        r->pred = predict_bytes(A->n, A->nnz, o->tol);
         r->t_submit = wall();
         {
             std::lock_guard<std::mutex> lk(s->mu);

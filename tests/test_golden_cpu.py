@@ -80,3 +80,25 @@ def test_stored_c2_oracle_solve():
         off += L
         assert np.all(np.diff(c) > 0) and L > 0
     assert off == len(g["row_vals"])
+
+
+def test_admission_table_covers_the_oracle_fill():
+    """The server's admission table (kFill in csrc/serve.hip) covers the peak
+    resident entries per row that the oracle's solves of the served families
+    reach (tests/golden/serving_fill.txt), within a 1.5x margin."""
+    import re
+    src = open(os.path.join(os.path.dirname(GOLDEN), "..", "paper_2210_03356_amd", "csrc",
+                            "serve.hip")).read()
+    body = src[src.index("constexpr FillEntry kFill[] = {"):]
+    body = body[:body.index("};")]
+    table = [(float(a), int(b), float(c), float(d)) for a, b, c, d in
+             re.findall(r"\{([\d.]+), (\d+), ([\d.e+-]+), (\d+)\}", body)]
+    assert len(table) >= 6
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "serving_fill.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) >= 9
+    for fam, n, avg, tol, peak in rows:
+        n, avg, tol, peak = int(n), float(avg), float(tol), float(peak)
+        per_row = next(p for a, nm, t, p in table
+                       if avg <= a and (nm == 0 or n <= nm) and tol >= t)
+        assert peak <= per_row <= 1.5 * peak, (fam, n, tol, peak, per_row)

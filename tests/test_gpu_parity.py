@@ -315,13 +315,17 @@ def test_certified_last_residual(sf, name):
     assert r.stats()["res_fro"] == last["e"]
 
 
-@pytest.mark.parametrize("group", ["4", "8"])
+@pytest.mark.parametrize("group", ["2", "4", "8", "auto"])
 @pytest.mark.parametrize("name", ["lap2d_48", "convdiff_30"])
 def test_products_in_many_batches(sf, monkeypatch, name, group):
     """A staging budget of 1 MB splits every product into many row batches, whose
     cursors and merged group lists cover only the batch's A entries: the solve
-    gives what the one-batch solve gives."""
-    monkeypatch.setenv("SIGNFN_ROW_GROUP", group)
+    gives what the one-batch solve gives (forced row groups, pairs, and the
+    per-product rule)."""
+    if group == "auto":
+        monkeypatch.delenv("SIGNFN_ROW_GROUP", raising=False)
+    else:
+        monkeypatch.setenv("SIGNFN_ROW_GROUP", group)
     make, kw = CASES[name]
     A = make()
     one = sf.sign_ns(_dev(sf, A), sf.default_opts(**kw))
@@ -333,6 +337,39 @@ def test_products_in_many_batches(sf, monkeypatch, name, group):
     # the same arithmetic row by row: every product is the oracle's within rounding
     ref = oracle.nsf(A, **kw).to_scipy()
     assert sp.linalg.norm(X2 - ref) <= 1e-10 * sp.linalg.norm(ref)
+
+def _uneven_fill_matrix(n_low=20000, n_high=6000, d=500, seed=31):
+    """Rows whose squares fill their reserved output poorly (entries i-d, i, i+d:
+    9 products fold into 5 columns) followed by rows that fill it almost fully
+    (8 random columns), so a product sized from its first batch's fill ratio
+    outgrows its output in a later batch."""
+    rng = np.random.default_rng(seed)
+    n = n_low + n_high
+    rows = []
+    for i in range(n):
+        if i < n_low:
+            c = [j for j in (i - d, i, i + d) if 0 <= j < n]
+        else:
+            c = sorted(set(rng.integers(0, n, 8).tolist()))
+        rows.append(np.array(c, np.int32))
+    indptr = np.zeros(n + 1, np.int64)
+    indptr[1:] = np.cumsum([len(c) for c in rows])
+    data = rng.uniform(0.5, 1.0, int(indptr[-1]))
+    return W.Csr(n=n, indptr=indptr, indices=np.concatenate(rows), data=data)
+
+
+def test_product_output_regrown_across_batches(sf, monkeypatch, capfd):
+    """Products split into batches size their output from the first batch's fill
+    ratio; a later batch that outgrows it triggers one regrow from the fill ratio
+    of all rows done so far, keeping the entries stored: the product equals the
+    oracle's, and the regrow branch ran."""
+    monkeypatch.setenv("SIGNFN_STAGING_BYTES", str(1 << 20))
+    monkeypatch.setenv("SIGNFN_PROGRESS", "1")
+    A = _uneven_fill_matrix()
+    _check_product(sf, A, A)
+    err = capfd.readouterr().err
+    assert "regrown from the fill ratio" in err, err[-2000:]
+
 
 NMF_CASES = {
     "lap2d_10": (lambda: W.laplacian_2d(10, jitter=0.05, seed=2, m=8.0), {}),
