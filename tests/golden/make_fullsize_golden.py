@@ -6,7 +6,7 @@ Stored: the oracle's summary (status, iterations, nnz, e of the result,
 tests/golden/probe.py for every row (a whole-matrix checksum), and a set of
 complete rows (columns and values) for entry-wise comparison.
 
-    python tests/golden/make_fullsize_golden.py c2
+    python tests/golden/make_fullsize_golden.py c2 [output directory]
 """
 import hashlib
 import os
@@ -54,8 +54,9 @@ def sample_rows(n: int, N: int):
     return np.array(sorted(i for i in s if 0 <= i < n), dtype=np.int64)
 
 
-def main(cfg: str):
+def main(cfg: str, outdir: str = HERE):
     kw, N = RUNS[cfg]
+    os.environ["ORACLE_PROGRESS"] = "1"   # one line per iteration on stderr
     A = W.config_matrix(cfg)
     t = time.perf_counter()
     r = oracle.nsf(A, **kw)
@@ -74,7 +75,7 @@ def main(cfg: str):
         k = np.searchsorted(r.indices[b:e], i)
         if k < e - b and r.indices[b + k] == i:
             diag += r.data[b + k]
-    out = os.path.join(HERE, f"{cfg}_fp64_oracle.npz")
+    out = os.path.join(outdir, f"{cfg}_fp64_oracle.npz")
     np.savez_compressed(out, fingerprint=fingerprint(A), options=repr(sorted(kw.items())),
                         iters=r.iters, nnz=r.nnz, res_fro=r.res_fro,
                         fro=float(np.sqrt(np.sum(r.data ** 2))), trace=diag,
@@ -84,4 +85,5 @@ def main(cfg: str):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1] if len(sys.argv) > 1 else "c2")
+    main(sys.argv[1] if len(sys.argv) > 1 else "c2",
+         sys.argv[2] if len(sys.argv) > 2 else HERE)

@@ -102,3 +102,14 @@ def test_admission_table_covers_the_oracle_fill():
         per_row = next(p for a, nm, t, p in table
                        if avg <= a and (nm == 0 or n <= nm) and tol >= t)
         assert peak <= per_row <= 1.5 * peak, (fam, n, tol, peak, per_row)
+
+
+def test_stored_c3_oracle_solve():
+    import make_fullsize_golden as mk
+    g = np.load(os.path.join(GOLDEN, "c3_fp64_oracle.npz"))
+    A = W.config_matrix("c3")
+    assert str(g["fingerprint"]) == mk.fingerprint(A)
+    assert int(g["iters"]) >= 5 and float(g["res_fro"]) <= 1e-12
+    # nonsymmetric: no norm identity, but the trace is the inertia of the gap term
+    assert abs(float(g["trace"]) - A.meta["inertia"]) <= 1e-8
+    assert len(g["probe"]) == A.n and len(g["rows"]) >= 64

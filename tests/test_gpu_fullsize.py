@@ -1,16 +1,16 @@
 """Parity at the full workload sizes, in the launch configuration bench.py times.
 
-C2 (256 x 256) is compared with the FP64 oracle's own solve of the same matrix,
-stored by tests/golden/make_fullsize_golden.py (a run of several minutes, too
-long for a test): the whole matrix through per-row hash probes, which estimate
-||X - S||_F, and entry by entry on complete stored rows.  For C3 (512 x 512),
-which the oracle cannot solve in the memory of a test machine, rows are checked
-against the dense sign of the principal patch on a ball of graph radius 34
-around them (the exponential decay of the sign of a gapped matrix makes the
-patch row equal to the row of sign(A) to about q^34), several hundred rows from
-shared patches, plus properties that hold at any size: X^2 = I and XA = AX on
-sampled rows, and trace(X) = (# eigenvalues right) - (# left), which the
-staggered gap term fixes as the sum of (-1)^(x+y(+z)).
+C2 (256 x 256) and C3 (512 x 512) are compared with the FP64 oracle's own solves
+of the same matrices, stored by tests/golden/make_fullsize_golden.py (runs of
+several minutes, too long for a test): the whole matrix through per-row hash
+probes, which estimate ||X - S||_F, and entry by entry on complete stored rows.
+Independently of the oracle, C3 rows are also checked against the dense sign of
+the principal patch on a ball of graph radius 34 around them (the exponential
+decay of the sign of a gapped matrix makes the patch row equal to the row of
+sign(A) to about q^34), several hundred rows from shared patches, plus
+properties that hold at any size: X^2 = I and XA = AX on sampled rows, and
+trace(X) = (# eigenvalues right) - (# left), which the staggered gap term fixes
+as the sum of (-1)^(x+y(+z)).
 """
 import math
 import os
@@ -126,15 +126,26 @@ if GOLDEN not in sys.path:
     sys.path.insert(0, GOLDEN)
 
 
+def _golden(cfg):
+    import make_fullsize_golden as mk
+    g = dict(np.load(os.path.join(GOLDEN, f"{cfg}_fp64_oracle.npz")))
+    A = W.config_matrix(cfg)
+    assert str(g["fingerprint"]) == mk.fingerprint(A), f"{cfg} generator changed since the golden run"
+    return A, g
+
+
 @pytest.fixture(scope="module")
 def c2_golden():
     """The FP64 oracle's solve of the full C2 matrix (tests/golden/
     make_fullsize_golden.py): summary, per-row probes and complete sample rows."""
-    import make_fullsize_golden as mk
-    g = dict(np.load(os.path.join(GOLDEN, "c2_fp64_oracle.npz")))
-    A = W.config_matrix("c2")
-    assert str(g["fingerprint"]) == mk.fingerprint(A), "C2 generator changed since the golden run"
-    return A, g
+    return _golden("c2")
+
+
+@pytest.fixture(scope="module")
+def c3_golden():
+    """The same for C3 (the oracle's full solve, run on a host with the memory it
+    needs)."""
+    return _golden("c3")
 
 
 def _check_against_oracle(res, g, rel_tol):
@@ -219,6 +230,20 @@ def c3_reference_rows():
         ref.update(cf.local_sign_rows_similar(A, y * N + x, 34, 4, d))
     assert len(ref) >= 256
     return A, ref
+
+
+@pytest.mark.parametrize("precision,rel_tol", [(1, 1e-8), (0, 1e-10)])
+def test_c3_full_against_oracle(sf, c3_golden, precision, rel_tol):
+    """C3 (the bench's workload) FP64 and mixed against the FP64 oracle's own full
+    solve: the whole matrix through the row probes and entry by entry on the stored
+    rows; the FP64 result has the oracle's number of entries."""
+    A, g = c3_golden
+    res = sf.sign_ns(sf.DeviceCsr.from_host(A),
+                     sf.default_opts(tol=1e-12, filter_y=1, precision=precision))
+    assert res.status == "OK"
+    _check_against_oracle(res, g, rel_tol)
+    if precision == 0:
+        assert abs(res.stats()["nnz"] - int(g["nnz"])) <= 1e-3 * int(g["nnz"])
 
 
 @pytest.mark.parametrize("precision,rel_tol", [(1, 1e-8), (0, 1e-10)])
