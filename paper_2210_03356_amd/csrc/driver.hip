@@ -19,7 +19,7 @@ Workspace::Workspace(Allocator *a, size_t staging_bytes) : al(a), s(a->stream) {
     for (DevBuf *b : {&lo, &span, &cap, &work, &capoff, &workoff, &tmp, &bins, &counts, &cursor,
                       &stage_col, &stage_val, &rs1, &rs2, &rs3, &rs4, &icnt, &hist, &tau,
                       &bstar, &seg, &red, &flag, &zero_b, &cstat, &mk, &mm, &mc, &cv, &mlen, &cnext, &symcnt, &symoff, &symfill,
-                      &symtcol, &symtval, &rs5, &whole, &sums, &pst, &rb})
+                      &symtcol, &symtval, &rs5, &whole, &sums, &pst, &rb, &plen, &pbeg, &plist})
         b->bind(a);
     // rows per workgroup for wide rows: 1 (off), 2, 4, 8 or 16
     if (const char *ge = std::getenv("SIGNFN_ROW_GROUP")) {
@@ -45,6 +45,17 @@ Workspace::Workspace(Allocator *a, size_t staging_bytes) : al(a), s(a->stream) {
         }
     }
     if (const char *pe = std::getenv("SIGNFN_PROGRESS")) progress = pe[0] == '1';
+    // SIGNFN_PAGES: "off" dense windows for every row group, "auto" (default)
+    // page windows by the per-product rule, "on" page windows for every group
+    if (const char *pg = std::getenv("SIGNFN_PAGES")) {
+        if (std::strcmp(pg, "off") == 0 || std::strcmp(pg, "0") == 0) page_mode = 0;
+        else if (std::strcmp(pg, "on") == 0) page_mode = 2;
+        else page_mode = 1;
+    }
+    if (const char *ps = std::getenv("SIGNFN_PAGE_SHIFT")) {
+        const int v = std::atoi(ps);
+        if (v >= 4 && v <= 8) page_shift = v;
+    }
     // SIGNFN_STAGING_BYTES: staging budget of every product when the call sets none
     if (staging_bytes == 0)
         if (const char *sb = std::getenv("SIGNFN_STAGING_BYTES"))
@@ -237,7 +248,8 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
     // totals of the plan (and B's density) come back in one copy
     int64_t tot[2];
     unsigned long long pst[2] = {0, 0};
-    const bool want_pst = w.auto_group || w.progress;  // (progress: reported with the product)
+    // B's density over its rows' column ranges (progress: reported with the product)
+    const bool want_pst = w.auto_group || w.progress || w.page_mode == 1;
     ScalarGather pg;
     pg.add(w.capoff.as<int64_t>() + n);
     pg.add(w.workoff.as<int64_t>() + n);
@@ -248,22 +260,37 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
         pg.add(w.pst.as<unsigned long long>());
         pg.add(w.pst.as<unsigned long long>() + 1);
     }
+    // B with a few entries per row (e.g. B = A): lane-per-slot accumulation
+    const bool short_b = B.nnz <= 16 * std::max<int64_t>(B.n, 1);
+    // page lists of B's rows, for page windows of row groups: counted and
+    // scanned here, so that their total comes back with the plan's
+    const bool pages_wanted = w.page_mode != 0 && !short_b && n > 0;
+    if (pages_wanted) {
+        w.plen.ensure(sizeof(int32_t) * n);
+        w.pbeg.ensure(sizeof(int64_t) * (n + 1));
+        launch_page_count<V>(B.view(), w.page_shift, w.plen.as<int32_t>(), s);
+        launch_exclusive_scan_i32(w.plen.as<int32_t>(), n, w.pbeg.as<int64_t>(),
+                                  w.tmp.as<int64_t>(), 0, s);
+        pg.add(w.pbeg.as<int64_t>() + n);
+    }
+    int64_t page_total = 0;
     {
         const int64_t *h = w.read_back(pg);
         tot[0] = h[0];
         tot[1] = h[1];
+        int at = 2;
         if (want_pst) {
-            pst[0] = (unsigned long long)h[2];
-            pst[1] = (unsigned long long)h[3];
+            pst[0] = (unsigned long long)h[at++];
+            pst[1] = (unsigned long long)h[at++];
         }
+        if (pages_wanted) page_total = h[at++];
     }
     const int64_t total_cap = tot[0];
     w.products += tot[1];
     ProductEpi epi;
     epi.lower = lower;
     epi.no_store = no_store ? 1 : 0;
-    // B with a few entries per row (e.g. B = A): lane-per-slot accumulation
-    epi.short_b = B.nnz <= 16 * std::max<int64_t>(B.n, 1);
+    epi.short_b = short_b ? 1 : 0;
     if (ff) {
         // the filter's histogram comes out of the product, and entries that no
         // cut can keep are not stored (the candidates number at most total_cap,
@@ -337,14 +364,30 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
     // others (FP32 values, sparse B rows) in groups of 4.  A served batch (row
     // mask set) mixes requests at different steps, whose rows the averages do
     // not describe: it takes no pairs.
+    // Page windows (kernels.hip k_spgemm_rows) pay off when B's rows occupy few
+    // of the 16-column pages of their column ranges: measured per product, 2D
+    // grid products (pages 0.04 - 0.3 of the range) gain up to 1.5x, 3D ones
+    // (0.33 - 0.7) lose 3 - 9% to the marking and the page lookups.
+    const double page_range = std::ldexp((double)page_total, w.page_shift);
+    const bool pages_ok =
+        pages_wanted && (w.page_mode == 2 || (pst[1] > 0 && page_range <= 0.3 * (double)pst[1]));
+    // With page windows the fill of the occupied pages decides instead: groups
+    // of 8 win for FP64 values with long A rows when B's entries fill 60% or
+    // more of its pages (2D grids, ~0.7) and lose 5 - 13% below (3D, ~0.5);
+    // pairs lose to groups of 4 (up to 3x on the stencil products).
     int group = w.row_group;
     if (w.auto_group && pst[1] > 0) {
-        const bool dense_b = 2048ull * pst[0] >= 200ull * pst[1];
         const bool long_a = A.nnz >= 512 * n;
-        if (!w.row_skip && (A.nnz < 64 * n || B.nnz <= 16 * n))
-            group = 2;
-        else
-            group = (sizeof(V) == 8 && long_a && dense_b) ? 8 : 4;
+        if (pages_ok) {
+            const bool full_pages = (double)pst[0] >= 0.6 * page_range;
+            group = (sizeof(V) == 8 && long_a && full_pages) ? 8 : 4;
+        } else {
+            const bool dense_b = 2048ull * pst[0] >= 200ull * pst[1];
+            if (!w.row_skip && (A.nnz < 64 * n || B.nnz <= 16 * n))
+                group = 2;
+            else
+                group = (sizeof(V) == 8 && long_a && dense_b) ? 8 : 4;
+        }
     }
     // The register-accumulator kernel (k_spgemm_regtile) trades the LDS atomic
     // per product for one LDS round trip per gathered B entry and register
@@ -355,6 +398,16 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
         group = w.rt_group;
     }
     if (group > 1) w.mlen.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1));
+    // row groups run their windows over the column pages they occupy
+    if (pages_ok && group > 1 && !use_rt) {
+        w.plist.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(page_total, 1));
+        launch_page_fill<V>(B.view(), w.page_shift, w.pbeg.as<int64_t>(), w.plist.as<int32_t>(),
+                            s);
+        epi.pages.beg = w.pbeg.as<int64_t>();
+        epi.pages.len = w.plen.as<int32_t>();
+        epi.pages.pg = w.plist.as<int32_t>();
+        epi.pages.shift = w.page_shift;
+    }
     const double ms_before = w.spgemm_ms;
 
     int64_t running = 0;
@@ -523,9 +576,11 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
     C.nnz = running;
     if (w.progress && pst[1] > 0)
         w.note("product: %lld rows, %s, groups of %d, B entries per 2048 columns %.0f, "
-               "A %.0f and B %.0f per row, output %lld, %.2f ms", (long long)n,
-               sizeof(V) == 4 ? "FP32" : "FP64", group,
-               2048.0 * (double)pst[0] / (double)pst[1], (double)A.nnz / (double)n,
+               "B pages %.3f of the range (%s), A %.0f and B %.0f per row, output %lld, "
+               "%.2f ms", (long long)n, sizeof(V) == 4 ? "FP32" : "FP64", group,
+               2048.0 * (double)pst[0] / (double)pst[1],
+               std::ldexp((double)page_total, w.page_shift) / (double)pst[1],
+               epi.pages.pg ? "page windows" : "dense windows", (double)A.nnz / (double)n,
                (double)B.nnz / (double)n, (long long)running, w.spgemm_ms - ms_before);
 }
 

@@ -23,6 +23,7 @@ struct Workspace {
     DevBuf symcnt, symoff, symfill, symtcol, symtval;  // mirroring of symmetric products
     DevBuf rs5;                                        // per-row sums not stored by a product
     DevBuf pst;                                        // column-range statistics of a plan
+    DevBuf plen, pbeg, plist;                          // page lists of a product's B rows
     const uint8_t *row_skip = nullptr;  // optional row mask for products (serving)
     int row_group = 8;                  // wide rows computed in groups of 1, 2, 4, 8 or 16
     bool auto_group = true;             // choose 4 or 8 per product from its column ranges
@@ -31,6 +32,10 @@ struct Workspace {
     // windows of 64*rt_nb columns; rt_mode 0 off, 1 by the per-product rule,
     // 2 for every product it supports
     int rt_mode = 0, rt_group = 16, rt_nb = 4;
+    // page windows for row groups (kernels.hpp PageLists): 0 off, 1 for products
+    // whose B rows occupy few of the pages of their column ranges, 2 always;
+    // pages of 2^page_shift columns
+    int page_mode = 1, page_shift = 4;
     bool progress = false;              // one stderr line per finished iteration
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     // accumulated product statistics, in total and per row class (kernel tile)

@@ -50,6 +50,8 @@ __device__ __forceinline__ float rl_val(float v, int l) {
 // tail that does not fill a whole round is split into eight contiguous bands.
 // A bijection of [0, nb) for every nb.
 constexpr int kXcdChunk = 64;
+constexpr int kPageMax = kPageMaxHost;  // LDS page table of the group kernels (int16 ranks)
+constexpr int kPageMinShift = 4;        // pages hold at least 16 columns
 
 __device__ __forceinline__ int xcd_band(int b, int nb) {
     const int per = (nb + 7) >> 3;
@@ -383,6 +385,32 @@ __global__ __launch_bounds__(kSpanThreads) void k_row_density(MatView<V> B,
     }
 }
 
+// Page lists of B's rows, one wave per row: an entry starts a new page when its
+// page differs from the previous entry's (the row is sorted), so the pages come
+// out distinct and ascending.
+template <typename V, bool kFill>
+__global__ void k_row_pages(MatView<V> B, int shift, int32_t *len, const int64_t *beg,
+                            int32_t *pg) {
+    const int64_t k = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
+    if (k >= B.n) return;  // uniform per wave
+    const int lane = lane_id();
+    const int l = B.len[k];
+    const int32_t *col = B.col + B.beg[k];
+    int count = 0;
+    int64_t at = kFill ? beg[k] : 0;
+    for (int t0 = 0; t0 < l; t0 += kWave) {
+        const int t = t0 + lane;
+        const int p = t < l ? col[t] >> shift : INT_MAX;
+        const int prev = t < l && t > 0 ? col[t - 1] >> shift : INT_MIN;
+        const bool start = t < l && p != prev;
+        const uint64_t m = __ballot(start);
+        if (kFill && start) pg[at + lanes_below(m)] = p;
+        at += __popcll(m);
+        count += __popcll(m);
+    }
+    if (!kFill && lane == 0) len[k] = count;
+}
+
 constexpr int kBinThreads = 256;
 
 // Row classes: 0 empty, 1 small window, 2 mid window, 3 wide rows swept in
@@ -617,9 +645,29 @@ __device__ __forceinline__ bool chunk_full(const int (&c)[U], int p, int bl, int
     return p + U * kWave <= bl && last < whi;
 }
 
+// Accumulator slot of a column inside the current window, and back.  Dense
+// windows hold consecutive columns from wlo.  Page windows hold, page after
+// page, the pages of the group's column range that hold entries: tab gives a
+// page's rank among them in column order (pages numbered from plo), the window
+// holds ranks r0 .. r0 + T/2^shift - 1, and wpg lists the window's pages by place.
+struct WinMap {
+    const int16_t *tab;  // nullptr: dense window
+    const int16_t *wpg;
+    int wlo, plo, r0, shift;
+    __device__ __forceinline__ int slot(int col) const {
+        if (!tab) return col - wlo;
+        return (((int)tab[(col >> shift) - plo] - r0) << shift) | (col & ((1 << shift) - 1));
+    }
+    __device__ __forceinline__ int col(int s) const {
+        if (!tab) return wlo + s;
+        return ((plo + (int)wpg[s >> shift]) << shift) | (s & ((1 << shift) - 1));
+    }
+};
+
 // Adds one chunk loaded by gather_chunk at position p of a B row of length bl
 // (columns c, values bv) times the group's coefficients aq into the LDS windows
-// [wlo, whi) of the rows present at the slot (bits of mq; a uniform test).
+// (columns below whi, slots from wm) of the rows present at the slot (bits of
+// mq; a uniform test).
 // Lanes whose entry lies outside the window or past the row end are masked
 // off.  Returns the number of the chunk's entries inside the window (a prefix
 // of the chunk) and, in *next, the column of the first entry after them
@@ -627,8 +675,8 @@ __device__ __forceinline__ bool chunk_full(const int (&c)[U], int p, int bl, int
 template <typename V, int R, int T, int U>
 __device__ __forceinline__ int group_accumulate(double (*acc)[T], const int (&c)[U],
                                                 const V (&bv)[U], const V (&aq)[R], uint32_t mq,
-                                                int p, int bl, int wlo, int whi, int lane,
-                                                int *next) {
+                                                int p, int bl, const WinMap &wm, int whi,
+                                                int lane, int *next) {
     int got = 0, col[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -638,7 +686,7 @@ __device__ __forceinline__ int group_accumulate(double (*acc)[T], const int (&c)
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         if (col[u] < whi) {
-            const int s = col[u] - wlo;
+            const int s = wm.slot(col[u]);
 #pragma unroll
             for (int r = 0; r < R; ++r)
                 if ((mq >> r) & 1u) atomicAdd(&acc[r][s], (double)aq[r] * (double)bv[u]);
@@ -679,7 +727,13 @@ __device__ __forceinline__ int group_accumulate(double (*acc)[T], const int (&c)
 // Finished windows get the D row and the diagonal added in LDS and are written
 // in column order (per-wave ballot compaction, zeros dropped); per-row sums of
 // squares of the product and of the output come out in a fixed order.
-template <typename V, int R, int T, int NT, int U>
+// PG (page windows, with epi.pages): the group first marks in an LDS table the
+// pages (2^shift columns) of its column range that its B rows, D rows and
+// diagonal occupy, ranks them, and runs its windows over the occupied pages
+// only: the output rows of a grid operator fill a small part of their column
+// range, so a few page windows replace many dense ones.  A group whose range
+// fits one dense window, or holds more pages than the table, uses dense windows.
+template <typename V, int R, int T, int NT, int U, bool PG>
 __global__ __launch_bounds__(NT) void k_spgemm_rows(
     const int32_t *__restrict__ rows, const int32_t *__restrict__ mk,
     const uint32_t *__restrict__ mm, const int32_t *__restrict__ mc, const V *__restrict__ cv,
@@ -701,6 +755,10 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
     __shared__ int wrt[R];              // entries written so far, per row
     __shared__ uint32_t hst[kBuckets];  // bucket histogram of the candidates
     __shared__ double wpre[R][NW];      // per-wave sums of squares not stored, per row
+    __shared__ int16_t ptab[PG ? kPageMax : 1];             // page -> rank (-1: empty)
+    __shared__ int16_t wpg[PG ? (T >> kPageMinShift) : 1];  // window place -> page
+    __shared__ int64_t scan_w[NW];
+    __shared__ int wnext;
 
     const int lane = lane_id(), wave = wave_id();
     const int i = rows[xcd_row(blockIdx.x, gridDim.x)];
@@ -719,7 +777,6 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
     if (all_lower) hi = min(hi, i + R);
     const int64_t mbeg = A.beg[i];
     const int ml = R == 1 ? A.len[i] : mlen[i];
-    const bool multi = hi - lo > T;
     const bool has_d = D.len != nullptr;
     // slots per wave and batch: 64, or fewer so that a short slot list still
     // spreads over every wave
@@ -730,10 +787,115 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
     if (epi.hist)
         for (int q = threadIdx.x; q < kBuckets; q += NT) hst[q] = 0u;
     for (int q = threadIdx.x; q < R * NW; q += NT) (&wpre[0][0])[q] = 0.0;
-    for (int wlo = lo; wlo < hi; wlo += T) {
-        const int nsl = min(T, hi - wlo);
-        const int whi = wlo + nsl;
-        const bool first = (wlo == lo);
+
+    int nwin = hi > lo ? (hi - lo + T - 1) / T : 0;
+    bool pm = false;
+    int S = 0, plo = 0, np = 0, npg = 0;  // npg: occupied pages
+    if constexpr (PG) {
+        S = epi.pages.shift;
+        plo = lo >> S;
+        np = hi > lo ? ((hi - 1) >> S) - plo + 1 : 0;
+        // (a range that fits one dense window gains nothing from pages)
+        pm = np > 0 && np <= kPageMax && hi - lo > T;
+    }
+    if (pm) {
+        // mark the occupied pages: those of every slot's B row, of the D rows
+        // and of the diagonal (plain stores of 1: concurrent writers agree)
+        for (int q = threadIdx.x; q < np; q += NT) ptab[q] = 0;
+        __syncthreads();
+        const PageLists &pl = epi.pages;
+        // slots spread over the waves as in the accumulation below
+        for (int t0 = wave * step; t0 < ml; t0 += NW * step) {
+            const int t = t0 + lane;
+            int64_t pb = 0;
+            int pn = 0;
+            if (lane < step && t < ml) {
+                const int k = R == 1 ? A.col[mbeg + t] : mk[mbeg + t];
+                pb = pl.beg[k];
+                pn = pl.len[k];
+            }
+            uint64_t act = __ballot(pn > 0);
+            while (act) {
+                const int q = __builtin_ctzll(act);
+                act &= act - 1;
+                const int64_t b = rl_i64(pb, q);
+                const int l = rl_i32(pn, q);
+                for (int j0 = 0; j0 < l; j0 += U * kWave) {
+                    int pq[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) pq[u] = pl.pg[b + min(j0 + u * kWave + lane, l - 1)];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int rel = pq[u] - plo;
+                        if (rel >= 0 && rel < np) ptab[rel] = 1;
+                    }
+                }
+            }
+        }
+        if (has_d) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int dl = D.len[i + r];
+                const int64_t db = D.beg[i + r];
+                for (int q = threadIdx.x; q < dl; q += NT) {
+                    const int rel = (D.col[db + q] >> S) - plo;
+                    if (rel >= 0 && rel < np) ptab[rel] = 1;
+                }
+            }
+        }
+        if (diag != V(0) && threadIdx.x < R) {
+            const int ir = i + threadIdx.x;
+            if (ir >= lo && ir < hi) ptab[(ir >> S) - plo] = 1;
+        }
+        __syncthreads();
+        // ranks in column order: each thread scans a run of consecutive pages
+        constexpr int PER = (kPageMax + NT - 1) / NT;
+        const int q0 = threadIdx.x * PER;
+        int cnt = 0;
+#pragma unroll
+        for (int e = 0; e < PER; ++e)
+            if (q0 + e < np) cnt += ptab[q0 + e];
+        int64_t total = 0;
+        int run = (int)block_excl_scan<int64_t, NT>(cnt, scan_w, &total);
+#pragma unroll
+        for (int e = 0; e < PER; ++e)
+            if (q0 + e < np) {
+                const int m = ptab[q0 + e];
+                ptab[q0 + e] = (int16_t)(m ? run : -1);
+                run += m;
+            }
+        npg = (int)total;
+        nwin = (npg + (T >> S) - 1) / (T >> S);
+        __syncthreads();
+    }
+    const bool multi = nwin > 1;
+    for (int w = 0; w < nwin; ++w) {
+        int wlo, whi, nsl, r0 = 0;
+        if (pm) {
+            // this window's pages: ranks r0 .. r1 - 1; the next window starts at
+            // the page of rank r1 (or at the end of the range)
+            const int tp = T >> S;
+            r0 = w * tp;
+            const int r1 = min(npg, r0 + tp);
+            if (threadIdx.x == 0) wnext = -1;
+            __syncthreads();
+            for (int q = threadIdx.x; q < np; q += NT) {
+                const int rk = ptab[q];
+                if (rk >= r0 && rk < r1) wpg[rk - r0] = (int16_t)q;
+                else if (rk == r1) wnext = q;
+            }
+            __syncthreads();
+            const int nx = wnext;
+            wlo = (plo + wpg[0]) << S;
+            whi = nx >= 0 ? (plo + nx) << S : hi;
+            nsl = (r1 - r0) << S;
+        } else {
+            wlo = lo + w * T;
+            whi = min(hi, wlo + T);
+            nsl = whi - wlo;
+        }
+        const bool first = (w == 0);
+        const WinMap wm{pm ? ptab : nullptr, wpg, wlo, plo, r0, S};
         for (int s = threadIdx.x; s < nsl; s += NT)
 #pragma unroll
             for (int r = 0; r < R; ++r) acc[r][s] = 0.0;
@@ -783,7 +945,8 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
                         const double bvv = (double)B.val[bb + p];
 #pragma unroll
                         for (int r = 0; r < R; ++r)
-                            if ((msk >> r) & 1) atomicAdd(&acc[r][col - wlo], (double)a[r] * bvv);
+                            if ((msk >> r) & 1)
+                                atomicAdd(&acc[r][wm.slot(col)], (double)a[r] * bvv);
                     }
                     cur = p;
                     nc = nx;
@@ -825,7 +988,7 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
                     if (chunk_full<U>(c, p, blq, whi))
                         gather_chunk<V, U>(B, bbq, p + U * kWave, blq, lane, cr, br);
                     int nxt = INT_MAX;
-                    int got = group_accumulate<V, R, T, U>(acc, c, bv, aq, mq, p, blq, wlo,
+                    int got = group_accumulate<V, R, T, U>(acc, c, bv, aq, mq, p, blq, wm,
                                                            whi, lane, &nxt);
                     p += got;
                     while (got == U * kWave) {  // the refill was issued above
@@ -833,7 +996,7 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
                         for (int u = 0; u < U; ++u) { c[u] = cr[u]; bv[u] = br[u]; }
                         if (chunk_full<U>(c, p, blq, whi))
                             gather_chunk<V, U>(B, bbq, p + U * kWave, blq, lane, cr, br);
-                        got = group_accumulate<V, R, T, U>(acc, c, bv, aq, mq, p, blq, wlo,
+                        got = group_accumulate<V, R, T, U>(acc, c, bv, aq, mq, p, blq, wm,
                                                            whi, lane, &nxt);
                         p += got;
                     }
@@ -858,7 +1021,7 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
                 double x = 0.0;
                 for (int s = threadIdx.x; s < nsl; s += NT) {
                     const double v = acc[r][s];
-                    x += sym_weight(epi.lower.of(i + r), wlo + s, i + r) * v * v;
+                    x += sym_weight(epi.lower.of(i + r), wm.col(s), i + r) * v * v;
                 }
                 x = wave_sum(x);
                 if (lane == 0) wsum[2 * r][wave] += x;
@@ -873,14 +1036,14 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
                 for (int q = threadIdx.x; q < dl; q += NT) {
                     const int c = D.col[db + q];
                     if (c >= wlo && c < whi)
-                        acc[r][c - wlo] += (double)dcoef * (double)D.val[db + q];
+                        acc[r][wm.slot(c)] += (double)dcoef * (double)D.val[db + q];
                 }
             }
             __syncthreads();
         }
         if (diag != V(0) && threadIdx.x < R) {
             const int r = threadIdx.x, ir = i + r;
-            if (ir >= wlo && ir < whi) acc[r][ir - wlo] += (double)diag;
+            if (ir >= wlo && ir < whi) acc[r][wm.slot(ir)] += (double)diag;
         }
         __syncthreads();
 
@@ -889,18 +1052,18 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
             const int rbeg = wave * REG;
             // columns written for this row: all, or up to the diagonal
             const bool low = epi.lower.of(i + r);
-            const int lim = low ? min(nsl, i + r + 1 - wlo) : nsl;
             int cw = 0;
             double pr = 0.0;
             for (int s0 = rbeg; s0 < rbeg + REG && s0 < nsl; s0 += kWave) {
                 const int s = s0 + lane;
-                const V v = s < lim ? (V)acc[r][s] : V(0);
+                const int cs = s < nsl ? wm.col(s) : INT_MAX;
+                const V v = cs != INT_MAX && (!low || cs <= i + r) ? (V)acc[r][s] : V(0);
                 bool keep = v != V(0);
                 if (keep && (epi.hist || epi.keep_from > 0)) {
                     // the filter's histogram counts every candidate; entries in
                     // buckets below keep_from are dropped by any cut it can choose
                     const int bk = bucket_of(as_f64(v));
-                    const double wgt = sym_weight(low, wlo + s, i + r);
+                    const double wgt = sym_weight(low, cs, i + r);
                     if (epi.hist) atomicAdd(&hst[bk], (uint32_t)wgt);
                     if (bk < epi.keep_from) {
                         keep = false;
@@ -917,24 +1080,25 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
             __syncthreads();
             int o = wrt[r], tot = 0;
             double y = 0.0;
-            for (int w = 0; w < NW; ++w) {
-                const int c = wcnt[w];
-                if (w < wave) o += c;
+            for (int wv = 0; wv < NW; ++wv) {
+                const int c = wcnt[wv];
+                if (wv < wave) o += c;
                 tot += c;
             }
             for (int s0 = rbeg; s0 < rbeg + REG && s0 < nsl; s0 += kWave) {
                 const int s = s0 + lane;
-                const V v = s < lim ? (V)acc[r][s] : V(0);
+                const int cs = s < nsl ? wm.col(s) : INT_MAX;
+                const V v = cs != INT_MAX && (!low || cs <= i + r) ? (V)acc[r][s] : V(0);
                 const bool nz = v != V(0) && (epi.keep_from == 0 ||
                                               bucket_of(as_f64(v)) >= epi.keep_from);
                 const uint64_t m = __ballot(nz);
                 if (nz) {
                     if (!epi.no_store) {
                         const int64_t pos = obase + o + lanes_below(m);
-                        out_col[pos] = wlo + s;
+                        out_col[pos] = cs;
                         out_val[pos] = v;
                     }
-                    y += sym_weight(low, wlo + s, i + r) * as_f64(v) * as_f64(v);
+                    y += sym_weight(low, cs, i + r) * as_f64(v) * as_f64(v);
                 }
                 o += __popcll(m);
             }
@@ -1844,6 +2008,23 @@ template void launch_row_density<double>(MatView<double>, unsigned long long *, 
 template void launch_row_density<float>(MatView<float>, unsigned long long *, hipStream_t);
 
 template <typename V>
+void launch_page_count(MatView<V> B, int shift, int32_t *len, hipStream_t s) {
+    if (B.n <= 0) return;
+    k_row_pages<V, false><<<blocks_for(B.n, 4), 256, 0, s>>>(B, shift, len, nullptr, nullptr);
+}
+template <typename V>
+void launch_page_fill(MatView<V> B, int shift, const int64_t *beg, int32_t *pg, hipStream_t s) {
+    if (B.n <= 0) return;
+    k_row_pages<V, true><<<blocks_for(B.n, 4), 256, 0, s>>>(B, shift, nullptr, beg, pg);
+}
+template void launch_page_count<double>(MatView<double>, int, int32_t *, hipStream_t);
+template void launch_page_count<float>(MatView<float>, int, int32_t *, hipStream_t);
+template void launch_page_fill<double>(MatView<double>, int, const int64_t *, int32_t *,
+                                       hipStream_t);
+template void launch_page_fill<float>(MatView<float>, int, const int64_t *, int32_t *,
+                                      hipStream_t);
+
+template <typename V>
 void launch_plan(MatView<V> A, MatView<V> B, MatView<V> D, int diag, int64_t r0, int64_t r1,
                  int32_t *lo, int32_t *span, int64_t *cap, int64_t *work, const uint8_t *skip,
                  hipStream_t s) {
@@ -2010,9 +2191,14 @@ static void group_launch(const int32_t *leads, int ngroups, const int32_t *mk, c
                          ProductEpi epi, hipStream_t s) {
     constexpr int T = R == 2 ? 4096 : 16384 / R;
     constexpr int NT = R == 2 ? 512 : 1024;
-    k_spgemm_rows<V, R, T, NT, kUnroll><<<ngroups, NT, 0, s>>>(
-        leads, mk, mm, mc, cv, mlen, A, B, D, (V)coef, (V)dcoef, (V)diag, lo, span, off, base,
-        out_col, out_val, out_len, cursor, cnext, sq_prod, sq_out, out_count, epi);
+    if (epi.pages.pg)
+        k_spgemm_rows<V, R, T, NT, kUnroll, true><<<ngroups, NT, 0, s>>>(
+            leads, mk, mm, mc, cv, mlen, A, B, D, (V)coef, (V)dcoef, (V)diag, lo, span, off, base,
+            out_col, out_val, out_len, cursor, cnext, sq_prod, sq_out, out_count, epi);
+    else
+        k_spgemm_rows<V, R, T, NT, kUnroll, false><<<ngroups, NT, 0, s>>>(
+            leads, mk, mm, mc, cv, mlen, A, B, D, (V)coef, (V)dcoef, (V)diag, lo, span, off, base,
+            out_col, out_val, out_len, cursor, cnext, sq_prod, sq_out, out_count, epi);
 }
 
 template <typename V>
@@ -2119,13 +2305,13 @@ void launch_spgemm(int cls, const int32_t *rows, int nrows, MatView<V> A, MatVie
         out_col, out_val, out_len, cursor, cnext, sq_prod, sq_out, out_count, epi
     switch (cls) {
         case 1:
-            k_spgemm_rows<V, 1, 512, 64, kUnroll><<<nrows, 64, 0, s>>>(SFN_ROW_ARGS);
+            k_spgemm_rows<V, 1, 512, 64, kUnroll, false><<<nrows, 64, 0, s>>>(SFN_ROW_ARGS);
             break;
         case 2:
-            k_spgemm_rows<V, 1, 4096, 256, kUnroll><<<nrows, 256, 0, s>>>(SFN_ROW_ARGS);
+            k_spgemm_rows<V, 1, 4096, 256, kUnroll, false><<<nrows, 256, 0, s>>>(SFN_ROW_ARGS);
             break;
         default:
-            k_spgemm_rows<V, 1, 8192, 512, kUnroll><<<nrows, 512, 0, s>>>(SFN_ROW_ARGS);
+            k_spgemm_rows<V, 1, 8192, 512, kUnroll, false><<<nrows, 512, 0, s>>>(SFN_ROW_ARGS);
             break;
     }
 #undef SFN_ROW_ARGS

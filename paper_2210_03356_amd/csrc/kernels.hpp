@@ -37,8 +37,20 @@ struct LowerRows {
     bool any() const { return all != 0 || rows != nullptr; }
 };
 
+// Occupied column pages of B's rows: page p holds columns [p << shift, (p+1) << shift);
+// row k occupies the ascending pages pg[beg[k] .. beg[k] + len[k]).  Given to a
+// product, its row groups run their windows over the pages they occupy instead
+// of over every column of their range.
+struct PageLists {
+    const int64_t *beg = nullptr;
+    const int32_t *len = nullptr;
+    const int32_t *pg = nullptr;
+    int shift = 4;
+};
+
 // Output options of the numeric product.
 struct ProductEpi {
+    PageLists pages;           // page-compressed windows for row groups (pg == nullptr: off)
     LowerRows lower;           // rows that store only columns <= the row (symmetric product)
     int keep_from = 0;         // store only entries whose bucket >= keep_from
     uint64_t *hist = nullptr;  // += bucket histogram of all nonzero entries (weighted
@@ -92,6 +104,16 @@ template <typename V>
 void launch_plan(MatView<V> A, MatView<V> B, MatView<V> D, int diag, int64_t r0, int64_t r1,
                  int32_t *lo, int32_t *span, int64_t *cap, int64_t *work, const uint8_t *skip,
                  hipStream_t s);
+// Page lists of B's rows (PageLists): len[k] = number of distinct pages
+// (column >> shift) of row k; then, with beg the exclusive scan of len, the
+// pages themselves in ascending order.
+template <typename V>
+void launch_page_count(MatView<V> B, int shift, int32_t *len, hipStream_t s);
+template <typename V>
+void launch_page_fill(MatView<V> B, int shift, const int64_t *beg, int32_t *pg, hipStream_t s);
+// Largest group column range (pages of 2^shift columns) the LDS page table of
+// the group kernels holds; wider groups use dense windows.
+constexpr int kPageMaxHost = 8192;
 
 // Row classes: 0 empty, 1..3 tiles.  Writes row lists per class (bins[c] holds
 // up to r1-r0 rows), counts into counts[4] (device), and len=0 for empty rows.
