@@ -42,7 +42,8 @@ def kernel_name(st, tile) -> str:
     v = "float" if st["hot_fp32"] else "double"
     if st.get("hot_regtile"):
         return f"k_spgemm_regtile<{v},{st['hot_group']},{tile // 64},{st['hot_threads']}>"
-    return f"k_spgemm_rows<{v},{st['hot_group']},{tile},{st['hot_threads']}>"
+    pages = ",pages" if st.get("hot_pages") else ""
+    return f"k_spgemm_rows<{v},{st['hot_group']},{tile},{st['hot_threads']}{pages}>"
 
 
 def read_traffic(st, config: str, precision: int, grid=None, method="ns"):
@@ -61,6 +62,7 @@ def read_traffic(st, config: str, precision: int, grid=None, method="ns"):
         return None
     key = ((f"regtile{st['hot_group']}x{st['hot_tile'] // 64}_" if st.get("hot_regtile") else
             f"group{st['hot_group']}_" if st["hot_group"] > 1 else "") +
+           ("pages_" if st.get("hot_pages") else "") +
            ("f32_" if st["hot_fp32"] else "f64_") +
            f"tile{st['hot_tile']}_hbm_bytes_per_launch")
     return float(vals[key]) if key in vals else None
@@ -447,7 +449,7 @@ def main():
         del r
     torch.cuda.synchronize()
     agg = dict(hot_ms=0.0, hot_bytes=0.0, hot_launches=0, hot_products=0, hot_gathered=0,
-               spgemm_ms=0.0, spgemm_bytes=0.0, products=0)
+               hot_madds=0, spgemm_ms=0.0, spgemm_bytes=0.0, products=0, madds=0)
     res = None
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -499,10 +501,11 @@ def main():
                            full_c2=not args.no_cpu_full_c2)
 
     traffic = read_traffic(st, args.config, args.precision, args.grid, args.method)
-    # second ceiling of the hot kernel: its multiply-adds against the measured LDS
-    # atomic-add rate (one LDS atomic add per multiply-add), or for the
+    # second ceiling of the hot kernel: the multiply-adds it performed (counted by
+    # the kernel: a symmetric product stops each row at the diagonal) against the
+    # measured LDS atomic-add rate (one LDS atomic add per multiply-add), or for the
     # register-accumulator kernel against the FP64 vector FMA peak
-    hot_rate = agg["hot_products"] / (agg["hot_ms"] * 1e-3) if agg["hot_ms"] else 0.0
+    hot_rate = agg["hot_madds"] / (agg["hot_ms"] * 1e-3) if agg["hot_ms"] else 0.0
     if st.get("hot_regtile"):
         second = {"kind": "valu_fma_f64", "achieved": round(hot_rate, 1),
                   "peak": 78.6e12 / 2, "unit": "multiply-adds/s",
@@ -548,6 +551,9 @@ def main():
         "nnz_result": st["nnz"],
         "products": int(agg["products"] / max(args.steps, 1)),
         "products_per_s": round(agg["products"] / (agg["spgemm_ms"] * 1e-3), 1)
+        if agg["spgemm_ms"] > 0 else None,
+        "madds": int(agg["madds"] / max(args.steps, 1)),
+        "madds_per_s": round(agg["madds"] / (agg["spgemm_ms"] * 1e-3), 1)
         if agg["spgemm_ms"] > 0 else None,
         "spgemm_ms_per_step": round(agg["spgemm_ms"] / max(args.steps, 1), 2),
         "spgemm_gbs": round(agg["spgemm_bytes"] / (agg["spgemm_ms"] * 1e-3) / 1e9, 1)

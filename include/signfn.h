@@ -134,6 +134,13 @@ typedef struct {
                             merged list of a row group) */
     int hot_regtile;     /* 1 if it is the register-accumulator kernel (windows of hot_tile
                             columns, hot_group rows per workgroup) */
+    int64_t madds;       /* multiply-adds the product kernels performed: a symmetric product
+                            formed from its lower triangle stops each row at the diagonal, so
+                            this is below `products` (which counts every entry of every
+                            gathered B row) */
+    int64_t hot_madds;   /* the hot kernel's share of madds */
+    int hot_pages;       /* 1 if the hot kernel ran page windows (row groups sweeping only the
+                            16-column pages their rows occupy) in most of its launches */
 } sign_stats;
 
 /* One entry per computed residual, k = 0 .. iters. */

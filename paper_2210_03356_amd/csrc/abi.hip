@@ -344,6 +344,7 @@ int sign_ns(const sign_csr *A, const sign_opts *o, void *hip_stream, sign_result
         st.step_fro = lo.d;
         st.nnz = r->nnz;
         st.products = w.products;
+        st.madds = w.madds;
         st.spgemm_ms = w.spgemm_ms;
         st.spgemm_bytes = w.spgemm_bytes;
         st.comm_rel = comm_rel;
@@ -385,6 +386,7 @@ int sign_newton(const sign_csr *A, const sign_opts *o, void *hip_stream, sign_re
         st.step_fro = lo.d;
         st.nnz = r->nnz;
         st.products = w.products;
+        st.madds = w.madds;
         st.spgemm_ms = w.spgemm_ms;
         st.spgemm_bytes = w.spgemm_bytes;
         st.inner_steps = inner;
@@ -426,6 +428,7 @@ int sign_spgemm(const sign_csr *A, const sign_csr *B, void *hip_stream, sign_res
         }
         r->stats.nnz = r->nnz;
         r->stats.products = w.products;
+        r->stats.madds = w.madds;
         r->stats.spgemm_ms = w.spgemm_ms;
         r->stats.spgemm_bytes = w.spgemm_bytes;
         w.hot_stats(r->stats);

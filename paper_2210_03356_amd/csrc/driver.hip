@@ -116,6 +116,8 @@ void Workspace::hot_stats(sign_stats &st) const {
     st.hot_bytes = c.bytes;
     st.hot_products = c.products;
     st.hot_gathered = c.gathered;
+    st.hot_madds = c.madds;
+    st.hot_pages = 2 * c.page_launches > c.launches ? 1 : 0;
 }
 
 int64_t *Workspace::pinned() {
@@ -454,7 +456,7 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
                                   cv_a, w.mlen.as<int32_t>(), w.cstat.as<int64_t>() + 4 * 8 + 5,
                                   s);
             SFN_HIP(hipEventRecord(w.ev[1], s));
-            if (use_rt)
+            if (use_rt) {
                 launch_spgemm_regtile<V>(group, w.rt_nb, leads, cnt[4], mk_a, mm_a, mc_a, cv_a,
                                          w.mlen.as<int32_t>(), A.view(), B.view(), Dv, coef,
                                          dcoef, diag, w.lo.as<int32_t>(), w.span.as<int32_t>(),
@@ -464,20 +466,23 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
                                          sq_prod ? sq_prod->as<double>() : nullptr,
                                          sq_out ? sq_out->as<double>() : nullptr,
                                          w.cstat.as<int64_t>() + 4 * 8 + 4, epi, s);
-            else
-            launch_spgemm_group<V>(group, leads, cnt[4], mk_a, mm_a, mc_a, cv_a,
-                                   w.mlen.as<int32_t>(), A.view(), B.view(), Dv, coef, dcoef,
-                                   diag, w.lo.as<int32_t>(), w.span.as<int32_t>(), base,
-                                   w.capoff.as<int64_t>(), w.stage_col.as<int32_t>(),
-                                   w.stage_val.as<V>(), C.lenp(), cursor_a, cnext_a,
-                                   sq_prod ? sq_prod->as<double>() : nullptr,
-                                   sq_out ? sq_out->as<double>() : nullptr,
-                                   w.cstat.as<int64_t>() + 4 * 8 + 4, epi, s);
+            } else {
+                epi.madds = (unsigned long long *)(w.cstat.as<int64_t>() + 4 * 8 + 6);
+                launch_spgemm_group<V>(group, leads, cnt[4], mk_a, mm_a, mc_a, cv_a,
+                                       w.mlen.as<int32_t>(), A.view(), B.view(), Dv, coef, dcoef,
+                                       diag, w.lo.as<int32_t>(), w.span.as<int32_t>(), base,
+                                       w.capoff.as<int64_t>(), w.stage_col.as<int32_t>(),
+                                       w.stage_val.as<V>(), C.lenp(), cursor_a, cnext_a,
+                                       sq_prod ? sq_prod->as<double>() : nullptr,
+                                       sq_out ? sq_out->as<double>() : nullptr,
+                                       w.cstat.as<int64_t>() + 4 * 8 + 4, epi, s);
+            }
         } else {
             SFN_HIP(hipEventRecord(w.ev[1], s));
         }
         SFN_HIP(hipEventRecord(w.ev[2], s));
         for (int cls = 3; cls >= 1; --cls) {
+            epi.madds = (unsigned long long *)(w.cstat.as<int64_t>() + cls * 8 + 6);
             launch_spgemm<V>(cls, w.bins.as<int32_t>() + (int64_t)cls * n, cnt[cls], A.view(),
                              B.view(), Dv, coef, dcoef, diag, w.lo.as<int32_t>(),
                              w.span.as<int32_t>(), base, w.capoff.as<int64_t>(),
@@ -530,6 +535,11 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
             c.launches += 1;
             c.rows += cls == 4 ? (int64_t)group * cnt[cls] : cnt[cls];
             c.products += q[1];
+            // the register-accumulator kernel does not count: its plan's products
+            const int64_t md = cls == 4 && use_rt ? q[1] : q[6];
+            c.madds += md;
+            w.madds += md;
+            if (cls == 4 && epi.pages.pg) c.page_launches += 1;
             c.a_nnz += q[2];
             c.d_nnz += q[3];
             c.out += q[4];

@@ -42,6 +42,9 @@ struct Workspace {
     struct ClassStat {
         int64_t launches = 0, rows = 0, products = 0, a_nnz = 0, d_nnz = 0, out = 0;
         int64_t gathered = 0;  // B entries loaded (once per slot of a row group)
+        int64_t madds = 0;     // multiply-adds performed (fewer than products when rows stop
+                               // at the diagonal)
+        int64_t page_launches = 0;  // launches with page windows
         double ms = 0.0, bytes = 0.0;
     };
     ClassStat cls[2][kClasses];  // [FP64, FP32][row class 1..3]
@@ -50,6 +53,7 @@ struct Workspace {
     int rt_used_group = 0, rt_used_nb = 0;  // configuration of the last such launch
     double merge_ms = 0.0;
     int64_t products = 0;
+    int64_t madds = 0;  // multiply-adds the product kernels performed
     double spgemm_ms = 0.0;
     double spgemm_bytes = 0.0;
     // fill the hot-kernel fields (class with the most device time) of s

@@ -759,6 +759,7 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
     __shared__ int16_t wpg[PG ? (T >> kPageMinShift) : 1];  // window place -> page
     __shared__ int64_t scan_w[NW];
     __shared__ int wnext;
+    __shared__ unsigned long long madd_sh;
 
     const int lane = lane_id(), wave = wave_id();
     const int i = rows[xcd_row(blockIdx.x, gridDim.x)];
@@ -784,6 +785,8 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
 
     for (int q = threadIdx.x; q < 2 * R * NW; q += NT) (&wsum[0][0])[q] = 0.0;
     if (threadIdx.x < R) wrt[threadIdx.x] = 0;
+    if (threadIdx.x == 0) madd_sh = 0ull;
+    unsigned long long madd = 0;  // multiply-adds of this wave (uniform), or lane (short B)
     if (epi.hist)
         for (int q = threadIdx.x; q < kBuckets; q += NT) hst[q] = 0u;
     for (int q = threadIdx.x; q < R * NW; q += NT) (&wpre[0][0])[q] = 0.0;
@@ -948,6 +951,7 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
                             if ((msk >> r) & 1)
                                 atomicAdd(&acc[r][wm.slot(col)], (double)a[r] * bvv);
                     }
+                    madd += (unsigned long long)(p - cur) * (unsigned)__popc((unsigned)msk);
                     cur = p;
                     nc = nx;
                 }
@@ -990,6 +994,7 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
                     int nxt = INT_MAX;
                     int got = group_accumulate<V, R, T, U>(acc, c, bv, aq, mq, p, blq, wm,
                                                            whi, lane, &nxt);
+                    const int pstart = p;
                     p += got;
                     while (got == U * kWave) {  // the refill was issued above
 #pragma unroll
@@ -1000,6 +1005,7 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
                                                            whi, lane, &nxt);
                         p += got;
                     }
+                    madd += (unsigned long long)(p - pstart) * (unsigned)__popc(mq);
                     // column of the first entry beyond the window, for the next one
                     if (multi && lane == q) nc = nxt;
                     if (multi && lane == q) cur = p;
@@ -1108,7 +1114,13 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
             if (threadIdx.x == 0) wrt[r] += tot;
         }
     }
+    if (epi.madds) {
+        // short B rows: per lane; otherwise the same count in every lane of a wave
+        if (epi.short_b) madd = wave_sum(madd);
+        if (lane == 0 && madd) atomicAdd(&madd_sh, madd);
+    }
     __syncthreads();
+    if (epi.madds && threadIdx.x == 0 && madd_sh) atomicAdd(epi.madds, madd_sh);
     if (epi.hist)
         for (int q = threadIdx.x; q < kBuckets; q += NT)
             if (hst[q]) atomicAdd((unsigned long long *)&epi.hist[q], (unsigned long long)hst[q]);

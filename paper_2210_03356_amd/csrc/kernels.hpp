@@ -59,6 +59,8 @@ struct ProductEpi {
                                //    because of keep_from (weighted likewise)
     int short_b = 0;           // B's rows are short: each lane walks its own slot's row
     int no_store = 0;          // form row lengths and sums of squares only, store nothing
+    unsigned long long *madds = nullptr;  // += multiply-adds performed (products of an A
+                                          //    and a B entry added into a window)
 };
 
 struct BinCfg {

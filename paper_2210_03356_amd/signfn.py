@@ -54,7 +54,8 @@ class sign_stats(C.Structure):
                 ("hot_launches", C.c_int64),
                 ("hot_ms", C.c_double),
                 ("hot_bytes", C.c_double), ("hot_products", C.c_int64),
-                ("hot_gathered", C.c_int64), ("hot_regtile", C.c_int)]
+                ("hot_gathered", C.c_int64), ("hot_regtile", C.c_int),
+                ("madds", C.c_int64), ("hot_madds", C.c_int64), ("hot_pages", C.c_int)]
 
 
 class sign_iter_stats(C.Structure):

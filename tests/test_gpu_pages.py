@@ -51,8 +51,9 @@ def test_page_window_products(sf, monkeypatch, capfd, group, shift):
     _pages_env(monkeypatch, group, shift)
     A = _wide_rows_matrix()
     R = W.random_sparse(A.n, mean_row=6, seed=9, powerlaw=False)
-    _check_product(sf, A, A)
-    _check_product(sf, R, A)
+    for left in (A, R):
+        st = _check_product(sf, left, A).stats()
+        assert st["madds"] == st["products"]
     err = capfd.readouterr().err
     assert "(page windows)" in err, err[-2000:]
 

@@ -473,9 +473,11 @@ def test_row_groups_match_oracle(sf, monkeypatch, group):
     # slots per row, spread over the waves one or a few each
     for left, right in ((A, A), (A, R), (R, A)):
         r = _check_product(sf, left, right)
-        if left is A:
-            st = r.stats()
-            assert st["products"] > 0
+        st = r.stats()
+        assert st["products"] > 0
+        # the kernels' own count of performed multiply-adds: every product the
+        # plan counts, once
+        assert st["madds"] == st["products"]
 
 
 @pytest.fixture(scope="module")
@@ -505,10 +507,16 @@ def test_symmetric_products_match_general(sf, monkeypatch, name):
     make, kw = CASES[name]
     A = make()
     monkeypatch.setenv("SIGNFN_SYMMETRIC", "1")
-    Xs = sf.sign_ns(_dev(sf, A), sf.default_opts(**kw)).to_scipy()
+    rs = sf.sign_ns(_dev(sf, A), sf.default_opts(**kw))
+    Xs = rs.to_scipy()
     assert (Xs - Xs.T).nnz == 0                      # exactly symmetric
     monkeypatch.setenv("SIGNFN_SYMMETRIC", "0")
-    Xg = sf.sign_ns(_dev(sf, A), sf.default_opts(**kw)).to_scipy()
+    rg = sf.sign_ns(_dev(sf, A), sf.default_opts(**kw))
+    Xg = rg.to_scipy()
+    # rows of a lower-triangle product stop at the diagonal: fewer multiply-adds
+    # performed than the plan counts; the general products perform them all
+    assert rs.stats()["madds"] < rs.stats()["products"]
+    assert rg.stats()["madds"] == rg.stats()["products"]
     S = oracle.nsf(A, **kw).to_scipy()
     assert sp.linalg.norm(Xs - Xg) <= 1e-10 * sp.linalg.norm(S)
     assert sp.linalg.norm(Xs - S) <= 1e-10 * sp.linalg.norm(S)
