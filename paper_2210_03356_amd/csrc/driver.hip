@@ -352,7 +352,12 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
     }
     w.bins.ensure(sizeof(int32_t) * kClasses * (size_t)std::max<int64_t>(n, 1));
     w.counts.ensure(sizeof(int32_t) * kClasses);
-    w.cstat.ensure(sizeof(int64_t) * 8 * kClasses);
+    // class statistics, then the spread per-workgroup counters (kernels.hpp)
+    w.cstat.ensure(sizeof(int64_t) * (8 * kClasses + kSpreadWords));
+    int64_t *const spread = w.cstat.as<int64_t>() + 8 * kClasses;
+    // spread counter j of class c: 0 entries written, 1 B entries of merged
+    // lists, 2 multiply-adds
+    auto counter = [&](int c, int j) { return spread + (c * kSpreadCounters + j) * kSpread * kSpreadStride; };
     // row groups need A compact (rows i .. i+g-1 adjacent in storage) -- every
     // matrix built here is; the merged lists reuse A's index range
     // Groups of 8 rows (2048-column windows) halve the B traffic of groups of 4
@@ -440,7 +445,8 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
         int32_t *mc_a = group > 1 ? w.mc.as<int32_t>() - abase : nullptr;
         V *cv_a = group > 1 ? w.cv.as<V>() - abase : nullptr;
         SFN_HIP(hipMemsetAsync(w.counts.get(), 0, sizeof(int32_t) * kClasses, s));
-        SFN_HIP(hipMemsetAsync(w.cstat.get(), 0, sizeof(int64_t) * 8 * kClasses, s));
+        SFN_HIP(hipMemsetAsync(w.cstat.get(), 0, sizeof(int64_t) * (8 * kClasses + kSpreadWords),
+                               s));
         launch_bin_rows(w.span.as<int32_t>(), w.work.as<int64_t>(), r0, r1, kSmallTile, kMidTile,
                         group, w.bins.as<int32_t>(), n, w.counts.as<int32_t>(),
                         C.lenp(), sq_prod ? sq_prod->as<double>() : nullptr,
@@ -453,8 +459,7 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
         if (cnt[4] > 0) {
             const int32_t *leads = w.bins.as<int32_t>() + (int64_t)4 * n;
             launch_merge_group<V>(group, leads, cnt[4], A.view(), B.view(), mk_a, mm_a, mc_a,
-                                  cv_a, w.mlen.as<int32_t>(), w.cstat.as<int64_t>() + 4 * 8 + 5,
-                                  s);
+                                  cv_a, w.mlen.as<int32_t>(), counter(4, 1), s);
             SFN_HIP(hipEventRecord(w.ev[1], s));
             if (use_rt) {
                 launch_spgemm_regtile<V>(group, w.rt_nb, leads, cnt[4], mk_a, mm_a, mc_a, cv_a,
@@ -465,9 +470,9 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
                                          C.lenp(), cursor_a, cnext_a,
                                          sq_prod ? sq_prod->as<double>() : nullptr,
                                          sq_out ? sq_out->as<double>() : nullptr,
-                                         w.cstat.as<int64_t>() + 4 * 8 + 4, epi, s);
+                                         counter(4, 0), epi, s);
             } else {
-                epi.madds = (unsigned long long *)(w.cstat.as<int64_t>() + 4 * 8 + 6);
+                epi.madds = (unsigned long long *)counter(4, 2);
                 launch_spgemm_group<V>(group, leads, cnt[4], mk_a, mm_a, mc_a, cv_a,
                                        w.mlen.as<int32_t>(), A.view(), B.view(), Dv, coef, dcoef,
                                        diag, w.lo.as<int32_t>(), w.span.as<int32_t>(), base,
@@ -475,14 +480,14 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
                                        w.stage_val.as<V>(), C.lenp(), cursor_a, cnext_a,
                                        sq_prod ? sq_prod->as<double>() : nullptr,
                                        sq_out ? sq_out->as<double>() : nullptr,
-                                       w.cstat.as<int64_t>() + 4 * 8 + 4, epi, s);
+                                       counter(4, 0), epi, s);
             }
         } else {
             SFN_HIP(hipEventRecord(w.ev[1], s));
         }
         SFN_HIP(hipEventRecord(w.ev[2], s));
         for (int cls = 3; cls >= 1; --cls) {
-            epi.madds = (unsigned long long *)(w.cstat.as<int64_t>() + cls * 8 + 6);
+            epi.madds = (unsigned long long *)counter(cls, 2);
             launch_spgemm<V>(cls, w.bins.as<int32_t>() + (int64_t)cls * n, cnt[cls], A.view(),
                              B.view(), Dv, coef, dcoef, diag, w.lo.as<int32_t>(),
                              w.span.as<int32_t>(), base, w.capoff.as<int64_t>(),
@@ -490,7 +495,7 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
                              cursor_a, cnext_a,
                              sq_prod ? sq_prod->as<double>() : nullptr,
                              sq_out ? sq_out->as<double>() : nullptr,
-                             w.cstat.as<int64_t>() + cls * 8 + 4, epi, s);
+                             counter(cls, 0), epi, s);
             SFN_HIP(hipEventRecord(w.ev[6 - cls], s));
         }
         // compact row starts of this batch, continuing from the previous batches
@@ -502,6 +507,8 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
         {
             ScalarGather eg;
             eg.add(C.begp() + r1);
+            eg.fold = spread;
+            eg.fold_dst = w.cstat.as<int64_t>();
             launch_gather_scalars(eg, w.cstat.as<int64_t>(), s);
             SFN_HIP(hipMemcpyAsync(cs, w.cstat.get(), sizeof(int64_t) * 8 * kClasses,
                                    hipMemcpyDeviceToHost, s));

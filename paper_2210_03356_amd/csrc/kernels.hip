@@ -614,7 +614,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_group(
     }
     if (threadIdx.x == 0) mlen[i] = (int32_t)nslot;
     g = wave_sum(g);
-    if (gathered && lane == 0 && g) atomicAdd(gathered, g);
+    if (gathered && lane == 0 && g) atomicAdd(gathered + (blockIdx.x % kSpread) * kSpreadStride, g);
 }
 
 
@@ -1120,7 +1120,8 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
         if (lane == 0 && madd) atomicAdd(&madd_sh, madd);
     }
     __syncthreads();
-    if (epi.madds && threadIdx.x == 0 && madd_sh) atomicAdd(epi.madds, madd_sh);
+    if (epi.madds && threadIdx.x == 0 && madd_sh)
+        atomicAdd(epi.madds + (blockIdx.x % kSpread) * kSpreadStride, madd_sh);
     if (epi.hist)
         for (int q = threadIdx.x; q < kBuckets; q += NT)
             if (hst[q]) atomicAdd((unsigned long long *)&epi.hist[q], (unsigned long long)hst[q]);
@@ -1139,7 +1140,9 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
             if (sq_out) sq_out[i + r] = y;
             tw += (unsigned long long)wrt[r];
         }
-        if (out_count) atomicAdd((unsigned long long *)out_count, tw);
+        if (out_count)
+            atomicAdd((unsigned long long *)(out_count + (blockIdx.x % kSpread) * kSpreadStride),
+                      tw);
     }
 }
 
@@ -1482,7 +1485,8 @@ __global__ __launch_bounds__(NT) void k_spgemm_regtile(
         }
         tw += (unsigned long long)wrt[u];
     }
-    if (out_count && lane == 0 && tw) atomicAdd((unsigned long long *)out_count, tw);
+    if (out_count && lane == 0 && tw)
+        atomicAdd((unsigned long long *)(out_count + (blockIdx.x % kSpread) * kSpreadStride), tw);
 }
 
 // ---------------------------------------------------------------------------
@@ -2090,7 +2094,15 @@ void launch_move_rows(const SegMove *t, int nseg, int64_t max_rows, const int64_
 // (read back with a single copy); the bucket total of a histogram is summed by
 // one workgroup.
 __global__ void k_gather_scalars(ScalarGather g, int64_t *dst) {
-    for (int j = 0; j < g.n; ++j) dst[j] = *g.src[j];
+    const int t = threadIdx.x;
+    if (t == 0)
+        for (int j = 0; j < g.n; ++j) dst[j] = *g.src[j];
+    if (g.fold && t < kClasses * kSpreadCounters) {
+        const int64_t *p = g.fold + (int64_t)t * kSpread * kSpreadStride;
+        int64_t a = 0;
+        for (int q = 0; q < kSpread; ++q) a += p[q * kSpreadStride];
+        g.fold_dst[(t / kSpreadCounters) * 8 + 4 + t % kSpreadCounters] = a;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_hist_total(const uint64_t *hist, int64_t *dst) {
@@ -2114,7 +2126,7 @@ __global__ void k_set_filter_args(int64_t *seg, int64_t n, double *tau_dev, doub
 }
 
 void launch_gather_scalars(const ScalarGather &g, int64_t *dst, hipStream_t s) {
-    if (g.n > 0) k_gather_scalars<<<1, 1, 0, s>>>(g, dst);
+    if (g.n > 0 || g.fold) k_gather_scalars<<<1, kWave, 0, s>>>(g, dst);
 }
 
 void launch_hist_total(const uint64_t *hist, int64_t *dst, hipStream_t s) {

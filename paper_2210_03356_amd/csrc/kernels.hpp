@@ -225,11 +225,24 @@ void launch_scatter_keep(MatView<V> X, const int32_t *row_seg, const int *bstar,
                          const int64_t *dst_ptr, int32_t *dcol, Vo *dval, hipStream_t s);
 
 // ---- read-back helpers -----------------------------------------------------------
+// Per-workgroup counters of the product kernels (entries written, multiply-adds,
+// B entries of merged lists) are added at counter + (block % kSpread) *
+// kSpreadStride: spread over 32 cache lines, which thousands of one-wave
+// workgroups would otherwise contend on.  Counter j of row class c lives at
+// spread + (c * kSpreadCounters + j) * kSpread * kSpreadStride.
+constexpr int kSpread = 32;
+constexpr int kSpreadStride = 8;  // int64 words: 64 bytes apart
+constexpr int kSpreadCounters = 3;
+constexpr int64_t kSpreadWords = (int64_t)kClasses * kSpreadCounters * kSpread * kSpreadStride;
 // dst[j] = *src[j] for j < n (int64 words), so scattered scalars come back to
-// the host in one copy
+// the host in one copy; with fold set, also fold_dst[8c + 4 + j] (j = 0, 1, 2:
+// slots 4, 5, 6 of class c) = the sum of spread counter j of class c (order
+// of the counters: entries written, B entries of merged lists, multiply-adds).
 struct ScalarGather {
     const int64_t *src[8] = {};
     int n = 0;
+    const int64_t *fold = nullptr;
+    int64_t *fold_dst = nullptr;
     void add(const void *p) { src[n++] = static_cast<const int64_t *>(p); }
 };
 void launch_gather_scalars(const ScalarGather &g, int64_t *dst, hipStream_t s);
