@@ -521,8 +521,14 @@ def main():
                       "source": (f"lds_atomic_rate measured in this run: "
                                  f"{probe['lds_add_f64_per_cu_clk']:.2f} ds_add_f64 lane-ops "
                                  f"per CU per clock at {probe['clock_mhz']:.0f} MHz x "
-                                 f"{probe['cus']} CUs (FP32: "
+                                 f"{probe['cus']} CUs, consecutive addresses (FP32: "
                                  f"{probe['lds_add_f32_per_cu_clk']:.2f})")}
+            if "lds_add_f64_scatter_per_s" in probe:
+                # the same adds at pseudo-random addresses of the window: a product's
+                # scattered adds lie between the two patterns
+                sc = probe["lds_add_f64_scatter_per_s"]
+                second["scatter_peak"] = sc
+                second["frac_scatter"] = round(hot_rate / sc, 4)
     line = {
         "metric": METRIC,
         "value": round(ms_per_step / 1e3, 4),
