@@ -222,8 +222,9 @@ def cpu_baseline(cfg, products_full, solve, full_c2=True):
 
 def serve_bench(args):
     """Served stream: Poisson arrivals of 1D/2D/conv-diff requests (n log-uniform in
-    [1024, 65536], tol in {1e-6, 1e-10}) through the continuous-batching server, next to
-    the same requests solved one after another with sign_ns on the same GPU."""
+    [1024, n_max], n_max = 65536 unless --serve-nmax sets it, tol in {1e-6, 1e-10})
+    through the continuous-batching server, next to the same requests solved one after
+    another with sign_ns on the same GPU."""
     import numpy as np
     import torch
     import paper_2210_03356_amd as sf
@@ -231,7 +232,8 @@ def serve_bench(args):
 
     torch.cuda.set_device(0)
     sf.load()
-    reqs = W.served_stream(count=args.serve_count, rate=args.serve_rate, seed=5)
+    reqs = W.served_stream(count=args.serve_count, rate=args.serve_rate, seed=5,
+                           n_max=args.serve_nmax)
     mats = [W.request_matrix(r) for r in reqs]
     print(f"# served stream: {len(reqs)} requests over {reqs[-1]['arrival']:.2f} s of arrivals",
           file=sys.stderr, flush=True)
@@ -282,7 +284,8 @@ def serve_bench(args):
         "sequential_sign_ns_solves_per_s": round(len(reqs) / seq, 3),
         "offered_load_vs_sequential": round(args.serve_rate * seq / len(reqs), 2),
         "config": {"workload": "c5: Poisson stream, 1D (sigma=2, m=4) / 2D (sigma=4, m=8) / "
-                               "conv-diff (m=8), jitter U[-.05,.05] seed 5000+id, seed 5",
+                               "conv-diff (m=8), jitter U[-.05,.05] seed 5000+id, seed 5, "
+                               f"n log-uniform in [1024, {args.serve_nmax}]",
                    "max_slots": args.serve_slots},
     }
     print(json.dumps(line), flush=True)
@@ -397,6 +400,8 @@ def main():
     ap.add_argument("--serve-count", type=int, default=300)
     ap.add_argument("--serve-rate", type=float, default=50.0)
     ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-nmax", type=int, default=65536,
+                    help="largest request size of the served stream")
     ap.add_argument("--ode", action="store_true", help="Section 4.2 matrix benchmark instead")
     ap.add_argument("--gapless", action="store_true",
                     help="gapless stress row: the literal (m = 0) matrix, nnz growth per iteration")
