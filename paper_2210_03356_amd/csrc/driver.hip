@@ -265,8 +265,9 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
     // B with a few entries per row (e.g. B = A): lane-per-slot accumulation
     const bool short_b = B.nnz <= 16 * std::max<int64_t>(B.n, 1);
     // page lists of B's rows, for page windows of row groups: counted and
-    // scanned here, so that their total comes back with the plan's
-    const bool pages_wanted = w.page_mode != 0 && !short_b && n > 0;
+    // scanned here, so that their total comes back with the plan's (not for
+    // n <= 2048, where column ranges are too short for pages to gain anything)
+    const bool pages_wanted = w.page_mode != 0 && !short_b && n > 2048;
     if (pages_wanted) {
         w.plen.ensure(sizeof(int32_t) * n);
         w.pbeg.ensure(sizeof(int64_t) * (n + 1));
