@@ -683,13 +683,22 @@ __device__ __forceinline__ int group_accumulate(double (*acc)[T], const int (&c)
         col[u] = p + u * kWave + lane < bl ? c[u] : INT_MAX;
         got += __popcll(__ballot(col[u] < whi));
     }
+    // a slot present in every row of the group (most of them) adds without
+    // testing the row bits
+    const bool full = mq == (R >= 32 ? ~0u : (1u << R) - 1u);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         if (col[u] < whi) {
             const int s = wm.slot(col[u]);
+            if (full) {
 #pragma unroll
-            for (int r = 0; r < R; ++r)
-                if ((mq >> r) & 1u) atomicAdd(&acc[r][s], (double)aq[r] * (double)bv[u]);
+                for (int r = 0; r < R; ++r)
+                    atomicAdd(&acc[r][s], (double)aq[r] * (double)bv[u]);
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    if ((mq >> r) & 1u) atomicAdd(&acc[r][s], (double)aq[r] * (double)bv[u]);
+            }
         }
     }
     if (got < U * kWave) {
