@@ -7,10 +7,12 @@
 // here); k_spgemm_regtile is a register-accumulator variant.  Rows whose column
 // range exceeds the tile are swept in several windows; B's rows are sorted,
 // so each (row of A entry, window) pair resumes from a per-entry cursor and
-// every B entry is read once per output row.  The finished window is scanned
-// in column order and its nonzeros written out, so results come out sorted
-// and without stored zeros.  The path is gather- and bandwidth-bound (no
-// dense contraction), so MFMA is not used.
+// every B entry is read once per output row.  Groups of rows whose outputs fill
+// a small part of their column range can instead run their windows over the
+// 16-column pages they occupy (page windows, k_spgemm_rows with PG).  The
+// finished window is scanned in column order and its nonzeros written out, so
+// results come out sorted and without stored zeros.  The path is gather- and
+// latency-bound (no dense contraction), so MFMA is not used.
 #include "kernels.hpp"
 
 #include <climits>
