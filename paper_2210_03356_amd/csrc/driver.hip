@@ -52,6 +52,7 @@ Workspace::Workspace(Allocator *a, size_t staging_bytes) : al(a), s(a->stream) {
         else if (std::strcmp(pg, "on") == 0) page_mode = 2;
         else page_mode = 1;
     }
+    if (const char *rt = std::getenv("SIGNFN_RESIDUAL_TWO_PASS")) residual_two_pass = rt[0] == '1';
     if (const char *ps = std::getenv("SIGNFN_PAGE_SHIFT")) {
         const int v = std::atoi(ps);
         if (v >= 4 && v <= 8) page_shift = v;
@@ -300,7 +301,10 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
         // counted twice below the diagonal of a symmetric product)
         epi.hist = ff->hist;
         epi.sq_pre = ff->sq_pre;
-        epi.keep_from = safe_drop_bucket(ff->tau, (lower.any() ? 2.0 : 1.0) * (double)total_cap);
+        epi.keep_from = ff->keep_from >= 0
+                            ? ff->keep_from
+                            : safe_drop_bucket(ff->tau, (lower.any() ? 2.0 : 1.0) *
+                                                            (double)total_cap);
     }
 
     // batches of rows whose reserved output fits the staging budget
@@ -308,7 +312,8 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
     // memory use changes as iterates grow: the budget follows it for products
     // that need more than a gigabyte of staging (smaller ones keep the last one)
     if (w.staging_auto && (double)total_cap * (double)entry > (double)(size_t(1) << 30))
-        w.staging_limit = w.auto_staging();
+        w.staging_limit = w.low_memory ? std::min<size_t>(w.auto_staging(), size_t(8) << 30)
+                                       : w.auto_staging();
     const int64_t budget = std::max<int64_t>((int64_t)(w.staging_limit / entry), n);
     if (w.progress && total_cap > (int64_t)1 << 30 && !w.al->alloc)
         w.note("product: %lld rows, %lld reserved entries, staging %.1f GB, pool %.1f GB in use, "
@@ -316,7 +321,10 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
                Pool::instance().used_bytes() / 1e9, Pool::instance().cached_bytes() / 1e9);
     std::vector<int64_t> cuts{0};
     std::vector<int64_t> capoff_h;
-    if (total_cap <= budget || no_store) {
+    // (a product that stores nothing runs in one batch -- batches cost it ~10% --
+    // except under memory pressure, where batches keep its per-A-entry cursors
+    // and merged lists to one batch's A entries instead of all of A)
+    if (total_cap <= budget || (no_store && !w.low_memory)) {
         cuts.push_back(n);
     } else {
         capoff_h.resize(n + 1);
@@ -737,6 +745,16 @@ int filter(Workspace &w, const DMat<V> &In, double tau, DMat<Vo> &Out, DevBuf *s
     return bstar;
 }
 
+int select_cut(Workspace &w, int64_t n, double tau) {
+    hipStream_t s = w.s;
+    w.seg.ensure(2 * sizeof(int64_t));
+    w.tau.ensure(sizeof(double));
+    w.bstar.ensure(sizeof(int64_t));
+    launch_set_filter_args(w.seg.as<int64_t>(), n, w.tau.as<double>(), tau, s);
+    launch_select(w.hist.as<uint64_t>(), w.tau.as<double>(), 1, w.bstar.as<int>(), s);
+    return read_scalar(w.bstar.as<int>(), s);
+}
+
 void filter_seg(Workspace &w, const DMat<double> &In, const std::vector<int64_t> &seg_h,
                 const int64_t *seg_d, const int32_t *row_seg, const std::vector<double> &tau_h,
                 DMat<double> &Out, DevBuf *sq_keep, DevBuf *sq_drop, std::vector<int> &bstar_h,
@@ -905,6 +923,20 @@ LoopOut nsf_loop(Workspace &w, DMat<V> &X, const LoopParams &p,
     double ff_prev = std::numeric_limits<double>::infinity();
     int n_up = 0, n_flat = 0;
     std::vector<double> es;
+    // Under memory pressure (filter_y): the residual and the update are formed
+    // in two passes, so that neither the unfiltered residual nor the update's
+    // candidates are ever stored -- from the first step when asked
+    // (SIGNFN_RESIDUAL_TWO_PASS=1), else from the step whose one-pass form runs
+    // out of device memory; dead matrices and the product staging then go back
+    // to the pool as soon as they are dead, and the staging is capped.
+    bool two_pass = w.residual_two_pass;
+    if (two_pass) w.low_memory = true;
+    auto release_dead = [&]() {
+        Xb.release_entries();
+        Xn.release_entries();
+        w.stage_col.reset();
+        w.stage_val.reset();
+    };
     for (int k = 1;; ++k) {
         const double t0 = now_s();
         if (!p.check_last && k - 1 >= p.max_iter) {
@@ -952,9 +984,34 @@ LoopOut nsf_loop(Workspace &w, DMat<V> &X, const LoopParams &p,
                 if (b <= p.tol) { e = b; e_bound = 1; }
             }
         }
-        if (!e_bound) {
-            product<V>(w, X, X, nullptr, -1.0, 0.0, 1.0, R, nullptr, &w.rs1, sym);
+        // two passes (filter_y only): this one forms e_k and the filter's
+        // histogram of R_k and stores nothing; the kept entries come after the cut
+        auto residual_first_pass = [&]() {
+            w.hist.ensure(sizeof(uint64_t) * kBuckets);
+            SFN_HIP(hipMemsetAsync(w.hist.get(), 0, sizeof(uint64_t) * kBuckets, w.s));
+            const FusedFilter hist_only{0.0, w.hist.as<uint64_t>(), nullptr};
+            product_rows<V>(w, X, X, nullptr, -1.0, 0.0, 1.0, R, nullptr, &w.rs1, LowerRows{},
+                            &hist_only, true);
             e = std::sqrt(w.sum_rows(w.rs1, n));
+        };
+        bool residual_two_pass = !e_bound && p.filter_y && two_pass;
+        if (residual_two_pass) {
+            residual_first_pass();
+        } else if (!e_bound) {
+            try {
+                product<V>(w, X, X, nullptr, -1.0, 0.0, 1.0, R, nullptr, &w.rs1, sym);
+                e = std::sqrt(w.sum_rows(w.rs1, n));
+            } catch (const Error &err) {
+                if (err.status != SIGN_ENOMEM || !p.filter_y || sym) throw;
+                w.note("ns k=%d: out of device memory forming the residual; this and the "
+                       "next steps in two passes", k);
+                two_pass = true;
+                w.low_memory = true;
+                release_dead();
+                R.release_entries();
+                residual_two_pass = true;
+                residual_first_pass();
+            }
         }
         es.push_back(e);
         sign_iter_stats it{};
@@ -983,7 +1040,18 @@ LoopOut nsf_loop(Workspace &w, DMat<V> &X, const LoopParams &p,
             break;
         }
         const double tau = nsf_budget(e, xf, p.tol, p.c_fixed, p.switch_res);
-        if (p.filter_y) {
+        if (residual_two_pass) {
+            // the cut from the first pass's histogram; the second pass stores the
+            // entries of the buckets from one below it: its sums may round apart
+            // from the first pass's by the order of the LDS additions, and an entry
+            // on a bucket edge must not slip below the cut
+            const int bstar = select_cut(w, n, tau);
+            w.note("ns k=%d: residual in two passes, %lld entries, cut at bucket %d", k,
+                   (long long)R.nnz, bstar);
+            const FusedFilter keep{tau, nullptr, nullptr, std::max(bstar - 1, 0)};
+            product_rows<V>(w, X, X, nullptr, -1.0, 0.0, 1.0, R, nullptr, nullptr, LowerRows{},
+                            &keep);
+        } else if (p.filter_y) {
             filter<V, V>(w, R, tau, Xn, nullptr, nullptr);
             std::swap(R, Xn);
         }
@@ -997,17 +1065,57 @@ LoopOut nsf_loop(Workspace &w, DMat<V> &X, const LoopParams &p,
         SFN_HIP(hipMemsetAsync(w.hist.get(), 0, sizeof(uint64_t) * kBuckets, w.s));
         SFN_HIP(hipMemsetAsync(w.rs5.get(), 0, sizeof(double) * n, w.s));  // rows with no output
         const FusedFilter fuse{tau, w.hist.as<uint64_t>(), w.rs5.as<double>()};
-        product<V>(w, X, R, &X, 0.5, 1.0, 0.0, Xb, &w.rs2, nullptr, sym, sym, &fuse);
-        // X^_{k+1} = Xbar_{k+1} - F_{k+1}
-        // (nbar: entries of the full Xbar -- the histogram counts every candidate,
-        // twice below the diagonal of a symmetric product)
-        int bstar;
+        int bstar = 0;
         int64_t nbar = 0;
-        if (sym) {
-            bstar = filter<V, V>(w, Xb, tau, Xl, &w.rs3, &w.rs4, 1, true, &nbar);
-            symmetrize<V>(w, Xl, Xn);
+        // under memory pressure Xbar is never stored either: a first pass forms its
+        // histogram and ||Xbar - X^_k||, the cut follows, and a second pass stores
+        // X^_{k+1} directly (from one bucket below the cut, as for the residual),
+        // with the sums of squares kept and dropped per row
+        auto update_two_pass = [&]() {
+            release_dead();  // candidates of a one-pass step, a swapped-out residual
+            SFN_HIP(hipMemsetAsync(w.hist.get(), 0, sizeof(uint64_t) * kBuckets, w.s));
+            const FusedFilter hist_only{0.0, w.hist.as<uint64_t>(), nullptr};
+            product_rows<V>(w, X, R, &X, 0.5, 1.0, 0.0, Xn, &w.rs2, nullptr, LowerRows{},
+                            &hist_only, true);
+            bstar = select_cut(w, n, tau);
+            w.rb.ensure(sizeof(int64_t) * 64);
+            launch_hist_total(w.hist.as<uint64_t>(), w.rb.as<int64_t>(), w.s);
+            nbar = read_scalar(w.rb.as<int64_t>(), w.s);
+            w.rs3.ensure(sizeof(double) * n);
+            w.rs4.ensure(sizeof(double) * n);
+            SFN_HIP(hipMemsetAsync(w.rs4.get(), 0, sizeof(double) * n, w.s));  // rows with no output
+            const FusedFilter keep{tau, nullptr, w.rs4.as<double>(), std::max(bstar - 1, 0)};
+            product_rows<V>(w, X, R, &X, 0.5, 1.0, 0.0, Xn, nullptr, &w.rs3, LowerRows{}, &keep);
+            // the step's inputs and the products' staging go back to the pool
+            // (X^_k is not read again)
+            R.release_entries();
+            X.release_entries();
+            w.stage_col.reset();
+            w.stage_val.reset();
+        };
+        if (two_pass && !sym) {
+            update_two_pass();
         } else {
-            bstar = filter<V, V>(w, Xb, tau, Xn, &w.rs3, &w.rs4, 0, true, &nbar);
+            try {
+                product<V>(w, X, R, &X, 0.5, 1.0, 0.0, Xb, &w.rs2, nullptr, sym, sym, &fuse);
+                // X^_{k+1} = Xbar_{k+1} - F_{k+1}
+                // (nbar: entries of the full Xbar -- the histogram counts every
+                // candidate, twice below the diagonal of a symmetric product)
+                if (sym) {
+                    bstar = filter<V, V>(w, Xb, tau, Xl, &w.rs3, &w.rs4, 1, true, &nbar);
+                    symmetrize<V>(w, Xl, Xn);
+                } else {
+                    bstar = filter<V, V>(w, Xb, tau, Xn, &w.rs3, &w.rs4, 0, true, &nbar);
+                }
+            } catch (const Error &err) {
+                if (err.status != SIGN_ENOMEM || !p.filter_y || sym) throw;
+                w.note("ns k=%d: out of device memory forming the update; this and the next "
+                       "steps in two passes", k);
+                two_pass = true;
+                w.low_memory = true;
+                SFN_HIP(hipMemsetAsync(w.rs5.get(), 0, sizeof(double) * n, w.s));
+                update_two_pass();
+            }
         }
         const std::vector<double> sums = w.sum_rows_many({&w.rs2, &w.rs5, &w.rs3, &w.rs4}, n);
         const double d = std::sqrt(sums[0]);
@@ -1018,6 +1126,11 @@ LoopOut nsf_loop(Workspace &w, DMat<V> &X, const LoopParams &p,
         trace.push_back(it);
         w.report("ns", k, it);
         std::swap(X, Xn);
+        if (two_pass) {
+            // the previous iterate and any candidates left from one-pass steps
+            Xb.release_entries();
+            Xn.release_entries();
+        }
         xf = xf_new;
         d_prev = d;
         ff_prev = ff;

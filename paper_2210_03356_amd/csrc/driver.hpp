@@ -36,6 +36,12 @@ struct Workspace {
     // whose B rows occupy few of the pages of their column ranges, 2 always;
     // pages of 2^page_shift columns
     int page_mode = 1, page_shift = 4;
+    // filtered residuals (filter_y) formed in two passes -- norm and histogram,
+    // then only the kept entries -- so that the unfiltered residual is never
+    // stored: from the first step (SIGNFN_RESIDUAL_TWO_PASS=1), else once an
+    // unfiltered residual outgrows a quarter of the device's memory
+    bool residual_two_pass = false;
+    bool low_memory = false;  // set with two passes: product staging capped at 8 GB
     bool progress = false;              // one stderr line per finished iteration
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     // accumulated product statistics, in total and per row class (kernel tile)
@@ -93,6 +99,9 @@ struct FusedFilter {
     double tau;
     uint64_t *hist;
     double *sq_pre;
+    // >= 0: a cut already chosen -- store only entries of buckets >= keep_from
+    // (instead of the safe edge of tau)
+    int keep_from = -1;
 };
 template <typename V>
 void product(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V> *D, double coef,
@@ -124,6 +133,9 @@ bool is_symmetric(Workspace &w, const DMat<V> &X);
 // squares of kept / dropped entries.
 // lower: In is the lower triangle of a symmetric matrix (Out likewise); the cut
 // and the sums of squares count entries below the diagonal twice.
+// The filter's cut (bucket index) for budget tau from the histogram in w.hist
+// (one segment of n rows), read back to the host.
+int select_cut(Workspace &w, int64_t n, double tau);
 // hist_ready: the histogram of In is already in w.hist (a fused product);
 // candidates (optional): the histogram's total count.
 template <typename V, typename Vo>

@@ -133,6 +133,13 @@ struct DMat {
         return v;
     }
     int64_t capacity() const { return (int64_t)(col.size() / sizeof(int32_t)); }
+    // give the entry arrays back (row arrays kept); later work on the stream that
+    // reuses the blocks runs after the work that used them
+    void release_entries() {
+        col.reset();
+        val.reset();
+        nnz = 0;
+    }
 };
 
 // Small host<->device helpers (synchronous on the given stream).

@@ -524,3 +524,111 @@ def test_symmetric_products_match_general(sf, monkeypatch, name):
     monkeypatch.setenv("SIGNFN_SYMMETRIC", "1")
     Xm = sf.sign_ns(_dev(sf, A), sf.default_opts(precision=1, **kw)).to_scipy()
     assert sp.linalg.norm(Xm - S) <= 1e-8 * sp.linalg.norm(S)
+
+
+TWO_PASS_CASES = {
+    "lap2d_32_filter_y": (lambda: W.laplacian_2d(32, jitter=0.05, seed=2, m=8.0),
+                          dict(tol=1e-12, filter_y=1)),
+    "convdiff_30_filter_y": (lambda: W.convdiff_2d(30, beta=0.5, sigma=4.0, m=8.0),
+                             dict(tol=1e-12, filter_y=1)),
+    "lap3d_9_filter_y": (lambda: W.laplacian_3d(9, perturb=0.5, seed=4, m=12.0),
+                         dict(tol=1e-10, filter_y=1)),
+}
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("name", list(TWO_PASS_CASES))
+def test_two_pass_residual(sf, monkeypatch, capfd, name, precision):
+    """Steps formed in two passes, as under memory pressure -- for the residual and
+    for the update, a first pass forms the norm and the filter's histogram and
+    stores nothing, a second stores only the entries from one bucket below the cut
+    -- give the one-pass solve's residual history and result, and the oracle's
+    (1e-10 in FP64, 1e-8 mixed)."""
+    make, kw = TWO_PASS_CASES[name]
+    A = make()
+    monkeypatch.delenv("SIGNFN_RESIDUAL_TWO_PASS", raising=False)
+    one = sf.sign_ns(_dev(sf, A), sf.default_opts(precision=precision, **kw))
+    monkeypatch.setenv("SIGNFN_RESIDUAL_TWO_PASS", "1")
+    monkeypatch.setenv("SIGNFN_PROGRESS", "1")
+    two = sf.sign_ns(_dev(sf, A), sf.default_opts(precision=precision, **kw))
+    err = capfd.readouterr().err
+    assert "residual in two passes" in err, err[-2000:]
+    assert one.status == "OK" and two.status == "OK"
+    X1, X2 = one.to_scipy(), two.to_scipy()
+    if precision == 0:
+        t1, t2 = one.trace(), two.trace()
+        assert len(t1) == len(t2)
+        # the first residual is the same matrix in both: the first pass gives its
+        # exact entry count and norm
+        assert t1[0]["nnz_r"] == t2[0]["nnz_r"]
+        assert abs(t1[0]["e"] - t2[0]["e"]) <= 1e-12 * t1[0]["e"]
+        # later iterates differ by what the extra bucket kept, far below the
+        # iteration's own residuals
+        for a, b in zip(t1[1:], t2[1:]):
+            if not a["e_bound"]:
+                assert abs(a["nnz_r"] - b["nnz_r"]) <= 1e-2 * a["nnz_r"]
+            assert abs(a["e"] - b["e"]) <= 1e-3 * a["e"] + 1e-14
+        assert sp.linalg.norm(X2 - X1) <= 1e-11 * sp.linalg.norm(X1)
+    # (the mixed mode's FP32 steps round their LDS sums apart from run to run, so
+    # two mixed runs agree only to the mode's accuracy)
+    tol = 1e-10 if precision == 0 else 1e-8
+    S = oracle.nsf(A, **kw).to_scipy()
+    assert sp.linalg.norm(X2 - S) <= tol * sp.linalg.norm(S)
+
+
+class _CappedHooks:
+    """Device allocation hooks for sign_opts (hipMalloc/hipFree) that refuse any
+    allocation taking the bytes in use past `cap`: a device smaller than it is."""
+
+    def __init__(self, sf, cap):
+        import ctypes as C
+        from paper_2210_03356_amd import signfn as S
+        hip = C.CDLL("libamdhip64.so")
+        self.cap, self.used, self.peak, self.refused, self._size = cap, 0, 0, 0, {}
+
+        def alloc(nbytes, stream, ctx):
+            if self.used + nbytes > self.cap:
+                self.refused += 1
+                return None
+            p = C.c_void_p()
+            if hip.hipMalloc(C.byref(p), C.c_size_t(nbytes)) != 0:
+                return None
+            self.used += nbytes
+            self.peak = max(self.peak, self.used)
+            self._size[p.value] = nbytes
+            return p.value
+
+        def free(ptr, stream, ctx):
+            if ptr:
+                hip.hipFree(C.c_void_p(ptr))
+                self.used -= self._size.pop(ptr)
+
+        self.alloc, self.free = S._ALLOC(alloc), S._FREE(free)
+
+
+def test_two_pass_after_running_out_of_memory(sf, monkeypatch, capfd):
+    """Under a device-memory cap (the caller's allocator refuses beyond 380 MB) the
+    one-pass steps of a filtered-residual solve run out (its peak is ~480 MB); the
+    step that runs out and the rest are formed in two passes (peak ~265 MB), and
+    the result is the oracle's.  Below the two-pass peak the call fails with
+    ENOMEM, a host-side error."""
+    A = W.convdiff_2d(64, beta=0.5, sigma=4.0, m=8.0)
+    kw = dict(tol=1e-12, filter_y=1)
+    monkeypatch.delenv("SIGNFN_RESIDUAL_TWO_PASS", raising=False)
+    monkeypatch.setenv("SIGNFN_PROGRESS", "1")
+    h = _CappedHooks(sf, 380 << 20)
+    r = sf.sign_ns(_dev(sf, A), sf.default_opts(staging_bytes=1 << 20, alloc=h.alloc,
+                                                free=h.free, **kw))
+    err = capfd.readouterr().err
+    assert r.status == "OK"
+    assert h.refused > 0 and h.peak <= h.cap
+    assert "out of device memory" in err and "two passes" in err, err[-2000:]
+    S = oracle.nsf(A, **kw).to_scipy()
+    X = r.to_scipy()
+    del r
+    assert sp.linalg.norm(X - S) <= 1e-10 * sp.linalg.norm(S)
+    small = _CappedHooks(sf, 150 << 20)
+    with pytest.raises(sf.SignError, match="ENOMEM"):
+        sf.sign_ns(_dev(sf, A), sf.default_opts(staging_bytes=1 << 20, alloc=small.alloc,
+                                                free=small.free, **kw))
+    assert small.used == 0  # every block handed back
