@@ -978,10 +978,19 @@ LoopOut nsf_loop(Workspace &w, DMat<V> &X, const LoopParams &p,
                 try_cert = pred <= 0.25 * p.tol;
             }
             if (try_cert) {
-                DMat<double> Xt;
-                Xt.bind(w.al);
-                const double b = thinned_residual_bound(w, X, sym, p.tol, Xt, &nnz_cert);
-                if (b <= p.tol) { e = b; e_bound = 1; }
+                try {
+                    DMat<double> Xt;
+                    Xt.bind(w.al);
+                    const double b = thinned_residual_bound(w, X, sym, p.tol, Xt, &nnz_cert);
+                    if (b <= p.tol) { e = b; e_bound = 1; }
+                } catch (const Error &err) {
+                    // no room for the thinned copy and its square: the full
+                    // residual below certifies instead
+                    if (err.status != SIGN_ENOMEM) throw;
+                    w.note("ns k=%d: out of device memory certifying from a thinned copy; "
+                           "forming the residual", k);
+                    release_dead();
+                }
             }
         }
         // two passes (filter_y only): this one forms e_k and the filter's
@@ -1052,7 +1061,20 @@ LoopOut nsf_loop(Workspace &w, DMat<V> &X, const LoopParams &p,
             product_rows<V>(w, X, X, nullptr, -1.0, 0.0, 1.0, R, nullptr, nullptr, LowerRows{},
                             &keep);
         } else if (p.filter_y) {
-            filter<V, V>(w, R, tau, Xn, nullptr, nullptr);
+            try {
+                filter<V, V>(w, R, tau, Xn, nullptr, nullptr);
+            } catch (const Error &err) {
+                if (err.status != SIGN_ENOMEM) throw;
+                // the kept residual does not fit beside the unfiltered one: once
+                // more with the dead matrices and the staging released, and the
+                // next steps in two passes
+                w.note("ns k=%d: out of device memory filtering the residual; the next "
+                       "steps in two passes", k);
+                two_pass = true;
+                w.low_memory = true;
+                release_dead();
+                filter<V, V>(w, R, tau, Xn, nullptr, nullptr);
+            }
             std::swap(R, Xn);
         }
         // Xbar_{k+1} = X^_k + 1/2 X^_k R^_k  (= 1/2 X^_k (3I - X^_k^2))

@@ -606,27 +606,36 @@ class _CappedHooks:
         self.alloc, self.free = S._ALLOC(alloc), S._FREE(free)
 
 
-def test_two_pass_after_running_out_of_memory(sf, monkeypatch, capfd):
-    """Under a device-memory cap (the caller's allocator refuses beyond 380 MB) the
-    one-pass steps of a filtered-residual solve run out (its peak is ~480 MB); the
-    step that runs out and the rest are formed in two passes (peak ~265 MB), and
-    the result is the oracle's.  Below the two-pass peak the call fails with
-    ENOMEM, a host-side error."""
+@pytest.mark.parametrize("cap_mb", [300, 380, 440])
+def test_two_pass_after_running_out_of_memory(sf, monkeypatch, capfd, cap_mb):
+    """Under a device-memory cap (the caller's allocator refuses beyond it) the
+    one-pass steps of a filtered-residual solve run out (its peak is ~480 MB) in the
+    residual's product, its filter or the update, depending on the cap; that step
+    is redone and the rest run in two passes (peak ~265 MB) -- or, near the top,
+    only the certification of the last residual from a thinned copy runs out and
+    the residual is formed in full -- and the result is the oracle's.  Below the
+    two-pass peak the call fails with ENOMEM, a host-side error."""
     A = W.convdiff_2d(64, beta=0.5, sigma=4.0, m=8.0)
     kw = dict(tol=1e-12, filter_y=1)
     monkeypatch.delenv("SIGNFN_RESIDUAL_TWO_PASS", raising=False)
     monkeypatch.setenv("SIGNFN_PROGRESS", "1")
-    h = _CappedHooks(sf, 380 << 20)
+    h = _CappedHooks(sf, cap_mb << 20)
     r = sf.sign_ns(_dev(sf, A), sf.default_opts(staging_bytes=1 << 20, alloc=h.alloc,
                                                 free=h.free, **kw))
     err = capfd.readouterr().err
     assert r.status == "OK"
     assert h.refused > 0 and h.peak <= h.cap
-    assert "out of device memory" in err and "two passes" in err, err[-2000:]
+    # (at the larger cap only the last residual's certification runs out: it is
+    # formed in full instead)
+    assert "out of device memory" in err, err[-2000:]
+    if cap_mb < 440:
+        assert "two passes" in err, err[-2000:]
     S = oracle.nsf(A, **kw).to_scipy()
     X = r.to_scipy()
     del r
     assert sp.linalg.norm(X - S) <= 1e-10 * sp.linalg.norm(S)
+    if cap_mb != 380:
+        return
     small = _CappedHooks(sf, 150 << 20)
     with pytest.raises(sf.SignError, match="ENOMEM"):
         sf.sign_ns(_dev(sf, A), sf.default_opts(staging_bytes=1 << 20, alloc=small.alloc,
