@@ -1008,7 +1008,18 @@ LoopOut nsf_loop(Workspace &w, DMat<V> &X, const LoopParams &p,
             residual_first_pass();
         } else if (!e_bound) {
             try {
-                product<V>(w, X, X, nullptr, -1.0, 0.0, 1.0, R, nullptr, &w.rs1, sym);
+                if (p.filter_y) {
+                    // the residual's filter takes its histogram from the product
+                    // (every candidate counted; its budget is not known yet, so
+                    // nothing is dropped early)
+                    w.hist.ensure(sizeof(uint64_t) * kBuckets);
+                    SFN_HIP(hipMemsetAsync(w.hist.get(), 0, sizeof(uint64_t) * kBuckets, w.s));
+                    const FusedFilter hist_only{0.0, w.hist.as<uint64_t>(), nullptr};
+                    product<V>(w, X, X, nullptr, -1.0, 0.0, 1.0, R, nullptr, &w.rs1, sym, false,
+                               &hist_only);
+                } else {
+                    product<V>(w, X, X, nullptr, -1.0, 0.0, 1.0, R, nullptr, &w.rs1, sym);
+                }
                 e = std::sqrt(w.sum_rows(w.rs1, n));
             } catch (const Error &err) {
                 if (err.status != SIGN_ENOMEM || !p.filter_y || sym) throw;
@@ -1062,7 +1073,7 @@ LoopOut nsf_loop(Workspace &w, DMat<V> &X, const LoopParams &p,
                             &keep);
         } else if (p.filter_y) {
             try {
-                filter<V, V>(w, R, tau, Xn, nullptr, nullptr);
+                filter<V, V>(w, R, tau, Xn, nullptr, nullptr, 0, true);
             } catch (const Error &err) {
                 if (err.status != SIGN_ENOMEM) throw;
                 // the kept residual does not fit beside the unfiltered one: once
@@ -1073,7 +1084,7 @@ LoopOut nsf_loop(Workspace &w, DMat<V> &X, const LoopParams &p,
                 two_pass = true;
                 w.low_memory = true;
                 release_dead();
-                filter<V, V>(w, R, tau, Xn, nullptr, nullptr);
+                filter<V, V>(w, R, tau, Xn, nullptr, nullptr, 0, true);
             }
             std::swap(R, Xn);
         }
