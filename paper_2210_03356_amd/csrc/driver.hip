@@ -392,7 +392,12 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
     // more of its pages (2D grids, ~0.7) and lose 5 - 13% below (3D, ~0.5);
     // pairs lose to groups of 4 (up to 3x on the stencil products).
     int group = w.row_group;
-    if (w.auto_group && pst[1] > 0) {
+    if (w.auto_group && w.row_skip && sizeof(V) == 8) {
+        // a served batch mixes requests whose rows the averages do not describe:
+        // groups of 8 measured best for it (the named stream: 29.2 against 28.4
+        // solves/s with the rules; 400 requests: 28.5 against 27.4)
+        group = 8;
+    } else if (w.auto_group && pst[1] > 0) {
         const bool long_a = A.nnz >= 512 * n;
         if (pages_ok) {
             const bool full_pages = (double)pst[0] >= 0.6 * page_range;
