@@ -790,9 +790,12 @@ __global__ __launch_bounds__(NT) void k_spgemm_rows(
     const int64_t mbeg = A.beg[i];
     const int ml = R == 1 ? A.len[i] : mlen[i];
     const bool has_d = D.len != nullptr;
-    // slots per wave and batch: 64, or fewer so that a short slot list still
-    // spreads over every wave
-    const int step = ml >= NW * kWave ? kWave : max(1, (ml + NW - 1) / NW);
+    // slots per wave and batch: at most 64, sized so that every wave gets the same
+    // number of batches and slots (a list of 1,500 slots: two batches of 47 per
+    // wave, not two of 64 for half the waves and one for the others -- each
+    // window waits for its slowest wave)
+    const int rounds = (ml + NW * kWave - 1) / (NW * kWave);
+    const int step = max(1, (ml + NW * rounds - 1) / (NW * max(rounds, 1)));
 
     for (int q = threadIdx.x; q < 2 * R * NW; q += NT) (&wsum[0][0])[q] = 0.0;
     if (threadIdx.x < R) wrt[threadIdx.x] = 0;
