@@ -388,9 +388,12 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
     const bool pages_ok =
         pages_wanted && (w.page_mode == 2 || (pst[1] > 0 && page_range <= 0.3 * (double)pst[1]));
     // With page windows the fill of the occupied pages decides instead: groups
-    // of 8 win for FP64 values with long A rows when B's entries fill 60% or
-    // more of its pages (2D grids, ~0.7) and lose 5 - 13% below (3D, ~0.5);
-    // pairs lose to groups of 4 (up to 3x on the stencil products).
+    // of 8 win for FP64 values with long A rows when B's entries fill 55% or
+    // more of its pages (2D grids, 0.59 - 0.7) and lose 5 - 13% below (3D,
+    // ~0.5). Squares of an iterate with short rows (X·X, hundreds of entries
+    // or fewer) gain 15 - 35% in groups of 8 at any fill and precision: the
+    // rows of a group gather the same B rows their own neighbours hold. Pairs
+    // lose to groups of 4 (up to 3x on the stencil products).
     int group = w.row_group;
     if (w.auto_group && w.row_skip && sizeof(V) == 8) {
         // a served batch mixes requests whose rows the averages do not describe:
@@ -400,8 +403,9 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
     } else if (w.auto_group && pst[1] > 0) {
         const bool long_a = A.nnz >= 512 * n;
         if (pages_ok) {
-            const bool full_pages = (double)pst[0] >= 0.6 * page_range;
-            group = (sizeof(V) == 8 && long_a && full_pages) ? 8 : 4;
+            const bool full_pages = (double)pst[0] >= 0.55 * page_range;
+            const bool short_square = &A == &B && !long_a;
+            group = ((sizeof(V) == 8 && long_a && full_pages) || short_square) ? 8 : 4;
         } else {
             const bool dense_b = 2048ull * pst[0] >= 200ull * pst[1];
             if (!w.row_skip && (A.nnz < 64 * n || B.nnz <= 16 * n))
