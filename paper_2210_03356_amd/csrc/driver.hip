@@ -267,8 +267,14 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
     const bool short_b = B.nnz <= 16 * std::max<int64_t>(B.n, 1);
     // page lists of B's rows, for page windows of row groups: counted and
     // scanned here, so that their total comes back with the plan's (not for
-    // n <= 2048, where column ranges are too short for pages to gain anything)
-    const bool pages_wanted = w.page_mode != 0 && !short_b && n > 2048;
+    // n <= 2048, where column ranges are too short for pages to gain anything,
+    // nor for short B rows: X·A with A the stencil runs fastest in pairs with
+    // dense windows -- in groups of 4 with page windows C2 takes 4.7 ms
+    // against 3.7, C4 32^3 15.9 against 10.9, C3 gains 2% of a mixed solve;
+    // SIGNFN_PAGES=on still forces them onto products with long A rows).
+    const bool pages_wanted =
+        w.page_mode != 0 && n > 2048 &&
+        (!short_b || (w.page_mode == 2 && A.nnz >= 64 * std::max<int64_t>(n, 1)));
     if (pages_wanted) {
         w.plen.ensure(sizeof(int32_t) * n);
         w.pbeg.ensure(sizeof(int64_t) * (n + 1));

@@ -58,6 +58,41 @@ def test_page_window_products(sf, monkeypatch, capfd, group, shift):
     assert "(page windows)" in err, err[-2000:]
 
 
+def _grid_stencil(nx=203, ny=61, seed=23):
+    """The 5-point stencil pattern of the same nx x ny grid (x fastest), random
+    values: rows of at most five entries, the short B rows of X*A."""
+    rng = np.random.default_rng(seed)
+    n = nx * ny
+    rows = []
+    for y in range(ny):
+        for x in range(nx):
+            c = [y * nx + x]
+            if x > 0: c.append(y * nx + x - 1)
+            if x < nx - 1: c.append(y * nx + x + 1)
+            if y > 0: c.append((y - 1) * nx + x)
+            if y < ny - 1: c.append((y + 1) * nx + x)
+            rows.append(np.sort(np.array(c, np.int32)))
+    indptr = np.zeros(n + 1, np.int64)
+    indptr[1:] = np.cumsum([len(c) for c in rows])
+    indices = np.concatenate(rows)
+    data = rng.uniform(0.1, 1.0, len(indices)) * rng.choice([-1.0, 1.0], len(indices))
+    return W.Csr(n=n, indptr=indptr, indices=indices, data=data)
+
+
+@pytest.mark.parametrize("group", [None, 2, 4, 8, 16])
+def test_page_windows_short_b_rows(sf, monkeypatch, capfd, group):
+    """Long rows times short ones (X*A with A the stencil: each lane walks its own
+    slot's B row of at most five entries) in page windows: the product is the
+    oracle's entry by entry, for every group size."""
+    _pages_env(monkeypatch, group)
+    A = _wide_rows_matrix()
+    B = _grid_stencil()
+    st = _check_product(sf, A, B).stats()
+    assert st["madds"] == st["products"]
+    err = capfd.readouterr().err
+    assert "(page windows)" in err, err[-2000:]
+
+
 def _band_and_far_matrix(n=135000, half=8, seed=5):
     """Rows holding a band i-half .. i+half and two columns far away: a product's
     row groups then span nearly all n columns, more than the LDS page table holds
