@@ -269,8 +269,9 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
     // scanned here, so that their total comes back with the plan's (not for
     // n <= 2048, where column ranges are too short for pages to gain anything,
     // nor for short B rows: X·A with A the stencil runs fastest in pairs with
-    // dense windows -- in groups of 4 with page windows C2 takes 4.7 ms
-    // against 3.7, C4 32^3 15.9 against 10.9, C3 gains 2% of a mixed solve;
+    // dense windows -- in groups of 4 with page windows the 256x256 Laplacian's
+    // takes 4.7 ms against 3.7, the 32^3 Laplacian's 15.9 against 10.9, and the
+    // 512x512 convection-diffusion gains 2% of a mixed solve;
     // SIGNFN_PAGES=on still forces them onto products with long A rows).
     const bool pages_wanted =
         w.page_mode != 0 && n > 2048 &&
