@@ -404,7 +404,7 @@ void product_rows(Workspace &w, const DMat<V> &A, const DMat<V> &B, const DMat<V
     int group = w.row_group;
     if (w.auto_group && w.row_skip && sizeof(V) == 8) {
         // a served batch mixes requests whose rows the averages do not describe:
-        // groups of 8 measured best for it (the named stream: 29.2 against 28.4
+        // groups of 8 measured best for it (2,000 requests at 50/s: 29.2 against 28.4
         // solves/s with the rules; 400 requests: 28.5 against 27.4)
         group = 8;
     } else if (w.auto_group && pst[1] > 0) {
